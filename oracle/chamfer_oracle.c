@@ -1,0 +1,411 @@
+/*
+ * CPU oracle for the near-linear Chamfer estimator (Bakshi, Indyk, Jayaram,
+ * Silwal, Waingarten, "A Near-Linear Time Algorithm for the Chamfer Distance").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Nothing in the product path may include,
+ * link or call it; it shares no source with the GPU library.
+ *
+ * Build: gcc -O2 -std=c11 -fPIC -shared -fopenmp -ffp-contract=off
+ *        -fno-fast-math chamfer_oracle.c -lm
+ * (-ffp-contract=off: every float operation below is one IEEE operation,
+ *  rounded to nearest even; fused multiply-adds appear only where fmaf is
+ *  written, and they are part of the definition there.)
+ *
+ * Conventions fixed here (each is a reading of the paper; the paper leaves
+ * them open):
+ *   - distances are not squared (footnote to the definition of CH in the
+ *     introduction);
+ *   - "dist32" is the canonical single-precision distance: k ascending,
+ *     l1: acc = acc + |a_k - b_k|, l2: acc = fmaf(t, t, acc) with
+ *     t = a_k - b_k, then sqrtf(acc).  It is used where a float decides an
+ *     integer (the crude distance D_a, and arg-mins);
+ *   - the exact Chamfer distance is computed in double precision from the
+ *     float inputs (which convert exactly), l2 by direct differences.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_L1 1
+#define OR_L2 2
+
+/* Purposes of the counter-based random streams (third counter word). */
+#define PURPOSE_GRID 1u
+#define PURPOSE_EMBED 2u
+#define PURPOSE_SAMPLE 3u
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC 2011).  Ten rounds of two 64x64->128 multiplies,    */
+/* with the key bumped by the Weyl constants between rounds.                */
+/* ------------------------------------------------------------------------ */
+void or_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * c0;
+        unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(uint64_t seed, uint64_t c0, uint64_t c1, uint32_t purpose, uint64_t out[4])
+{
+    uint64_t ctr[4] = {c0, c1, (uint64_t)purpose, 0};
+    uint64_t key[2] = {seed, 0};
+    or_philox4x64(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hash family at every scale (appendix lemma constructing an LSH at every  */
+/* scale): h(x)_k = ceil((x_k + z_k) / r) with z ~ U[0, r]^k.  Written in   */
+/* cell units: ceil(x_k / r + z'_k) with z'_k = z_k / r ~ U[0, 1).          */
+/* For scale i and hashed coordinate k the oracle draws                    */
+/*   z'_ik = (word0 >> 40) * 2^-24            (24-bit lattice in [0, 1))     */
+/*   M_ik  = word1 | 1                         (odd 64-bit multiplier)       */
+/* from the counter (k, i, GRID).  zfrac and mult are [L][kh].              */
+/* ------------------------------------------------------------------------ */
+void or_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult)
+{
+    for (int i = 0; i < L; ++i)
+        for (int k = 0; k < kh; ++k) {
+            uint64_t w[4];
+            draw(seed, (uint64_t)k, (uint64_t)i, PURPOSE_GRID, w);
+            zfrac[(size_t)i * kh + k] = ldexpf((float)(w[0] >> 40), -24);
+            mult[(size_t)i * kh + k] = w[1] | 1ull;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* l2 -> l1 embedding (appendix theorem on embedding l2 into l1):           */
+/* T(x)_j = (1 / (beta k)) sum_i Z_ji x_i, beta = sqrt(2/pi), Z Gaussian.   */
+/* Z_jk from Box-Muller on the counter (j*d + k, 0, EMBED):                 */
+/*   u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1], u2 = (w1 >> 11) 2^-53 in [0, 1)*/
+/*   g  = sqrt(-2 ln u1) cos(2 pi u2)                                        */
+/* and the stored matrix is Zs_jk = (float)(g / (beta k)).  Zs is [ke][d].  */
+/* ------------------------------------------------------------------------ */
+void or_embedding(uint64_t seed, int d, int ke, float *Zs)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    const double beta = sqrt(2.0 / 3.14159265358979323846);
+    const double scale = 1.0 / (beta * (double)ke);
+    for (int j = 0; j < ke; ++j)
+        for (int k = 0; k < d; ++k) {
+            uint64_t w[4];
+            draw(seed, (uint64_t)j * (uint64_t)d + (uint64_t)k, 0, PURPOSE_EMBED, w);
+            double u1 = ldexp((double)((w[0] >> 11) + 1), -53);
+            double u2 = ldexp((double)(w[1] >> 11), -53);
+            double g = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+            Zs[(size_t)j * d + k] = (float)(g * scale);
+        }
+}
+
+/* smallest integer e with 2^e >= x, for x > 0 */
+static int ceil_log2_double(double x)
+{
+    int e;
+    double m = frexp(x, &e); /* x = m 2^e, m in [0.5, 1) */
+    return (m == 0.5) ? e - 1 : e;
+}
+
+/* Default number of scales: L = ceil(log2(max(nA, nB) / eps)), the
+ * L = O(log(n/eps)) of the CrudeNN figure, clamped to [1, 64]. */
+int or_default_scales(int64_t nA, int64_t nB, double eps)
+{
+    int64_t n = nA > nB ? nA : nB;
+    if (n < 1) n = 1;
+    int L = ceil_log2_double((double)n / eps);
+    if (L < 1) L = 1;
+    if (L > 64) L = 64;
+    return L;
+}
+
+/* Default number of samples: T = ceil(ceil(log2 nA) / eps^2), the
+ * T = O(log(n)/eps^2) of the main theorem's proof, at least 1. */
+int64_t or_default_samples(int64_t nA, double eps)
+{
+    int q = 0;
+    while (((int64_t)1 << q) < nA) ++q;
+    int64_t T = (int64_t)ceil((double)q / (eps * eps));
+    return T < 1 ? 1 : T;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scale calibration.  The CrudeNN figure assumes distances in             */
+/* [1, poly(n/eps)] and uses r_i = 2^i; this oracle instead takes the top   */
+/* scale from the data: lo_k/hi_k = per-coordinate min/max over A u B,      */
+/* S = sum_k (hi_k - lo_k) (double, k ascending) bounds every l1 (hence l2) */
+/* distance, e_top = smallest e with 2^e >= S (0 if S == 0), and scale i of */
+/* L (0 = finest) has side r_i = 2^(e_top - (L - 1 - i)).                   */
+/* ------------------------------------------------------------------------ */
+void or_calibrate(const float *A, int64_t nA, const float *B, int64_t nB, int d,
+                  float *lo, float *hi, double *S_out, int *e_top_out)
+{
+    for (int k = 0; k < d; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    for (int64_t r = 0; r < nA + nB; ++r) {
+        const float *x = r < nA ? A + (size_t)r * d : B + (size_t)(r - nA) * d;
+        for (int k = 0; k < d; ++k) {
+            if (x[k] < lo[k]) lo[k] = x[k];
+            if (x[k] > hi[k]) hi[k] = x[k];
+        }
+    }
+    double S = 0.0;
+    for (int k = 0; k < d; ++k) S = S + ((double)hi[k] - (double)lo[k]);
+    *S_out = S;
+    *e_top_out = (S > 0.0) ? ceil_log2_double(S) : 0;
+}
+
+/* Coordinates that get hashed: l1 hashes y = x - lo (d of them); l2 hashes
+ * the embedded y_j = sum_k Zs_jk (x_k - lo_k) accumulated with fmaf in
+ * ascending k (ke of them). */
+static void hashed_coords(const float *x, int d, int metric, const float *lo,
+                          const float *Zs, int ke, float *y)
+{
+    if (metric == OR_L1) {
+        for (int k = 0; k < d; ++k) y[k] = x[k] - lo[k];
+    } else {
+        for (int j = 0; j < ke; ++j) {
+            float acc = 0.0f;
+            for (int k = 0; k < d; ++k) acc = fmaf(Zs[(size_t)j * d + k], x[k] - lo[k], acc);
+            y[j] = acc;
+        }
+    }
+}
+
+/* Bucket key of point y at scale i (side 2^e):
+ *   cell_k = ceilf(ldexpf(y_k, -e) + z'_ik) + 0.0f   (the +0 folds -0 into +0)
+ *   key    = (sum_k bits(cell_k) * M_ik mod 2^64) >> 1
+ * Two points share a bucket iff their keys are equal; distinct cells share a
+ * key only by a 64-bit hash collision.  Keys fit in 63 bits. */
+static uint64_t bucket_key(const float *y, int kh, int e, const float *zf, const uint64_t *M)
+{
+    uint64_t acc = 0;
+    for (int k = 0; k < kh; ++k) {
+        float q = ldexpf(y[k], -e) + zf[k];
+        float c = ceilf(q) + 0.0f;
+        uint32_t bits;
+        memcpy(&bits, &c, 4);
+        acc += (uint64_t)bits * M[k];
+    }
+    return acc >> 1;
+}
+
+/* keys[i * n + p] for every point p of X and scale i < L. */
+void or_hash_keys(const float *X, int64_t n, int d, int metric, const float *lo,
+                  const float *Zs, int ke, int L, int e_top, const float *zfrac,
+                  const uint64_t *mult, uint64_t *keys)
+{
+    int kh = metric == OR_L1 ? d : ke;
+    float *y = (float *)malloc(sizeof(float) * (size_t)kh);
+    for (int64_t p = 0; p < n; ++p) {
+        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
+        for (int i = 0; i < L; ++i) {
+            int e = e_top - (L - 1 - i);
+            keys[(size_t)i * n + p] =
+                bucket_key(y, kh, e, zfrac + (size_t)i * kh, mult + (size_t)i * kh);
+        }
+    }
+    free(y);
+}
+
+/* Canonical single-precision distance (see header). */
+float or_dist32(const float *a, const float *b, int d, int metric)
+{
+    float acc = 0.0f;
+    if (metric == OR_L1) {
+        for (int k = 0; k < d; ++k) acc = acc + fabsf(a[k] - b[k]);
+        return acc;
+    }
+    for (int k = 0; k < d; ++k) {
+        float t = a[k] - b[k];
+        acc = fmaf(t, t, acc);
+    }
+    return sqrtf(acc);
+}
+
+/* Squared accumulator for l2 (before the square root), the l1 sum for l1. */
+static float acc32(const float *a, const float *b, int d, int metric)
+{
+    float acc = 0.0f;
+    if (metric == OR_L1) {
+        for (int k = 0; k < d; ++k) acc = acc + fabsf(a[k] - b[k]);
+        return acc;
+    }
+    for (int k = 0; k < d; ++k) {
+        float t = a[k] - b[k];
+        acc = fmaf(t, t, acc);
+    }
+    return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CrudeNN (CrudeNN figure, step 3): for each a the smallest scale i with   */
+/* some b in a's bucket; the candidate is the lowest-index such b, and      */
+/* D_a = dist32(a, b).  If no scale collides, the candidate is b = 0 (any   */
+/* b keeps D_a >= min_b d(a, b)) and the scale is reported as L.            */
+/* The join sorts B's (key, index) pairs per scale and binary-searches.     */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint64_t key; int64_t idx; } kv_t;
+
+static int kv_cmp(const void *x, const void *y)
+{
+    const kv_t *a = (const kv_t *)x, *b = (const kv_t *)y;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+    return 0;
+}
+
+void or_crude_nn(const uint64_t *keysA, int64_t nA, const uint64_t *keysB, int64_t nB,
+                 int L, const float *A, const float *B, int d, int metric,
+                 int32_t *scale_out, int32_t *nn_out, float *D_out)
+{
+    kv_t *tab = (kv_t *)malloc(sizeof(kv_t) * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t a = 0; a < nA; ++a) { scale_out[a] = -1; nn_out[a] = 0; }
+    for (int i = 0; i < L; ++i) {
+        for (int64_t b = 0; b < nB; ++b) { tab[b].key = keysB[(size_t)i * nB + b]; tab[b].idx = b; }
+        qsort(tab, (size_t)nB, sizeof(kv_t), kv_cmp);
+        for (int64_t a = 0; a < nA; ++a) {
+            if (scale_out[a] >= 0) continue;
+            uint64_t k = keysA[(size_t)i * nA + a];
+            int64_t lo = 0, hi = nB; /* first entry with key >= k */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (tab[mid].key < k) lo = mid + 1; else hi = mid;
+            }
+            if (lo < nB && tab[lo].key == k) { scale_out[a] = i; nn_out[a] = (int32_t)tab[lo].idx; }
+        }
+    }
+    for (int64_t a = 0; a < nA; ++a) {
+        if (scale_out[a] < 0) { scale_out[a] = L; nn_out[a] = 0; }
+        D_out[a] = or_dist32(A + (size_t)a * d, B + (size_t)nn_out[a] * d, d, metric);
+    }
+    free(tab);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact nearest neighbours (the definition of CH in the introduction).     */
+/* or_nn_f64: min over b in double precision, l2 by direct differences,     */
+/*            arg-min ties to the lower b.                                   */
+/* or_nn_f32: min over b of (dist32 accumulator, b), i.e. the canonical     */
+/*            float arg-min; returns dist32 of the winner.                   */
+/* rows (nullable) selects rows of X.                                        */
+/* ------------------------------------------------------------------------ */
+void or_nn_f64(const float *X, int64_t nx, const int32_t *rows, const float *B, int64_t nb,
+               int d, int metric, double *mind, int32_t *arg)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nx; ++r) {
+        const float *x = X + (size_t)(rows ? rows[r] : r) * d;
+        double best = INFINITY;
+        int64_t bi = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const float *y = B + (size_t)b * d;
+            double s = 0.0;
+            if (metric == OR_L1) {
+                for (int k = 0; k < d; ++k) s += fabs((double)x[k] - (double)y[k]);
+            } else {
+                for (int k = 0; k < d; ++k) {
+                    double t = (double)x[k] - (double)y[k];
+                    s += t * t;
+                }
+                s = sqrt(s);
+            }
+            if (s < best) { best = s; bi = b; }
+        }
+        mind[r] = best;
+        arg[r] = (int32_t)bi;
+    }
+}
+
+void or_nn_f32(const float *X, int64_t nx, const int32_t *rows, const float *B, int64_t nb,
+               int d, int metric, float *mind, int32_t *arg)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nx; ++r) {
+        const float *x = X + (size_t)(rows ? rows[r] : r) * d;
+        float best = INFINITY;
+        int64_t bi = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            float s = acc32(x, B + (size_t)b * d, d, metric);
+            if (s < best) { best = s; bi = b; }
+        }
+        mind[r] = metric == OR_L1 ? best : sqrtf(best);
+        arg[r] = (int32_t)bi;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Importance-sampling distribution (Chamfer-Estimate figure, steps 1-2) in */
+/* 64-bit fixed point.  With maxD = max_a D_a in [2^(e-1), 2^e) and         */
+/* q = ceil(log2 nA):  s = 47 - q - e,  w_a = ceil(D_a 2^s) (exact),         */
+/* P = inclusive prefix of w, W = P[nA-1] <= 2^47.  Pr[x = a] = w_a / W and */
+/* D = W 2^-s.  Returns 0, or 1 when every D_a is 0 (then w = P = W = 0).   */
+/* ------------------------------------------------------------------------ */
+int or_weights(const float *D, int64_t nA, int *s_out, uint64_t *w, uint64_t *P, uint64_t *W_out)
+{
+    float maxD = 0.0f;
+    for (int64_t a = 0; a < nA; ++a) if (D[a] > maxD) maxD = D[a];
+    if (!(maxD > 0.0f)) {
+        for (int64_t a = 0; a < nA; ++a) { w[a] = 0; P[a] = 0; }
+        *s_out = 0; *W_out = 0;
+        return 1;
+    }
+    int e;
+    frexp((double)maxD, &e);
+    int q = 0;
+    while (((int64_t)1 << q) < nA) ++q;
+    int s = 47 - q - e;
+    uint64_t run = 0;
+    for (int64_t a = 0; a < nA; ++a) {
+        w[a] = (uint64_t)ceil(ldexp((double)D[a], s));
+        run += w[a];
+        P[a] = run;
+    }
+    *s_out = s;
+    *W_out = run;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* T i.i.d. draws x ~ w/W (Chamfer-Estimate figure, step 3).  Draw l uses   */
+/* word0 of the counter (l, attempt, SAMPLE) and Lemire's bounded-integer   */
+/* method (ACM TOMACS 2019): m = x W (128-bit), reject while the low half   */
+/* is below (2^64 - W) mod W, u = m >> 64 is uniform on [0, W); the sample  */
+/* is the first a with P[a] > u.                                             */
+/* ------------------------------------------------------------------------ */
+void or_sample(uint64_t seed, const uint64_t *P, int64_t nA, uint64_t W, int64_t T, int32_t *idx)
+{
+    for (int64_t l = 0; l < T; ++l) {
+        uint64_t u = 0;
+        for (uint64_t attempt = 0;; ++attempt) {
+            uint64_t w4[4];
+            draw(seed, (uint64_t)l, attempt, PURPOSE_SAMPLE, w4);
+            unsigned __int128 m = (unsigned __int128)w4[0] * W;
+            uint64_t low = (uint64_t)m;
+            if (low < W) {
+                uint64_t t = (0 - W) % W;
+                if (low < t) continue;
+            }
+            u = (uint64_t)(m >> 64);
+            break;
+        }
+        int64_t lo = 0, hi = nA - 1; /* first a with P[a] > u */
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (P[mid] > u) hi = mid; else lo = mid + 1;
+        }
+        idx[l] = (int32_t)lo;
+    }
+}

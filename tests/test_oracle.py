@@ -1,0 +1,444 @@
+"""Pins for the CPU oracle: each test ties a piece of the oracle to something
+other than the oracle itself -- an independent library implementation, a
+closed form, a value derived by hand, or a statement the paper proves.
+
+Where the oracle computes a plain definition (CH, nearest neighbours) it is
+checked against scipy and hand-derived values; where it follows the paper's
+randomized algorithms it is checked against the lemmas the paper proves
+about them (collision probability of the grid hash, the l2->l1 embedding's
+normalisation, D_a >= min_b d(a,b), unbiasedness and the variance bound of
+the estimator, the outlier scenario of the experiments section).
+"""
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+from scipy.spatial.distance import cdist
+from scipy import stats
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U32 = 2.0 ** -24  # unit roundoff of float32
+
+
+# ---------------------------------------------------------------- Philox ---
+
+def test_philox_matches_numpy(orc):
+    """Philox4x64-10 vs numpy's own implementation (numpy increments the
+    counter before producing each block)."""
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        key = rng.integers(0, 2**63, size=2, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        ctr = rng.integers(1, 2**63, size=4, dtype=np.uint64)
+        bg = np.random.Philox(key=key, counter=ctr - np.array([1, 0, 0, 0], np.uint64))
+        ref = bg.random_raw(4)
+        np.testing.assert_array_equal(orc.philox4x64(ctr, key), ref)
+
+
+# ---------------------------------------------------------- exact CH -------
+
+def test_exact_hand_cases(orc):
+    with open(os.path.join(GOLDEN, "hand_cases.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        A = np.array(c["A"], np.float32)
+        B = np.array(c["B"], np.float32)
+        for metric, key in ((1, "l1"), (2, "l2")):
+            ch, _, _ = orc.chamfer_exact(A, B, metric)
+            assert ch == pytest.approx(c[key], rel=1e-15, abs=1e-15)
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("d", [1, 3, 17])
+def test_exact_vs_scipy(orc, metric, d):
+    rng = np.random.default_rng(d * 10 + metric)
+    A = rng.standard_normal((57, d)).astype(np.float32)
+    B = rng.standard_normal((41, d)).astype(np.float32)
+    ch, mind, arg = orc.chamfer_exact(A, B, metric)
+    M = cdist(A.astype(np.float64), B.astype(np.float64),
+              "cityblock" if metric == 1 else "euclidean")
+    np.testing.assert_allclose(mind, M.min(axis=1), rtol=1e-13)
+    np.testing.assert_array_equal(arg, M.argmin(axis=1))
+    dist, _ = cKDTree(B.astype(np.float64)).query(A.astype(np.float64), k=1, p=metric)
+    assert ch == pytest.approx(float(np.sum(dist)), rel=1e-12)
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_exact_invariants(orc, metric):
+    rng = np.random.default_rng(5)
+    A = rng.integers(-50, 50, size=(40, 4)).astype(np.float32)
+    B = rng.integers(-50, 50, size=(33, 4)).astype(np.float32)
+    ch, _, _ = orc.chamfer_exact(A, B, metric)
+    assert orc.chamfer_exact(A, A, metric)[0] == 0.0
+    # permutation of either set
+    assert orc.chamfer_exact(A[::-1].copy(), B[rng.permutation(33)], metric)[0] == pytest.approx(ch, rel=1e-15)
+    # integer translation (exact in float32) and scaling by 2 (exact)
+    assert orc.chamfer_exact(A + 7, B + 7, metric)[0] == pytest.approx(ch, rel=1e-15)
+    assert orc.chamfer_exact(2 * A, 2 * B, metric)[0] == pytest.approx(2 * ch, rel=1e-15)
+    # |B| = 1: CH is the plain sum of distances to the single point
+    b = B[:1]
+    ref = np.sum(np.abs(A - b).sum(1)) if metric == 1 else np.sum(np.sqrt(((A.astype(np.float64) - b) ** 2).sum(1)))
+    assert orc.chamfer_exact(A, b, metric)[0] == pytest.approx(float(ref), rel=1e-14)
+
+
+def test_dist32_exact_on_small_integers(orc):
+    """With small integer coordinates every float32 step is exact, so
+    dist32 equals the closed-form integer distance."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        d = int(rng.integers(1, 40))
+        a = rng.integers(-100, 100, size=d).astype(np.float32)
+        b = rng.integers(-100, 100, size=d).astype(np.float32)
+        l1 = int(np.abs(a.astype(np.int64) - b.astype(np.int64)).sum())
+        l2sq = int(((a.astype(np.int64) - b.astype(np.int64)) ** 2).sum())
+        assert orc.dist32(a, b, 1) == np.float32(l1)
+        assert orc.dist32(a, b, 2) == np.float32(math.sqrt(l2sq))
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_dist32_error_bound(orc, metric):
+    """dist32 is within the float32 rounding bound of the exact distance."""
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        d = int(rng.integers(1, 300))
+        a = (rng.standard_normal(d) * 10).astype(np.float32)
+        b = (rng.standard_normal(d) * 10).astype(np.float32)
+        ex = cdist(a[None].astype(np.float64), b[None].astype(np.float64),
+                   "cityblock" if metric == 1 else "euclidean")[0, 0]
+        bound = (d + 3) * U32 * ex
+        assert abs(float(orc.dist32(a, b, metric)) - ex) <= bound
+
+
+def test_nn_f32_is_canonical_argmin(orc):
+    """nn_f32 picks, among equal float32 distances, the lower index."""
+    A = np.array([[0.0, 0.0]], np.float32)
+    B = np.array([[3.0, 4.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]], np.float32)
+    for metric in (1, 2):
+        m, arg = orc.nn_f32(A, B, metric)
+        assert arg[0] == 1 and m[0] == 1.0
+        m64, arg64 = orc.nn_f64(A, B, metric)
+        assert arg64[0] == 1 and m64[0] == 1.0
+
+
+# ---------------------------------------------------------- parameters -----
+
+def test_default_parameters(orc):
+    with open(os.path.join(GOLDEN, "parameters.json")) as f:
+        g = json.load(f)
+    for c in g["scales"]:
+        assert orc.default_scales(c["n_a"], c["n_b"], c["eps"]) == c["L"]
+    for c in g["samples"]:
+        assert orc.default_samples(c["n_a"], c["eps"]) == c["T"]
+
+
+def test_calibration_hand_cases(orc):
+    A = np.array([[0, 0], [1, 3]], np.float32)
+    B = np.array([[-1, 2]], np.float32)
+    lo, hi, S, e = orc.calibrate(A, B)
+    np.testing.assert_array_equal(lo, [-1, 0])
+    np.testing.assert_array_equal(hi, [1, 3])
+    assert S == 5.0 and e == 3          # 2^2 < 5 <= 2^3
+    lo, hi, S, e = orc.calibrate(np.array([[0, 0]], np.float32), np.array([[4, 0]], np.float32))
+    assert S == 4.0 and e == 2          # exact power of two
+    lo, hi, S, e = orc.calibrate(np.ones((3, 2), np.float32), np.ones((2, 2), np.float32))
+    assert S == 0.0 and e == 0          # all points coincide
+    lo, hi, S, e = orc.calibrate(np.array([[0.0]], np.float32), np.array([[0.75]], np.float32))
+    assert e == 0                       # 2^-1 < 0.75 <= 2^0
+
+
+# ------------------------------------------------------------- hashing -----
+
+def _keys_at(orc, X, seed, e, lo=None, metric=1, Zs=None, kh=None):
+    """Keys of X at one scale of side 2^e (L = 1, e_top = e)."""
+    d = X.shape[1]
+    kh = kh or d
+    zf, mt = orc.grid_tables(seed, 1, kh)
+    lo = np.zeros(d, np.float32) if lo is None else lo
+    return orc.hash_keys(X, metric, lo, Zs, 1, e, zf, mt)[0]
+
+
+def test_grid_collision_probability(orc):
+    """Appendix lemma on the grid hash: Pr[h(x) = h(y)] =
+    prod_k max(0, 1 - |x_k - y_k| / r).  Monte Carlo over seeds."""
+    x = np.array([0.3, 0.1, 0.7, 2.0], np.float32)
+    cases = [
+        (np.array([0.2, -0.1, 0.05, 0.0], np.float32), 0),    # r = 1
+        (np.array([0.6, 0.3, 0.0, -0.5], np.float32), 1),     # r = 2
+        (np.array([1.5, 0.0, 0.0, 0.0], np.float32), 0),      # separated: prob 0
+        (np.array([0.05, 0.02, 0.01, 0.0], np.float32), -2),  # r = 1/4
+    ]
+    n_seeds = 3000
+    for delta, e in cases:
+        y = x + delta
+        r = 2.0 ** e
+        p = float(np.prod(np.maximum(0.0, 1.0 - np.abs((y.astype(np.float64) - x)) / r)))
+        X = np.stack([x, y])
+        hits = 0
+        for s in range(n_seeds):
+            k = _keys_at(orc, X, 1000 + s, e)
+            hits += int(k[0] == k[1])
+        sd = math.sqrt(max(p * (1 - p), 1e-12) / n_seeds)
+        assert abs(hits / n_seeds - p) <= 4.5 * sd + 1e-9, (delta, e, hits / n_seeds, p)
+
+
+def test_same_cell_same_key_distinct_cells_distinct_keys(orc):
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 64, size=(4000, 6)).astype(np.float32)
+    zf, mt = orc.grid_tables(77, 1, 6)
+    keys = orc.hash_keys(X, 1, np.zeros(6, np.float32), None, 1, 3, zf, mt)[0]
+    cells = np.ceil(np.ldexp(X, -3).astype(np.float32) + zf[0]).astype(np.int64)
+    # equal cells <=> equal keys on this sample (no 63-bit collisions expected)
+    _, inv_c = np.unique(cells, axis=0, return_inverse=True)
+    _, inv_k = np.unique(keys, return_inverse=True)
+    assert len(np.unique(inv_c)) == len(np.unique(inv_k))
+    pairs = set(zip(inv_c.ravel().tolist(), inv_k.ravel().tolist()))
+    assert len(pairs) == len(np.unique(inv_c))
+    assert int(keys.max()) < 2 ** 63
+
+
+def test_shift_table_range(orc):
+    zf, mt = orc.grid_tables(5, 24, 64)
+    assert zf.min() >= 0.0 and zf.max() < 1.0
+    assert np.all(np.ldexp(zf.astype(np.float64), 24) == np.round(np.ldexp(zf.astype(np.float64), 24)))
+    assert np.all(mt & np.uint64(1) == 1)
+    # roughly uniform on [0, 1)
+    assert stats.kstest(zf.ravel(), "uniform").pvalue > 1e-4
+    # independent per scale
+    assert not np.array_equal(zf[0], zf[1])
+
+
+def test_embedding_normalisation(orc):
+    """Appendix theorem embedding l2 into l1: with beta = sqrt(2/pi),
+    E ||T(x)||_1 = ||x||_2.  Averaged over seeds."""
+    rng = np.random.default_rng(9)
+    d, ke = 24, 32
+    x = rng.standard_normal(d)
+    vals = []
+    for s in range(600):
+        Zs = orc.embedding(s, d, ke).astype(np.float64)
+        vals.append(np.abs(Zs @ x).sum())
+    vals = np.array(vals)
+    ratio = vals.mean() / np.linalg.norm(x)
+    assert abs(ratio - 1.0) < 4.5 * vals.std() / np.linalg.norm(x) / math.sqrt(len(vals))
+    # entries are N(0, 1) / (beta * ke)
+    Zs = orc.embedding(123, 64, 64).astype(np.float64) * math.sqrt(2 / math.pi) * 64
+    assert stats.kstest(Zs.ravel(), "norm").pvalue > 1e-4
+
+
+# -------------------------------------------------------------- CrudeNN ----
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_crude_nn_join_brute_force(orc, metric):
+    """CrudeNN figure, step 3, checked by brute force over all (a, b, i):
+    the reported scale is the first with any b sharing a's key, and the
+    candidate is the lowest such b."""
+    rng = np.random.default_rng(21 + metric)
+    A = rng.uniform(-3, 3, size=(150, 5)).astype(np.float32)
+    B = rng.uniform(-3, 3, size=(90, 5)).astype(np.float32)
+    r = orc.crude_nn(A, B, metric, 0.3, seed=99, n_scales=12)
+    kA, kB, L = r["keys_a"], r["keys_b"], r["L"]
+    for a in range(A.shape[0]):
+        first, cand = L, 0
+        for i in range(L):
+            hit = np.nonzero(kB[i] == kA[i, a])[0]
+            if hit.size:
+                first, cand = i, int(hit[0])
+                break
+        assert r["scale"][a] == first and r["nn"][a] == cand
+        assert r["D"][a] == orc.dist32(A[a], B[cand], metric)
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_crude_nn_upper_bound(orc, metric):
+    """Oversampling lemma: D_a >= min_b d(a, b) with probability one."""
+    A, B = workloads.clusters_l2(seed=4, n=600, d=12, k=20)
+    r = orc.crude_nn(A, B, metric, 0.2, seed=5)
+    m32, _ = orc.nn_f32(A, B, metric)
+    m64, _ = orc.nn_f64(A, B, metric)
+    assert np.all(r["D"] >= m32)
+    assert np.all(r["D"].astype(np.float64) >= m64 * (1 - 1e-6))
+    lam = r["D"].astype(np.float64).sum() / m64.sum()
+    assert 1.0 <= lam < 8.0          # E[D_a] <= O(log n) min_b d(a,b)
+
+
+def test_crude_nn_single_b_and_self(orc):
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((50, 7)).astype(np.float32)
+    b = rng.standard_normal((1, 7)).astype(np.float32)
+    for metric in (1, 2):
+        r = orc.crude_nn(A, b, metric, 0.1, seed=1)
+        assert np.all(r["nn"] == 0)
+        assert np.all(r["D"] == np.array([orc.dist32(a, b[0], metric) for a in A]))
+    # A = B with well separated points: every a finds itself at the finest scale
+    P = rng.uniform(0, 1, size=(100, 3)).astype(np.float32)
+    for metric in (1, 2):
+        r = orc.crude_nn(P, P, metric, 0.1, seed=2)
+        assert np.all(r["D"] == 0.0)
+
+
+def test_grid_levels_vs_quality(orc):
+    """More grid levels cannot make D_a worse on average here (experiments
+    section: a few levels already give D_a within ~2x)."""
+    A, B = workloads.small_l2(seed=3, n=1500, d=3)
+    m64, _ = orc.nn_f64(A, B, 1)
+    lam = {}
+    for L in (3, 8, 16):
+        r = orc.crude_nn(A, B, 1, 0.2, seed=8, n_scales=L)
+        lam[L] = r["D"].astype(np.float64).sum() / m64.sum()
+    assert lam[16] <= lam[3] + 1e-9
+    assert lam[16] < 4.0
+
+
+# -------------------------------------------------------------- weights ----
+
+def test_weights_closed_form(orc):
+    rng = np.random.default_rng(7)
+    for n in (1, 2, 3, 1000, 4097):
+        D = np.abs(rng.standard_normal(n) * rng.choice([1e-6, 1.0, 1e6])).astype(np.float32)
+        D[rng.integers(0, n, size=max(1, n // 10))] = 0.0
+        D[0] = max(D[0], np.float32(1e-3))
+        s, w, P, W, zero = orc.weights(D)
+        assert not zero
+        q = max(0, math.ceil(math.log2(n))) if n > 1 else 0
+        assert 2 ** q >= n and (q == 0 or 2 ** (q - 1) < n)
+        mx = Fraction(float(D.max())) * (Fraction(2) ** s)
+        assert Fraction(2) ** (46 - q) <= mx < Fraction(2) ** (47 - q)
+        for a in range(0, n, max(1, n // 200)):
+            assert int(w[a]) == math.ceil(Fraction(float(D[a])) * (Fraction(2) ** s))
+        assert np.array_equal(P, np.cumsum(w, dtype=np.uint64))
+        assert W == int(P[-1]) and W <= 2 ** 47
+        assert np.all((w == 0) == (D == 0))
+    s, w, P, W, zero = orc.weights(np.zeros(5, np.float32))
+    assert zero and W == 0
+
+
+def test_sampling_frequencies(orc):
+    """Draws follow Pr[x = a] = w_a / W (chi-square)."""
+    D = np.array([1, 100, 1, 0, 50, 3, 100, 7], np.float32)
+    s, w, P, W, _ = orc.weights(D)
+    T = 200_000
+    idx = orc.sample(12345, P, W, T)
+    cnt = np.bincount(idx, minlength=len(D))
+    assert cnt[3] == 0                    # zero weight is never drawn
+    nz = w > 0
+    expected = T * w[nz].astype(np.float64) / W
+    chi = ((cnt[nz] - expected) ** 2 / expected).sum()
+    assert stats.chi2.sf(chi, nz.sum() - 1) > 1e-4
+
+
+def test_sampling_small_totals(orc):
+    """With W = 1 every draw is the one point of weight 1; with tiny W all
+    draws land on positive-weight points and cover them."""
+    P = np.array([0, 0, 1, 1], np.uint64)
+    assert np.all(orc.sample(3, P, 1, 100) == 2)
+    P = np.array([1, 1, 3], np.uint64)
+    idx = orc.sample(4, P, 3, 3000)
+    assert set(idx.tolist()) == {0, 2}
+    assert abs(np.mean(idx == 2) - 2 / 3) < 0.05
+
+
+# ------------------------------------------------------------ estimator ----
+
+def test_estimator_single_a(orc):
+    """|A| = 1: every sample is that point with weight W/w = 1."""
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((1, 5)).astype(np.float32)
+    B = rng.standard_normal((300, 5)).astype(np.float32)
+    for metric in (1, 2):
+        ch, _, _ = orc.chamfer_exact(A, B, metric)
+        for seed in range(5):
+            r = orc.chamfer_estimate(A, B, metric, 0.1, 50, seed)
+            assert r["eta"] == pytest.approx(ch, rel=1e-15)
+
+
+def test_estimator_single_b(orc):
+    """|B| = 1: D_a is the true distance (in float32), so every seed gives
+    CH up to float32 rounding and the 2^-(47-q) weight quantisation."""
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((700, 6)).astype(np.float32)
+    b = rng.standard_normal((1, 6)).astype(np.float32)
+    for metric in (1, 2):
+        ch, _, _ = orc.chamfer_exact(A, b, metric)
+        for seed in range(5):
+            r = orc.chamfer_estimate(A, b, metric, 0.1, 64, seed)
+            assert r["eta"] == pytest.approx(ch, rel=2e-6)
+
+
+def test_estimator_degenerate(orc):
+    rng = np.random.default_rng(15)
+    P = rng.standard_normal((200, 4)).astype(np.float32)
+    for metric in (1, 2):
+        assert orc.chamfer_estimate(P, P, metric, 0.1, 100, 3)["eta"] == 0.0
+        same = np.ones((20, 4), np.float32)
+        assert orc.chamfer_estimate(same, same[:3], metric, 0.1, 100, 3)["eta"] == 0.0
+        assert orc.chamfer_estimate(P[:0], P, metric, 0.1, 100, 3)["eta"] == 0.0
+
+
+def test_estimator_unbiased_and_variance(orc):
+    """Variance lemma: E[eta] = CH and Var[eta] <= CH^2 (D/CH - 1) / T,
+    for a fixed CrudeNN output, over the sampling randomness."""
+    A, B = workloads.small_l2(seed=17, n=300, d=4)
+    metric, T = 1, 20
+    ch, m64, _ = orc.chamfer_exact(A, B, metric)
+    crude = orc.crude_nn(A, B, metric, 0.2, seed=1)
+    s, w, P, W, _ = orc.weights(crude["D"])
+    # variance of one term under the quantised distribution, in closed form
+    wf = w.astype(np.float64)
+    pos = wf > 0
+    second = np.sum((W / wf[pos]) * m64[pos] ** 2)
+    var_exact = (second - ch ** 2) / T
+    Dn = math.ldexp(W, -s)
+    assert var_exact <= ch ** 2 * (Dn / ch - 1) / T * (1 + 1e-9)
+    etas = np.array([orc.chamfer_estimate(A, B, metric, 0.2, T, seed, crude=crude)["eta"]
+                     for seed in range(1500)])
+    # the crude output above must not depend on the sampling seed
+    assert abs(etas.mean() - ch) <= 4.5 * math.sqrt(var_exact / len(etas))
+    ratio = etas.var(ddof=1) / var_exact
+    lo, hi = stats.chi2.ppf([1e-5, 1 - 1e-5], len(etas) - 1) / (len(etas) - 1)
+    assert lo <= ratio <= hi * 1.2     # heavy tails: allow some slack above
+
+
+def test_estimator_unbiased_over_hash_seeds(orc):
+    """Unbiasedness also holds averaging over the hash randomness."""
+    A, B = workloads.small_l2(seed=18, n=200, d=3)
+    ch, _, _ = orc.chamfer_exact(A, B, 2)
+    etas = np.array([orc.chamfer_estimate(A, B, 2, 0.2, 16, s)["eta"] for s in range(800)])
+    assert abs(etas.mean() - ch) <= 4.5 * etas.std(ddof=1) / math.sqrt(len(etas))
+
+
+def test_estimator_coverage_small_config(orc):
+    """Main theorem: within (1 +- eps) CH with probability >= 99/100.
+    Small configuration (l2, d = 16, eps = 0.2, T = 512), 300 seeds here
+    (the GPU suite runs 1000)."""
+    A, B = workloads.small_l2()
+    ch, _, _ = orc.chamfer_exact(A, B, 2)
+    crude_fail = 0
+    for seed in range(300):
+        eta = orc.chamfer_estimate(A, B, 2, 0.2, 512, seed)["eta"]
+        crude_fail += int(abs(eta - ch) > 0.2 * ch)
+    assert crude_fail <= 3
+
+
+@pytest.mark.parametrize("d", [2, 100])
+def test_outlier_scenario(orc, d):
+    """Experiments section, outliers: a Gaussian cloud plus one point at
+    0.5 n (1,...,1).  Importance sampling finds the outlier and stays within
+    eps; uniform sampling of the same budget misses it."""
+    A, B = workloads.outlier_cloud(seed=d, n=2000, d=d)
+    ch, m64, _ = orc.chamfer_exact(A, B, 1)
+    share = m64[-1] / ch
+    assert share > 0.25                     # the outlier carries much of CH
+    rng = np.random.default_rng(0)
+    for seed in range(10):
+        r = orc.chamfer_estimate(A, B, 1, 0.1, 100, seed)
+        assert abs(r["eta"] - ch) <= 0.1 * ch
+        uni = rng.integers(0, A.shape[0], size=100)
+        u_est = A.shape[0] * m64[uni].mean()
+        if A.shape[0] - 1 not in uni:
+            assert abs(u_est - ch) > 0.5 * share * ch
