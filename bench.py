@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the Chamfer estimator on one MI355X.
+
+One step = one chamfer_estimate call (calibration, grid tables, bucketing of
+B, CrudeNN probe of A, fixed-point weights and draws, exact nearest
+neighbours of the T draws, reweighted mean) on inputs already resident in
+HBM.  The default workload is l2, |A| = |B| = 100,000, d = 128, 1000-cluster
+Gaussian mixture, eps = 0.1, T = 2000, L = 20 scales.  Also timed on the
+same inputs: brute-force exact CH on the GPU (chamfer_exact), per-stage
+times from HIP events recorded by the library, per-step latency
+percentiles, and the CPU oracle on the host.
+
+Prints one JSON line.  --gpus N with N > 1 exits with a message: this build
+runs on one GPU.
+"""
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC_NAME = "Chamfer points/s at ε=0.1 vs GPU brute force; %HBM/MFMA peak; p50/p99 ms"
+
+# MI355X published peaks and unit counts.
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
+BF16_MFMA_TFLOPS = 2500.0
+# Plain (non-packed) FP32 vector lane operations: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz.
+VALU_LANE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    # name: (generator, kwargs, metric, eps, T, L, description)
+    "l2_100k_d128": ("clusters_l2", dict(n=100_000, d=128, k=1000), 2, 0.1, 2000, 20,
+                     "l2, |A|=|B|=100000, d=128, 1000-cluster Gaussian mixture "
+                     "(centres N(0,16 I), sigma~U[0.2,1]); eps=0.1, T=2000, L=20"),
+    "l2_1m_d128": ("clusters_l2", dict(n=1_000_000, d=128, k=1000), 2, 0.1, 2000, 24,
+                   "l2, |A|=|B|=1000000, d=128, 1000-cluster Gaussian mixture; eps=0.1, "
+                   "T=2000, L=24"),
+    "l1_1m_d64": ("mixed_l1", dict(n=1_000_000, d=64, k=5000), 1, 0.1, 2000, 24,
+                  "l1, |A|=|B|=1000000, d=64, 70% 5000-cluster Laplace(0,0.5) mixture + "
+                  "30% uniform [-50,50]^64; eps=0.1, T=2000, L=24"),
+    "l2_4k_d16": ("small_l2", dict(n=4096, d=16), 2, 0.2, 512, 15,
+                  "l2, |A|=|B|=4096, d=16, 16-centre mixture; eps=0.2, T=512, L=15"),
+}
+
+
+def loaded_hip_runtime():
+    """Path of the HIP runtime already mapped into this process (the one torch
+    and libchamfer use), so events and streams come from one runtime."""
+    with open("/proc/self/maps") as f:
+        for line in f:
+            path = line.split()[-1]
+            if "libamdhip64.so" in path:
+                return path
+    return "libamdhip64.so.7"
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime (ctypes)."""
+
+    def __init__(self, n):
+        self.hip = ctypes.CDLL(loaded_hip_runtime())
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            h = ctypes.c_void_p()
+            rc = self.hip.hipEventCreate(ctypes.byref(h))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed: {rc}")
+            self.arr[i] = h
+
+    def ms(self, i, j):
+        self.hip.hipEventSynchronize(self.arr[j])
+        out = ctypes.c_float()
+        rc = self.hip.hipEventElapsedTime(ctypes.byref(out), self.arr[i], self.arr[j])
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(out.value)
+
+    def close(self):
+        for h in self.arr:
+            self.hip.hipEventDestroy(h)
+
+
+def algorithmic_sample_pass(metric, T, n_b, d):
+    """Work of the exact pass over the draws: T * n_B * d coordinate terms."""
+    elems = float(T) * n_b * d
+    if metric == 2:
+        return dict(bound="alu", unit="TOP/s", ops=2.0 * elems, peak=VALU_LANE_TOPS,
+                    note="2 VALU lane-ops (subtract, fma) per coordinate term")
+    return dict(bound="alu", unit="TOP/s", ops=2.0 * elems, peak=VALU_LANE_TOPS,
+                note="2 VALU lane-ops (subtract, add |t|) per coordinate term")
+
+
+def cpu_baseline(args, A, B, metric, eps, T, L, seed):
+    import oracle
+    n_a = A.shape[0]
+    t0 = time.perf_counter()
+    ref = oracle.chamfer_estimate(A, B, metric, eps, T, seed, n_scales=L)
+    dt = time.perf_counter() - t0
+    return dict(value=(A.shape[0] + B.shape[0]) / dt, unit="points/s", cores=oracle.threads(),
+                kind="oracle", seconds=dt,
+                sample=f"full workload (|A|={n_a}, |B|={B.shape[0]}), one estimate; "
+                       f"double-precision exact pass on {oracle.threads()} OpenMP threads, "
+                       f"hashing single-threaded"), ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="l2_100k_d128", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--brute-steps", type=int, default=2)
+    ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2307_03043_amd as ch
+    import workloads
+
+    gen, kw, metric, eps, T, L, desc = WORKLOADS[args.workload]
+    A, B = getattr(workloads, gen)(seed=args.seed, **kw)
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A).to(dev)
+    Bt = torch.from_numpy(B).to(dev)
+    torch.cuda.synchronize()
+    seed = 1
+
+    def step():
+        return ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, with_aux=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] {args.workload}: warmup done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    eta = float(out["eta"].item())
+    print(f"[bench] timed {args.steps} steps: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # per-stage times and per-step latency from the library's stage events
+    ev = HipEvents(ch.STAGE_EVENTS * args.steps)
+    outs = []
+    for s in range(args.steps):
+        sub = ctypes.c_void_p(ctypes.addressof(ev.arr)
+                              + s * ch.STAGE_EVENTS * ctypes.sizeof(ctypes.c_void_p))
+        outs.append(ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, with_aux=True,
+                                        stage_events=sub))
+    torch.cuda.synchronize()
+    names = ["calibrate+tables", "bucket_B", "probe_A+D_a", "weights+draws", "exact_pass",
+             "final"]
+    stage = np.zeros((args.steps, len(names)))
+    lat = np.zeros(args.steps)
+    for s in range(args.steps):
+        base = s * ch.STAGE_EVENTS
+        for i in range(len(names)):
+            stage[s, i] = ev.ms(base + i, base + i + 1)
+        lat[s] = ev.ms(base, base + ch.STAGE_EVENTS - 1)
+    ev.close()
+    aux = outs[-1]
+    stages_ms = {n: float(stage[:, i].mean()) for i, n in enumerate(names)}
+    dom = int(np.argmax(stage.mean(axis=0)))
+    lam = float(aux["D"].item())
+
+    # roofline of the exact pass over the draws (one kernel, stage 4 -> 5)
+    work = algorithmic_sample_pass(metric, T, n_b, d)
+    kernel_ms = stages_ms["exact_pass"]
+    achieved = work["ops"] / (kernel_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_nnmin (exact pass over the T draws)", "bound": work["bound"],
+                "achieved": achieved, "peak": work["peak"], "unit": work["unit"],
+                "frac": achieved / work["peak"], "traffic": None, "kernel_ms": kernel_ms,
+                "algorithmic": work["note"]}
+
+    result = {
+        "metric": METRIC_NAME,
+        "value": (n_a + n_b) / dt,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "n_a": n_a, "n_b": n_b, "d": d,
+                   "metric": "l2" if metric == 2 else "l1", "eps": eps, "T": T, "L": L,
+                   "seed": args.seed},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "stages_ms": stages_ms,
+        "dominant_stage": names[dom],
+        "roofline": roofline,
+        "eta": eta,
+        "D_normaliser": lam,
+    }
+
+    if not args.no_brute:
+        ch.chamfer_exact(At, Bt, metric, rows_out=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.brute_steps):
+            ex, _, _ = ch.chamfer_exact(At, Bt, metric, rows_out=False)
+        torch.cuda.synchronize()
+        bt = (time.perf_counter() - t0) / args.brute_steps
+        exact = float(ex.item())
+        result["brute_force"] = {"ms": bt * 1e3, "points_per_s": (n_a + n_b) / bt,
+                                 "speedup_of_estimate": bt / dt, "CH": exact,
+                                 "dtype": "f32", "kernel": "k_nnmin over all rows of A"}
+        result["accuracy"] = {"rel_err": abs(eta - exact) / exact, "lambda_hat": lam / exact}
+        print(f"[bench] brute force {bt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        base, ref = cpu_baseline(args, A, B, metric, eps, T, L, seed)
+        result["cpu_baseline"] = base
+        result["accuracy"] = dict(result.get("accuracy", {}),
+                                  oracle_eta=ref["eta"], gpu_vs_oracle_rel=abs(eta - ref["eta"]) / ref["eta"])
+        print(f"[bench] cpu oracle {base['seconds']:.2f} s", file=sys.stderr, flush=True)
+
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * chamfer.h -- C ABI of libchamfer, a gfx950 (MI355X) implementation of the
+ * near-linear (1 +- eps) Chamfer-distance estimator of Bakshi, Indyk,
+ * Jayaram, Silwal and Waingarten, "A Near-Linear Time Algorithm for the
+ * Chamfer Distance" (NeurIPS 2023), and of the exact brute-force Chamfer
+ * distance it speeds up.
+ *
+ *   CH(A, B) = sum_{a in A} min_{b in B} d(a, b),  d = l1 or l2, NOT squared
+ *   (definition of CH in the introduction and the footnote to it).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Point sets are DEVICE pointers to row-major, contiguous float32 arrays
+ *   [n, d] (row p at X + p*d).  Every other array argument is a device
+ *   pointer too, unless marked "host".  The caller owns all memory,
+ *   including the workspace `ws` (size from chamfer_workspace_bytes); the
+ *   library never allocates or frees device memory and keeps no state
+ *   between calls.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   work is enqueued on it asynchronously; the caller synchronises.  Output
+ *   buffers are valid once the stream has reached the end of the call.
+ * - Return value: CHAMFER_OK, or a negative chamfer_status for an argument
+ *   error (checked on the host before anything is launched) or a failed HIP
+ *   launch.  Data-dependent errors (a NaN or Inf coordinate) cannot be seen
+ *   on the host without a synchronisation; they are reported through the
+ *   optional device status word and make the floating outputs NaN.
+ * - Calls on one stream with one workspace must not overlap; calls with
+ *   distinct workspaces may run concurrently on distinct streams.
+ * - Results are deterministic: the same arguments give bit-identical outputs
+ *   on every run, whatever the launch configuration (no floating-point
+ *   atomics; integer atomics only for min/max, whose result is order-free).
+ */
+#ifndef CHAMFER_H
+#define CHAMFER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum chamfer_metric { CHAMFER_L1 = 1, CHAMFER_L2 = 2 };
+
+enum chamfer_status {
+    CHAMFER_OK = 0,
+    CHAMFER_EINVAL = -1,      /* bad argument (host check, nothing launched)   */
+    CHAMFER_EWORKSPACE = -2,  /* ws NULL or ws_bytes < chamfer_workspace_bytes */
+    CHAMFER_EHIP = -3,        /* a HIP launch or runtime call failed           */
+    CHAMFER_ENONFINITE = -4   /* device status: an input coordinate is NaN/Inf */
+};
+
+enum chamfer_precision {
+    CHAMFER_FP32 = 0,  /* float32 arithmetic, exact canonical arg-mins        */
+    CHAMFER_BF16 = 1,  /* l2 distance tiles on bf16 MFMA + float32 re-rank    */
+    CHAMFER_FP8 = 2    /* l2 distance tiles on fp8-e4m3 MFMA + float32 re-rank*/
+};
+
+/* Tunables; pass NULL for all defaults.  Zero fields take their default. */
+typedef struct chamfer_opts {
+    int32_t n_scales;   /* L grid scales; 0 => ceil(log2(max(n_A,n_B)/eps))   */
+    int32_t embed_dim;  /* l2 only: embedding dimension k_e; 0 => 32          */
+    int32_t precision;  /* enum chamfer_precision; 0 => CHAMFER_FP32          */
+    int32_t reserved;   /* must be 0                                          */
+} chamfer_opts;
+
+/* Optional device outputs of chamfer_estimate; any field may be NULL. */
+typedef struct chamfer_aux {
+    int32_t *sample_idx;   /* [T] sampled rows x_l of A                         */
+    float *sample_min;     /* [T] min_b d(x_l, b), float32                      */
+    int32_t *sample_nn;    /* [T] the b attaining it (lowest index on ties)     */
+    double *D;             /* [1] normaliser D = sum_a D_a (= W * 2^-s)         */
+    uint64_t *W;           /* [1] fixed-point total of the weights              */
+    int32_t *s;            /* [1] fixed-point exponent (w_a = ceil(D_a 2^s))    */
+    int32_t *status;       /* [1] CHAMFER_OK or CHAMFER_ENONFINITE              */
+    float *crude_D;        /* [n_A] D_a from CrudeNN                            */
+    int32_t *crude_nn;     /* [n_A] the b with D_a = d(a, b)                    */
+    int32_t *crude_scale;  /* [n_A] first colliding scale (L if none)           */
+    /* Host array of CHAMFER_STAGE_EVENTS hipEvent_t (as void*), or NULL.  When
+     * set, event i is recorded on the stream at stage boundary i: 0 start,
+     * 1 calibration and tables done, 2 B bucketed, 3 CrudeNN done (D_a),
+     * 4 weights and draws done, 5 exact pass over the draws done, 6 end.
+     * Stage 4->5 is a single kernel (the nearest-neighbour pass). */
+    void **stage_events;
+} chamfer_aux;
+
+#define CHAMFER_STAGE_EVENTS 7
+
+/*
+ * Workspace bytes sufficient for any entry point below called with these
+ * sizes and options (T = 0 means the default sample count; for
+ * chamfer_nn_min, n_A is n_x).  With eps outside (0, 1) the size covers only
+ * chamfer_exact and chamfer_nn_min.  Returns 0 for invalid sizes/options.
+ */
+size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric,
+                               double eps, int64_t T, const chamfer_opts *opts);
+
+/*
+ * Exact Chamfer distance by brute force (definition of CH in the
+ * introduction; the O(d n^2) baseline the paper compares against).
+ *   ch_out     [1] double: sum_a m_a, summed in double precision.
+ *   rowmin_out [n_A] float or NULL: m_a = min_b d(a, b) in float32.
+ *   rownn_out  [n_A] int32 or NULL: the b attaining m_a.
+ * With precision FP32 (the default), m_a and its arg-min are the canonical
+ * float32 values: accumulator over k ascending (l1: acc + |a_k - b_k|, l2:
+ * fma(t, t, acc) with t = a_k - b_k, then a correctly rounded square root),
+ * minimised over b with ties to the lower index.  BF16/FP8 (l2 only) rank
+ * candidates with low-precision tiles and re-rank the best ones in float32;
+ * their results carry a stated error instead.
+ * Errors: EINVAL if d < 1, metric not 1/2, n_A < 0, n_B < 1, or rows exceed
+ * the int32 index range; EWORKSPACE; EHIP.
+ */
+int chamfer_exact(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                  int32_t metric, double *ch_out, float *rowmin_out, int32_t *rownn_out,
+                  const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * CrudeNN (the CrudeNN figure): for every a in A an upper bound
+ * D_a >= min_b d(a, b).  L randomly shifted grids with sides
+ * r_i = 2^(e_top - (L-1-i)), i = 0 finest, where 2^e_top is the smallest
+ * power of two >= sum_k (max_k - min_k) over A u B.  l2 points are first
+ * mapped to l1 by a Gaussian embedding with k_e rows (appendix theorem on
+ * embedding l2 into l1).  D_a = d(a, b) for the lowest-index b sharing a's
+ * bucket at the first scale where any b does; if none does, b = 0.
+ *   D_out [n_A] float (canonical float32 distance), nn_out [n_A] int32,
+ *   scale_out [n_A] int32 or NULL (the scale, L when no scale collided).
+ * Randomness: Philox4x64-10 with key (seed, 0) and counter
+ * (c0, c1, purpose, 0); shifts and multipliers use purpose 1 with
+ * (c0, c1) = (coordinate, scale), the embedding purpose 2 with
+ * (row * d + column, 0).  The same seed gives the same output.
+ * Errors: as chamfer_exact, plus EINVAL unless 0 < eps < 1, or if opts
+ * request more than 64 scales or a bad embedding dimension.
+ */
+int crude_nn(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+             int32_t metric, double eps, uint64_t seed, float *D_out, int32_t *nn_out,
+             int32_t *scale_out, const chamfer_opts *opts, void *ws, size_t ws_bytes,
+             void *stream);
+
+/*
+ * Chamfer-Estimate (the Chamfer-Estimate figure): CrudeNN, then T i.i.d.
+ * draws x_l ~ D_a / D, then eta = (1/T) sum_l (D / D_{x_l}) min_b d(x_l, b).
+ * The distribution is held in 64-bit fixed point: s = 47 - ceil(log2 n_A) -
+ * e_max (max_a D_a in [2^(e_max-1), 2^e_max)), w_a = ceil(D_a 2^s), W = sum
+ * w_a, and eta uses W / w_{x_l}, which keeps it exactly unbiased.  Draws
+ * use Lemire's bounded integers on Philox4x64-10.  T = 0 selects
+ * T = ceil(ceil(log2 n_A) / eps^2).  eta = 0 if n_A = 0 or every D_a = 0.
+ *   eta_out [1] double (device).  aux: optional extra outputs (see above).
+ * Errors: as crude_nn, plus EINVAL if T < 0.
+ */
+int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                     int32_t metric, double eps, int64_t T, uint64_t seed, double *eta_out,
+                     chamfer_aux *aux, const chamfer_opts *opts, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * The bucket keys CrudeNN joins on, for inspection and testing (appendix
+ * lemma on the grid hash at every scale).  For scale i and point x with
+ * hashed coordinates y (l1: y_k = x_k - lo_k; l2: the embedding of x - lo):
+ *   cell_k = ceilf(ldexpf(y_k, -e_i) + z'_ik) + 0.0f,
+ *   key    = (sum_k bits(cell_k) * M_ik mod 2^64) >> 1.
+ *   keys_A_out [L][n_A] uint64, keys_B_out [L][n_B] uint64 (either may be
+ *   NULL), e_top_out [1] int32 or NULL.
+ * Errors: as crude_nn.
+ */
+int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                      int32_t metric, double eps, uint64_t seed, uint64_t *keys_A_out,
+                      uint64_t *keys_B_out, int32_t *e_top_out, const chamfer_opts *opts,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Exact nearest neighbour of selected rows (step 3 of the Chamfer-Estimate
+ * figure; also the inner loop of chamfer_exact).  Query q is row rows[q] of
+ * X (or row q when rows is NULL), q < n_x; B has n_B rows.
+ *   min_out [n_x] float, arg_out [n_x] int32 (either may be NULL): canonical
+ *   float32 min and arg-min as in chamfer_exact.
+ * Errors: as chamfer_exact (n_x < 0 is EINVAL).
+ */
+int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float *B,
+                   int64_t n_B, int32_t d, int32_t metric, float *min_out, int32_t *arg_out,
+                   const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* Host helpers (no device work). */
+int64_t chamfer_default_samples(int64_t n_A, double eps);            /* T default */
+int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps); /* L default */
+/* The scaled Gaussian embedding matrix, Z_jk / (sqrt(2/pi) k_e), [k_e][d], into
+ * host memory; the same matrix chamfer_estimate uses for `seed`. */
+int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, float *Z_host);
+const char *chamfer_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHAMFER_H */

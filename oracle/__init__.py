@@ -61,6 +61,7 @@ def lib():
     if not os.path.exists(_SO):
         build()
     L = ctypes.CDLL(_SO)
+    L.or_threads.restype = _INT
     L.or_philox4x64.argtypes = [_U64, _U64, _U64]
     L.or_grid_tables.argtypes = [ctypes.c_uint64, _INT, _INT, _F32, _U64]
     L.or_embedding.argtypes = [ctypes.c_uint64, _INT, _INT, _F32]
@@ -84,6 +85,11 @@ def lib():
     L.or_sample.argtypes = [ctypes.c_uint64, _U64, _I64, ctypes.c_uint64, _I64, _I32]
     _lib = L
     return L
+
+
+def threads() -> int:
+    """OpenMP threads of the parallel loops (exact nearest neighbours)."""
+    return int(lib().or_threads())
 
 
 def _f32(x):

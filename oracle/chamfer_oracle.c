@@ -24,12 +24,25 @@
  *     float inputs (which convert exactly), l2 by direct differences.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define OR_L1 1
 #define OR_L2 2
+
+/* Threads the OpenMP loops below use (1 without OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Purposes of the counter-based random streams (third counter word). */
 #define PURPOSE_GRID 1u

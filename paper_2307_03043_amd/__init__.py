@@ -1,0 +1,304 @@
+"""Python binding of libchamfer (gfx950 / MI355X).
+
+Thin ctypes marshalling over the C ABI declared in ``include/chamfer.h``:
+every function here has the name of a C entry point, turns torch tensors
+into device pointers, passes torch's current HIP stream and a cached
+workspace, and returns torch tensors.  All computation happens in the HIP
+kernels of ``libchamfer.so``; if the library is missing or was not built for
+this machine, every call raises.
+
+Point sets are float32 CUDA (HIP) tensors of shape [n, d], contiguous.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libchamfer.so")
+
+L1 = 1
+L2 = 2
+FP32, BF16, FP8 = 0, 1, 2
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "workspace missing or too small",
+           -3: "HIP launch or runtime error", -4: "input contains NaN or Inf"}
+
+
+class ChamferError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("n_scales", ctypes.c_int32), ("embed_dim", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_AUX_ARRAYS = ("sample_idx", "sample_min", "sample_nn", "D", "W", "s", "status",
+               "crude_D", "crude_nn", "crude_scale")
+STAGE_EVENTS = 7
+
+
+class Aux(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in _AUX_ARRAYS] + [("stage_events", ctypes.c_void_p)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_VP, _I64, _I32, _U64, _F64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                              ctypes.c_uint64, ctypes.c_double)
+_SIGS = {
+    "chamfer_workspace_bytes": (ctypes.c_size_t, [_I64, _I64, _I32, _I32, _F64, _I64, _VP]),
+    "chamfer_exact": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _VP, _VP, _VP, _VP, _VP,
+                                     ctypes.c_size_t, _VP]),
+    "crude_nn": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _U64, _VP, _VP, _VP,
+                                _VP, _VP, ctypes.c_size_t, _VP]),
+    "chamfer_estimate": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _I64, _U64,
+                                        _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "chamfer_hash_keys": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _U64, _VP,
+                                         _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "chamfer_nn_min": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _I32, _I32, _VP, _VP, _VP,
+                                      _VP, ctypes.c_size_t, _VP]),
+    "chamfer_default_samples": (ctypes.c_int64, [_I64, _F64]),
+    "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
+    "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
+    "chamfer_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libchamfer.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(SO_PATH):
+                raise RuntimeError(f"libchamfer.so not built ({SO_PATH}); run "
+                                   "`python -c 'import __graft_entry__ as g; g.build()'`")
+            L = ctypes.CDLL(SO_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise ChamferError(rc, where)
+
+
+def _opts(n_scales=0, embed_dim=0, precision=0) -> Opts:
+    return Opts(n_scales, embed_dim, precision, 0)
+
+
+# ----------------------------------------------------------- torch glue ---
+
+def _torch():
+    import torch
+    return torch
+
+
+def _points(x, name):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 [n, d] tensor")
+    return x
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+_ws_cache: dict = {}
+
+
+def _workspace(nbytes: int, device):
+    """A cached uint8 device buffer per (device, stream) of at least nbytes."""
+    torch = _torch()
+    key = (device.index if device.index is not None else torch.cuda.current_device(),
+           torch.cuda.current_stream(device).cuda_stream)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def release_workspaces():
+    _ws_cache.clear()
+
+
+# ------------------------------------------------------------- host API ---
+
+def chamfer_workspace_bytes(n_a, n_b, d, metric, eps=0.5, T=0, n_scales=0, embed_dim=0,
+                            precision=0) -> int:
+    o = _opts(n_scales, embed_dim, precision)
+    return int(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o)))
+
+
+def chamfer_default_samples(n_a: int, eps: float) -> int:
+    return int(lib().chamfer_default_samples(n_a, eps))
+
+
+def chamfer_default_scales(n_a: int, n_b: int, eps: float) -> int:
+    return int(lib().chamfer_default_scales(n_a, n_b, eps))
+
+
+def chamfer_embedding_matrix(seed: int, d: int, embed_dim: int = 32) -> np.ndarray:
+    z = np.zeros((embed_dim, d), np.float32)
+    _check(lib().chamfer_embedding_matrix(seed, d, embed_dim, z.ctypes.data),
+           "chamfer_embedding_matrix")
+    return z
+
+
+# ----------------------------------------------------------- device API ---
+
+def chamfer_exact(A, B, metric=L2, *, precision=0, rows_out=True):
+    """Exact CH(A, B) (double, [1] tensor) and the per-row min / arg-min."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    if B.shape[1] != d:
+        raise ValueError("A and B differ in dimension")
+    dev = A.device
+    o = _opts(precision=precision)
+    nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, 0.0, 0, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_exact")
+    ws = _workspace(nbytes, dev)
+    ch = torch.empty(1, dtype=torch.float64, device=dev)
+    rmin = torch.empty(n_a, dtype=torch.float32, device=dev) if rows_out else None
+    rnn = torch.empty(n_a, dtype=torch.int32, device=dev) if rows_out else None
+    _check(lib().chamfer_exact(_ptr(A), _ptr(B), n_a, n_b, d, metric, _ptr(ch), _ptr(rmin),
+                               _ptr(rnn), ctypes.byref(o), _ptr(ws), ws.numel(), _stream(dev)),
+           "chamfer_exact")
+    return ch, rmin, rnn
+
+
+def chamfer_nn_min(X, B, metric=L2, rows=None, *, precision=0):
+    """Nearest neighbour in B of rows of X (all rows, or X[rows])."""
+    torch = _torch()
+    X, B = _points(X, "X"), _points(B, "B")
+    d = X.shape[1]
+    if B.shape[1] != d:
+        raise ValueError("X and B differ in dimension")
+    if rows is not None:
+        if rows.dtype != torch.int32 or not rows.is_cuda or not rows.is_contiguous():
+            raise TypeError("rows must be a contiguous int32 CUDA tensor")
+        n_x = rows.numel()
+    else:
+        n_x = X.shape[0]
+    dev = X.device
+    o = _opts(precision=precision)
+    nbytes = lib().chamfer_workspace_bytes(n_x, B.shape[0], d, metric, 0.0, 0, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_nn_min")
+    ws = _workspace(nbytes, dev)
+    mn = torch.empty(n_x, dtype=torch.float32, device=dev)
+    arg = torch.empty(n_x, dtype=torch.int32, device=dev)
+    _check(lib().chamfer_nn_min(_ptr(X), _ptr(rows), n_x, _ptr(B), B.shape[0], d, metric,
+                                _ptr(mn), _ptr(arg), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                _stream(dev)), "chamfer_nn_min")
+    return mn, arg
+
+
+def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):
+    """CrudeNN: D_a (float32), candidate b, first colliding scale."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    dev = A.device
+    o = _opts(n_scales, embed_dim)
+    nbytes = lib().chamfer_workspace_bytes(n_a, B.shape[0], d, metric, eps, 0, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "crude_nn")
+    ws = _workspace(nbytes, dev)
+    D = torch.empty(n_a, dtype=torch.float32, device=dev)
+    nn = torch.empty(n_a, dtype=torch.int32, device=dev)
+    sc = torch.empty(n_a, dtype=torch.int32, device=dev)
+    _check(lib().crude_nn(_ptr(A), _ptr(B), n_a, B.shape[0], d, metric, eps, seed, _ptr(D),
+                          _ptr(nn), _ptr(sc), ctypes.byref(o), _ptr(ws), ws.numel(),
+                          _stream(dev)), "crude_nn")
+    return D, nn, sc
+
+
+def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0, precision=0,
+                     with_aux=True, stage_events=None):
+    """(1 +- eps) estimate of CH(A, B).  Returns a dict of device tensors:
+    eta [1] double, and with_aux: sample_idx/min/nn [T], D, W, s, status,
+    crude_D/nn/scale [n_A].  stage_events: optional ctypes array of
+    STAGE_EVENTS hipEvent_t handles recorded at the stage boundaries."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = A.device
+    o = _opts(n_scales, embed_dim, precision)
+    if T == 0 and 0.0 < eps < 1.0:
+        T = chamfer_default_samples(max(n_a, 1), eps)
+    nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_estimate")
+    ws = _workspace(nbytes, dev)
+    out = {"eta": torch.empty(1, dtype=torch.float64, device=dev), "T": T}
+    aux = Aux()
+    if with_aux:
+        out.update(
+            sample_idx=torch.empty(T, dtype=torch.int32, device=dev),
+            sample_min=torch.empty(T, dtype=torch.float32, device=dev),
+            sample_nn=torch.empty(T, dtype=torch.int32, device=dev),
+            D=torch.empty(1, dtype=torch.float64, device=dev),
+            W=torch.empty(1, dtype=torch.int64, device=dev),
+            s=torch.empty(1, dtype=torch.int32, device=dev),
+            status=torch.empty(1, dtype=torch.int32, device=dev),
+            crude_D=torch.empty(n_a, dtype=torch.float32, device=dev),
+            crude_nn=torch.empty(n_a, dtype=torch.int32, device=dev),
+            crude_scale=torch.empty(n_a, dtype=torch.int32, device=dev),
+        )
+        for f in _AUX_ARRAYS:
+            setattr(aux, f, out[f].data_ptr())
+    if stage_events is not None:
+        aux.stage_events = ctypes.cast(stage_events, ctypes.c_void_p)
+    _check(lib().chamfer_estimate(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, T, seed,
+                                  _ptr(out["eta"]), ctypes.byref(aux), ctypes.byref(o),
+                                  _ptr(ws), ws.numel(), _stream(dev)), "chamfer_estimate")
+    return out
+
+
+def chamfer_hash_keys(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):
+    """Bucket keys [L, n_A], [L, n_B] (int64 holding the uint64 keys < 2^63)
+    and e_top."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = A.device
+    o = _opts(n_scales, embed_dim)
+    L = n_scales if n_scales else chamfer_default_scales(n_a, n_b, eps)
+    nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, 0, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_hash_keys")
+    ws = _workspace(nbytes, dev)
+    ka = torch.empty((L, n_a), dtype=torch.int64, device=dev)
+    kb = torch.empty((L, n_b), dtype=torch.int64, device=dev)
+    et = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().chamfer_hash_keys(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, seed, _ptr(ka),
+                                   _ptr(kb), _ptr(et), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                   _stream(dev)), "chamfer_hash_keys")
+    return ka, kb, et

@@ -1,0 +1,389 @@
+// libchamfer C ABI: argument checks, workspace layout and the launch
+// sequence of each entry point.  All device work is enqueued on the
+// caller's stream; nothing here waits for the device.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+using namespace chamfer;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ceil_log2_u64(uint64_t n) {
+    int q = 0;
+    while (q < 63 && (1ull << q) < n) ++q;
+    return q;
+}
+
+int ceil_log2_dbl(double x) {
+    int e;
+    const double m = std::frexp(x, &e);
+    return m == 0.5 ? e - 1 : e;
+}
+
+// Host Philox4x64-10 (Salmon et al., SC 2011), for the embedding matrix.
+void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * c[0];
+        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * c[2];
+        const uint64_t x0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0;
+        const uint64_t x2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+        c[1] = (uint64_t)p1;
+        c[3] = (uint64_t)p0;
+        c[0] = x0;
+        c[2] = x2;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+}
+
+// Z_jk / (beta k_e), beta = sqrt(2/pi), Z_jk by Box-Muller from the words of
+// counter (j*d + k, 0, EMBED, 0): u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],
+// u2 = (w1 >> 11) 2^-53, g = sqrt(-2 ln u1) cos(2 pi u2).  Row-major [ke][d].
+void embedding_host(uint64_t seed, int d, int ke, float *Z) {
+    const double pi = 3.14159265358979323846;
+    const double two_pi = 2.0 * pi;
+    const double scale = 1.0 / (std::sqrt(2.0 / pi) * (double)ke);
+    for (int j = 0; j < ke; ++j)
+        for (int k = 0; k < d; ++k) {
+            uint64_t c[4] = {(uint64_t)j * (uint64_t)d + (uint64_t)k, 0, kPurposeEmbed, 0};
+            philox_host(c, seed, 0);
+            const double u1 = std::ldexp((double)((c[0] >> 11) + 1), -53);
+            const double u2 = std::ldexp((double)(c[1] >> 11), -53);
+            const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
+            Z[(size_t)j * d + k] = (float)(g * scale);
+        }
+}
+
+bool valid_ke(int ke) { return ke == 8 || ke == 16 || ke == 32 || ke == 64; }
+
+int default_scales(int64_t nA, int64_t nB, double eps) {
+    int64_t n = nA > nB ? nA : nB;
+    if (n < 1) n = 1;
+    int L = ceil_log2_dbl((double)n / eps);
+    if (L < 1) L = 1;
+    if (L > kMaxScales) L = kMaxScales;
+    return L;
+}
+
+int64_t default_samples(int64_t nA, double eps) {
+    const int q = ceil_log2_u64((uint64_t)(nA < 1 ? 1 : nA));
+    const int64_t T = (int64_t)std::ceil((double)q / (eps * eps));
+    return T < 1 ? 1 : T;
+}
+
+// Validate and lay out the workspace.  hashing: the entry point runs
+// CrudeNN (needs eps and the table regions); otherwise only the regions of
+// the nearest-neighbour pass are laid out, so its total never exceeds the
+// hashing total for the same sizes.
+int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, double eps,
+              int64_t T, const chamfer_opts *opts, bool hashing) {
+    const bool need_eps = hashing;
+    std::memset(&pl, 0, sizeof(pl));
+    if (d < 1 || (metric != CHAMFER_L1 && metric != CHAMFER_L2)) return CHAMFER_EINVAL;
+    if (nA < 0 || nB < 1 || nA > INT32_MAX || nB > INT32_MAX || T < 0 || T > INT32_MAX)
+        return CHAMFER_EINVAL;
+    if (need_eps && !(eps > 0.0 && eps < 1.0)) return CHAMFER_EINVAL;
+    chamfer_opts o{};
+    if (opts) o = *opts;
+    if (o.n_scales < 0 || o.n_scales > kMaxScales || o.reserved != 0) return CHAMFER_EINVAL;
+    if (o.precision < CHAMFER_FP32 || o.precision > CHAMFER_FP8) return CHAMFER_EINVAL;
+    const int ke = o.embed_dim ? o.embed_dim : 32;
+    if (!valid_ke(ke)) return CHAMFER_EINVAL;
+    const double e = (eps > 0.0 && eps < 1.0) ? eps : 0.5;
+    pl.nA = nA;
+    pl.nB = nB;
+    pl.d = d;
+    pl.metric = metric;
+    pl.precision = o.precision;
+    pl.L = o.n_scales ? o.n_scales : default_scales(nA, nB, e);
+    pl.ke = ke;
+    pl.kh = metric == CHAMFER_L1 ? d : ke;
+    pl.T = T ? T : default_samples(nA, e);
+    pl.q = ceil_log2_u64((uint64_t)(nA < 1 ? 1 : nA));
+    int lc = ceil_log2_u64((uint64_t)(2 * nB));
+    if (lc < 6) lc = 6;
+    pl.log2cap = lc;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    const int64_t nrow = (hashing && pl.T > nA) ? pl.T : nA;
+    const size_t h = hashing ? 1 : 0;
+    pl.off_params = take(sizeof(DevParams));
+    pl.off_lohi = take(2 * (size_t)d * sizeof(uint32_t));
+    pl.off_zfrac = take(h * pl.L * pl.kh * sizeof(float));
+    pl.off_mult = take(h * pl.L * pl.kh * sizeof(uint64_t));
+    pl.off_embed = take(metric == CHAMFER_L2 ? h * d * ke * sizeof(float) : 0);
+    pl.off_tables = take(h * pl.L * ((size_t)1 << lc) * sizeof(Bucket));
+    pl.off_D = take(h * nA * sizeof(float));
+    pl.off_nn = take(h * nA * sizeof(int32_t));
+    pl.off_scale = take(h * nA * sizeof(int32_t));
+    pl.off_blocksums = take(h * ((nA + kScanBlock - 1) / kScanBlock + 1) * 8);
+    pl.off_P = take(h * nA * sizeof(uint64_t));
+    pl.off_idx = take(h * pl.T * sizeof(int32_t));
+    pl.off_best = take((size_t)nrow * sizeof(uint64_t));
+    pl.off_partial = take((size_t)(nn_finalize_blocks(nrow) + 1) * sizeof(double));
+    pl.off_fallback = take(0);
+    pl.off_lowp = take(0);
+    pl.off_lowpnorm = take(0);
+    pl.total = off;
+    return CHAMFER_OK;
+}
+
+template <class T>
+T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+#define CH_TRY(expr)                                    \
+    do {                                                \
+        if ((expr) != hipSuccess) return CHAMFER_EHIP;  \
+    } while (0)
+
+int check_ws(const Plan &pl, void *ws, size_t ws_bytes) {
+    if (ws == nullptr || ws_bytes < pl.total) return CHAMFER_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % 16 != 0) return CHAMFER_EINVAL;
+    return CHAMFER_OK;
+}
+
+// Calibration, tables and (l2) the embedding upload: common prefix of the
+// hashing entry points.
+int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed, void *ws,
+                  hipStream_t st) {
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
+    CH_TRY(launch_init_params(p, lohi, pl.d, st));
+    if (pl.metric == CHAMFER_L2) {
+        // The embedding matrix is drawn on the host (it needs log and cos in
+        // double precision) and uploaded transposed, [d][ke].
+        thread_local std::vector<float> z, zt;
+        z.resize((size_t)pl.ke * pl.d);
+        zt.resize((size_t)pl.ke * pl.d);
+        embedding_host(seed, pl.d, pl.ke, z.data());
+        for (int j = 0; j < pl.ke; ++j)
+            for (int k = 0; k < pl.d; ++k) zt[(size_t)k * pl.ke + j] = z[(size_t)j * pl.d + k];
+        CH_TRY(hipMemcpyAsync(at<float>(ws, pl.off_embed), zt.data(), zt.size() * sizeof(float),
+                              hipMemcpyHostToDevice, st));
+    }
+    CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, at<float>(ws, pl.off_zfrac),
+                              at<uint64_t>(ws, pl.off_mult), st));
+    CH_TRY(launch_minmax(A, pl.nA, pl.d, lohi, p, st));
+    CH_TRY(launch_minmax(B, pl.nB, pl.d, lohi, p, st));
+    CH_TRY(launch_calib_final(lohi, pl.d, p, st));
+    return CHAMFER_OK;
+}
+
+// Record stage event i if the caller asked for stage events.
+hipError_t mark(void **ev, int i, hipStream_t st) {
+    if (ev == nullptr || ev[i] == nullptr) return hipSuccess;
+    return hipEventRecord(static_cast<hipEvent_t>(ev[i]), st);
+}
+
+int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
+               int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr) {
+    CH_TRY(mark(ev, 0, st));
+    int rc = hash_prologue(pl, A, B, seed, ws, st);
+    if (rc) return rc;
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    Bucket *tables = at<Bucket>(ws, pl.off_tables);
+    CH_TRY(launch_table_fill(tables, (size_t)pl.L << pl.log2cap, st));
+    CH_TRY(mark(ev, 1, st));
+    const uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
+    const float *emb = at<float>(ws, pl.off_embed);
+    const float *zf = at<float>(ws, pl.off_zfrac);
+    const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
+    CH_TRY(launch_hash(0, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
+                       tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr, p, st));
+    CH_TRY(mark(ev, 2, st));
+    CH_TRY(launch_hash(1, A, pl.nA, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
+                       tables, pl.log2cap, nullptr, D, nn, scale, p, st));
+    CH_TRY(mark(ev, 3, st));
+    return CHAMFER_OK;
+}
+
+__global__ void k_store_zero(double *out, int32_t *status) {
+    if (threadIdx.x == 0) {
+        if (out) *out = 0.0;
+        if (status) *status = CHAMFER_OK;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,
+                               int64_t T, const chamfer_opts *opts) {
+    Plan pl;
+    // Without a valid eps only the non-hashing entry points can run.
+    const bool hashing = eps > 0.0 && eps < 1.0;
+    if (make_plan(pl, n_A, n_B, d, metric, eps, T, opts, hashing) != CHAMFER_OK) return 0;
+    return pl.total;
+}
+
+int chamfer_exact(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                  int32_t metric, double *ch_out, float *rowmin_out, int32_t *rownn_out,
+                  const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    Plan pl;
+    int rc = make_plan(pl, n_A, n_B, d, metric, 0.5, 0, opts, false);
+    if (rc) return rc;
+    if (ch_out == nullptr || (A == nullptr && n_A > 0) || B == nullptr) return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_A == 0) {
+        k_store_zero<<<1, 64, 0, st>>>(ch_out, nullptr);
+        return hipGetLastError() == hipSuccess ? CHAMFER_OK : CHAMFER_EHIP;
+    }
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
+    auto *best = at<unsigned long long>(ws, pl.off_best);
+    double *partial = at<double>(ws, pl.off_partial);
+    CH_TRY(launch_init_params(p, lohi, d, st));
+    CH_TRY(launch_minmax(A, n_A, d, lohi, p, st));
+    CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
+    CH_TRY(launch_calib_final(lohi, d, p, st));
+    CH_TRY(launch_fill_u64(best, n_A, ~0ull, st));
+    CH_TRY(launch_nnmin(A, nullptr, n_A, B, n_B, d, metric, best, p, st));
+    CH_TRY(launch_nn_finalize(best, n_A, metric, rowmin_out, rownn_out, partial, p, st));
+    CH_TRY(launch_sum_final(partial, nn_finalize_blocks(n_A), p, ch_out, st));
+    return CHAMFER_OK;
+}
+
+int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float *B,
+                   int64_t n_B, int32_t d, int32_t metric, float *min_out, int32_t *arg_out,
+                   const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    Plan pl;
+    int rc = make_plan(pl, n_x, n_B, d, metric, 0.5, 0, opts, false);
+    if (rc) return rc;
+    if ((X == nullptr && n_x > 0) || B == nullptr) return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    if (n_x == 0) return CHAMFER_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    auto *best = at<unsigned long long>(ws, pl.off_best);
+    CH_TRY(launch_init_params(p, nullptr, d, st));
+    CH_TRY(launch_fill_u64(best, n_x, ~0ull, st));
+    CH_TRY(launch_nnmin(X, rows, n_x, B, n_B, d, metric, best, p, st));
+    CH_TRY(launch_nn_finalize(best, n_x, metric, min_out, arg_out, nullptr, p, st));
+    return CHAMFER_OK;
+}
+
+int crude_nn(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+             int32_t metric, double eps, uint64_t seed, float *D_out, int32_t *nn_out,
+             int32_t *scale_out, const chamfer_opts *opts, void *ws, size_t ws_bytes,
+             void *stream) {
+    Plan pl;
+    int rc = make_plan(pl, n_A, n_B, d, metric, eps, 0, opts, true);
+    if (rc) return rc;
+    if ((A == nullptr && n_A > 0) || B == nullptr ||
+        (n_A > 0 && (D_out == nullptr || nn_out == nullptr)))
+        return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    if (n_A == 0) return CHAMFER_OK;
+    return crude_core(pl, A, B, seed, D_out, nn_out, scale_out, ws,
+                      static_cast<hipStream_t>(stream));
+}
+
+int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                     int32_t metric, double eps, int64_t T, uint64_t seed, double *eta_out,
+                     chamfer_aux *aux, const chamfer_opts *opts, void *ws, size_t ws_bytes,
+                     void *stream) {
+    Plan pl;
+    int rc = make_plan(pl, n_A, n_B, d, metric, eps, T, opts, true);
+    if (rc) return rc;
+    if ((A == nullptr && n_A > 0) || B == nullptr || eta_out == nullptr) return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    chamfer_aux ax{};
+    if (aux) ax = *aux;
+    if (n_A == 0) {
+        k_store_zero<<<1, 64, 0, st>>>(eta_out, ax.status);
+        return hipGetLastError() == hipSuccess ? CHAMFER_OK : CHAMFER_EHIP;
+    }
+    float *D = ax.crude_D ? ax.crude_D : at<float>(ws, pl.off_D);
+    int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
+    int32_t *scale = ax.crude_scale;
+    void **ev = ax.stage_events;
+    if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev))) return rc;
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    uint64_t *P = at<uint64_t>(ws, pl.off_P);
+    int32_t *idx = at<int32_t>(ws, pl.off_idx);
+    auto *best = at<unsigned long long>(ws, pl.off_best);
+    CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
+    CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
+    CH_TRY(mark(ev, 4, st));
+    CH_TRY(launch_nnmin(A, idx, pl.T, B, n_B, d, metric, best, p, st));
+    CH_TRY(mark(ev, 5, st));
+    CH_TRY(launch_estimate_final(best, idx, D, pl.T, metric, p, eta_out, ax, st));
+    CH_TRY(mark(ev, 6, st));
+    return CHAMFER_OK;
+}
+
+int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                      int32_t metric, double eps, uint64_t seed, uint64_t *keys_A_out,
+                      uint64_t *keys_B_out, int32_t *e_top_out, const chamfer_opts *opts,
+                      void *ws, size_t ws_bytes, void *stream) {
+    Plan pl;
+    int rc = make_plan(pl, n_A, n_B, d, metric, eps, 0, opts, true);
+    if (rc) return rc;
+    if ((A == nullptr && n_A > 0) || B == nullptr) return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = hash_prologue(pl, A, B, seed, ws, st))) return rc;
+    DevParams *p = at<DevParams>(ws, pl.off_params);
+    const uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
+    const float *emb = at<float>(ws, pl.off_embed);
+    const float *zf = at<float>(ws, pl.off_zfrac);
+    const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
+    if (keys_A_out)
+        CH_TRY(launch_hash(2, A, n_A, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
+                           pl.log2cap, keys_A_out, nullptr, nullptr, nullptr, p, st));
+    if (keys_B_out)
+        CH_TRY(launch_hash(2, B, n_B, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
+                           pl.log2cap, keys_B_out, nullptr, nullptr, nullptr, p, st));
+    if (e_top_out) {
+        // e_top lives in the device parameter block.
+        CH_TRY(hipMemcpyAsync(e_top_out, &p->e_top, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              st));
+    }
+    return CHAMFER_OK;
+}
+
+int64_t chamfer_default_samples(int64_t n_A, double eps) {
+    if (!(eps > 0.0 && eps < 1.0)) return -1;
+    return default_samples(n_A, eps);
+}
+
+int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps) {
+    if (!(eps > 0.0 && eps < 1.0)) return -1;
+    return default_scales(n_A, n_B, eps);
+}
+
+int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, float *Z_host) {
+    if (d < 1 || !valid_ke(embed_dim) || Z_host == nullptr) return CHAMFER_EINVAL;
+    embedding_host(seed, d, embed_dim, Z_host);
+    return CHAMFER_OK;
+}
+
+const char *chamfer_strerror(int status) {
+    switch (status) {
+        case CHAMFER_OK: return "ok";
+        case CHAMFER_EINVAL: return "invalid argument";
+        case CHAMFER_EWORKSPACE: return "workspace missing or too small";
+        case CHAMFER_EHIP: return "HIP launch or runtime error";
+        case CHAMFER_ENONFINITE: return "input contains NaN or Inf";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,446 @@
+// CrudeNN on the GPU (the CrudeNN figure and the appendix lemma on the grid
+// hash at every scale): scale calibration, per-scale shifts and key
+// multipliers, the open-addressing bucket tables of B, and the probe of A
+// that yields the first colliding scale, the candidate b and D_a.
+//
+// Layout: one wavefront (64 lanes) per tile of 64 consecutive points.  The
+// tile's hashed coordinates are staged in LDS with an odd row stride, so the
+// per-lane reads of row p, coordinate k hit 64 distinct banks.  Shifts and
+// multipliers are indexed only by the (wave-uniform) scale and coordinate,
+// so they are read through the scalar cache.  Keys are never written to HBM
+// on the estimator path: B's keys go straight into the tables and A's keys
+// are recomputed scale by scale until the first hit.
+#include <climits>
+
+#include "internal.h"
+
+namespace chamfer {
+
+// ------------------------------------------------------------- parameters
+
+__global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        p->status = CHAMFER_OK;
+        p->e_top = 0;
+        p->s = 0;
+        p->all_zero = 0;
+        p->max_d_bits = 0;
+        p->nonfinite = 0;
+        p->W = 0;
+        p->S = 0.0;
+    }
+    if (lohi != nullptr)
+        for (int k = t; k < d; k += gridDim.x * blockDim.x) {
+            lohi[k] = 0xffffffffu;  // running min (ordered encoding)
+            lohi[d + k] = 0u;       // running max
+        }
+}
+
+hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t st) {
+    const int blocks = lohi ? (d + 255) / 256 : 1;
+    k_init_params<<<blocks, 256, 0, st>>>(p, lohi, d);
+    return hipGetLastError();
+}
+
+// Shifts z'_ik (cell units, 24-bit lattice in [0,1)) and odd multipliers
+// M_ik from Philox4x64-10, counter (k, i, GRID, 0), key (seed, 0).
+__global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L * kh) return;
+    const int i = t / kh, k = t - i * kh;
+    uint64_t c[4] = {(uint64_t)k, (uint64_t)i, (uint64_t)kPurposeGrid, 0};
+    philox4x64_10(c, seed, 0);
+    zfrac[t] = ldexpf((float)(uint32_t)(c[0] >> 40), -24);
+    mult[t] = c[1] | 1ull;
+}
+
+hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
+                              hipStream_t st) {
+    const int n = L * kh;
+    k_grid_tables<<<(n + 255) / 256, 256, 0, st>>>(seed, L, kh, zfrac, mult);
+    return hipGetLastError();
+}
+
+// Per-coordinate min and max over a point set, and a non-finite flag.  The
+// flat element e has coordinate e mod d; the grid stride is a multiple of d,
+// so every thread keeps one coordinate.  Min/max use integer atomics on an
+// order-preserving encoding, whose result does not depend on their order.
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int64_t total,
+                                                int d, int64_t stride, uint32_t *lohi,
+                                                DevParams *p) {
+    extern __shared__ uint32_t sm[];
+    const bool use_lds = d <= 2048;
+    if (use_lds) {
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            sm[i] = 0xffffffffu;
+            sm[d + i] = 0u;
+        }
+        __syncthreads();
+    }
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    int bad = 0;
+    if (g < stride) {
+        for (int64_t e = g; e < total; e += stride) {
+            const float v = X[e];
+            bad |= !isfinite(v);
+            const uint32_t o = float_to_ordered(v);
+            lo = min(lo, o);
+            hi = max(hi, o);
+        }
+        const int k = (int)(g % d);
+        if (use_lds) {
+            atomicMin(&sm[k], lo);
+            atomicMax(&sm[d + k], hi);
+        } else {
+            atomicMin(&lohi[k], lo);
+            atomicMax(&lohi[d + k], hi);
+        }
+    }
+    if (bad) atomicOr(&p->nonfinite, 1u);
+    if (use_lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            if (sm[i] != 0xffffffffu) atomicMin(&lohi[i], sm[i]);
+            if (sm[d + i] != 0u) atomicMax(&lohi[d + i], sm[d + i]);
+        }
+    }
+}
+
+hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
+                         hipStream_t st) {
+    const int64_t total = n * (int64_t)d;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    const int64_t min_blocks = (d + 255) / 256;
+    if (blocks < min_blocks) blocks = min_blocks;
+    const int64_t stride = (blocks * 256 / d) * d;
+    const size_t lds = d <= 2048 ? 2 * (size_t)d * sizeof(uint32_t) : 0;
+    k_minmax<<<(unsigned)blocks, 256, lds, st>>>(X, total, d, stride, lohi, p);
+    return hipGetLastError();
+}
+
+// S = sum_k (hi_k - lo_k) in double, k ascending; e_top = ceil(log2 S).
+__global__ void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double S = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double hi = (double)ordered_to_float(lohi[d + k]);
+        const double lo = (double)ordered_to_float(lohi[k]);
+        S = S + (hi - lo);
+    }
+    p->S = S;
+    p->e_top = S > 0.0 ? ceil_log2_pos(S) : 0;
+    if (p->nonfinite) p->status = CHAMFER_ENONFINITE;
+}
+
+hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st) {
+    k_calib_final<<<1, 64, 0, st>>>(lohi, d, p);
+    return hipGetLastError();
+}
+
+__global__ void k_table_fill(Bucket *t, size_t count) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        Bucket b;
+        b.key = kEmptyKey;
+        b.val = INT_MAX;
+        b.pad = 0;
+        t[i] = b;
+    }
+}
+
+hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_table_fill<<<(unsigned)blocks, 256, 0, st>>>(tables, count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ keys
+
+// Key of hashed coordinates y (stride 1) at the scale of side 2^e:
+// cell_k = ceil(y_k 2^-e + z'_k) + 0 (the +0 turns -0 into +0, so equal
+// cells have equal bits), key = (sum_k bits(cell_k) M_k mod 2^64) >> 1.
+__device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh, int e,
+                                                         const float *__restrict__ zf,
+                                                         const uint64_t *__restrict__ M) {
+    unsigned long long acc = 0;
+    for (int k = 0; k < kh; ++k) {
+        const float q = ldexpf(y[k], -e) + zf[k];
+        const float c = ceilf(q) + 0.0f;
+        acc += (unsigned long long)__float_as_uint(c) * M[k];
+    }
+    return acc >> 1;
+}
+
+// Same, with y_k = x_k - lo_k read from HBM (l1 with d too large for LDS).
+__device__ __forceinline__ unsigned long long bucket_key_global(
+    const float *__restrict__ x, const uint32_t *__restrict__ lohi, int kh, int e,
+    const float *__restrict__ zf, const uint64_t *__restrict__ M) {
+    unsigned long long acc = 0;
+    for (int k = 0; k < kh; ++k) {
+        const float y = x[k] - ordered_to_float(lohi[k]);
+        const float q = ldexpf(y, -e) + zf[k];
+        const float c = ceilf(q) + 0.0f;
+        acc += (unsigned long long)__float_as_uint(c) * M[k];
+    }
+    return acc >> 1;
+}
+
+// Home slot: the top bits of the 63-bit key (the best-mixed bits of a
+// multiply-accumulate hash).
+__device__ __forceinline__ uint64_t home_slot(unsigned long long key, int log2cap) {
+    return (uint64_t)(key >> (63 - log2cap));
+}
+
+// Insert (key -> b) keeping the lowest b per key.  Linear probing; a slot's
+// key changes only from EMPTY, by CAS, so each key owns exactly one slot.
+__device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, int b) {
+    const uint64_t mask = (1ull << log2cap) - 1;
+    uint64_t slot = home_slot(key, log2cap);
+    for (;;) {
+        Bucket *e = tab + slot;
+        unsigned long long cur =
+            __hip_atomic_load(&e->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kEmptyKey) {
+            const unsigned long long prev = atomicCAS(&e->key, kEmptyKey, key);
+            if (prev == kEmptyKey || prev == key) {
+                atomicMin(&e->val, b);
+                return;
+            }
+            cur = prev;
+        }
+        if (cur == key) {
+            if (__hip_atomic_load(&e->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > b)
+                atomicMin(&e->val, b);
+            return;
+        }
+        slot = (slot + 1) & mask;
+    }
+}
+
+// Lowest b stored under key, or -1.  Runs in a later kernel than every insert.
+__device__ __forceinline__ int table_probe(const Bucket *__restrict__ tab, int log2cap,
+                                           unsigned long long key) {
+    const uint64_t mask = (1ull << log2cap) - 1;
+    uint64_t slot = home_slot(key, log2cap);
+    for (;;) {
+        const Bucket e = tab[slot];
+        if (e.key == key) return e.val;
+        if (e.key == kEmptyKey) return -1;
+        slot = (slot + 1) & mask;
+    }
+}
+
+// Canonical float32 distance: k ascending, l1 acc + |t|, l2 fma(t, t, acc),
+// then a correctly rounded square root.
+template <int METRIC>
+__device__ __forceinline__ float dist32(const float *__restrict__ a, const float *__restrict__ b,
+                                        int d) {
+    float acc = 0.0f;
+    if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+        const float4 *a4 = reinterpret_cast<const float4 *>(a);
+        const float4 *b4 = reinterpret_cast<const float4 *>(b);
+        for (int k = 0; k < (d >> 2); ++k) {
+            const float4 u = a4[k], v = b4[k];
+            const float t0 = u.x - v.x, t1 = u.y - v.y, t2 = u.z - v.z, t3 = u.w - v.w;
+            if (METRIC == CHAMFER_L1) {
+                acc = acc + fabsf(t0);
+                acc = acc + fabsf(t1);
+                acc = acc + fabsf(t2);
+                acc = acc + fabsf(t3);
+            } else {
+                acc = fmaf(t0, t0, acc);
+                acc = fmaf(t1, t1, acc);
+                acc = fmaf(t2, t2, acc);
+                acc = fmaf(t3, t3, acc);
+            }
+        }
+    } else {
+        for (int k = 0; k < d; ++k) {
+            const float t = a[k] - b[k];
+            if (METRIC == CHAMFER_L1)
+                acc = acc + fabsf(t);
+            else
+                acc = fmaf(t, t, acc);
+        }
+    }
+    return METRIC == CHAMFER_L1 ? acc : sqrtf(acc);
+}
+
+constexpr int kTile = 64;      // points per workgroup (one wavefront)
+constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
+
+// MODE 0: insert the tile's points (B) into the L tables.
+// MODE 1: probe (A): first scale with a hit, candidate, D_a; max D_a.
+// MODE 2: write keys[L][n].
+// KE: embedding dimension for l2 (0 for l1).  YG: l1 coordinates from HBM.
+template <int METRIC, int MODE, int KE, bool YG>
+__global__ __launch_bounds__(kTile) void k_hash(
+    const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
+    const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
+    const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
+    int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
+    int32_t *scale_out, DevParams *p) {
+    extern __shared__ float smem[];
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kTile;
+    const int np = (int)min<int64_t>(kTile, n - p0);
+    const int64_t pt = p0 + t;
+    const bool active = t < np;
+
+    if (p->status != CHAMFER_OK) {
+        if (MODE == 1 && active) {
+            D_out[pt] = __builtin_nanf("");
+            nn_out[pt] = -1;
+            if (scale_out) scale_out[pt] = -1;
+        }
+        return;
+    }
+    const int kh = METRIC == CHAMFER_L1 ? d : KE;
+    const int khp = kh | 1;  // odd row stride
+    float *ys = smem;        // [kTile][khp]
+    const int e_top = p->e_top;
+
+    if (METRIC == CHAMFER_L1) {
+        if (!YG) {
+            for (int e = t; e < np * d; e += kTile) {
+                const int r = e / d, k = e - r * d;
+                ys[r * khp + k] = X[(p0 + r) * d + k] - ordered_to_float(lohi[k]);
+            }
+            __syncthreads();
+        }
+    } else {
+        // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k.
+        float *xs = smem + kTile * khp;  // [kTile][kEmbedChunk + 1]
+        float y[KE > 0 ? KE : 1];
+#pragma unroll
+        for (int j = 0; j < KE; ++j) y[j] = 0.0f;
+        for (int k0 = 0; k0 < d; k0 += kEmbedChunk) {
+            const int kc = min(kEmbedChunk, d - k0);
+            __syncthreads();
+            for (int e = t; e < np * kc; e += kTile) {
+                const int r = e / kc, k = e - r * kc;
+                xs[r * (kEmbedChunk + 1) + k] =
+                    X[(p0 + r) * d + k0 + k] - ordered_to_float(lohi[k0 + k]);
+            }
+            __syncthreads();
+            if (active) {
+                for (int k = 0; k < kc; ++k) {
+                    const float xv = xs[t * (kEmbedChunk + 1) + k];
+                    const float *zc = embed_t + (size_t)(k0 + k) * KE;
+#pragma unroll
+                    for (int j = 0; j < KE; ++j) y[j] = fmaf(zc[j], xv, y[j]);
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < KE; ++j) ys[t * khp + j] = y[j];
+        }
+        __syncthreads();
+    }
+
+    const float *yrow = ys + t * khp;
+    const float *xrow = X + pt * d;
+    auto key_at = [&](int i) -> unsigned long long {
+        const int e = e_top - (L - 1 - i);
+        if (METRIC == CHAMFER_L1 && YG)
+            return bucket_key_global(xrow, lohi, kh, e, zfrac + (size_t)i * kh,
+                                     mult + (size_t)i * kh);
+        return bucket_key(yrow, kh, e, zfrac + (size_t)i * kh, mult + (size_t)i * kh);
+    };
+
+    if (MODE == 0) {
+        if (active)
+            for (int i = 0; i < L; ++i)
+                table_insert(tables + ((size_t)i << log2cap), log2cap, key_at(i), (int)pt);
+        return;
+    }
+    if (MODE == 2) {
+        if (active)
+            for (int i = 0; i < L; ++i) keys_out[(size_t)i * n + pt] = key_at(i);
+        return;
+    }
+    // MODE 1: probe.
+    float D = 0.0f;
+    if (active) {
+        int found = L, cand = 0;
+        for (int i = 0; i < L; ++i) {
+            const int v = table_probe(tables + ((size_t)i << log2cap), log2cap, key_at(i));
+            if (v >= 0) {
+                found = i;
+                cand = v;
+                break;
+            }
+        }
+        D = dist32<METRIC>(xrow, Bpts + (size_t)cand * d, d);
+        D_out[pt] = D;
+        nn_out[pt] = cand;
+        if (scale_out) scale_out[pt] = found;
+    }
+    // wave max of D (all lanes take part; D >= 0 so bits order as floats)
+    uint32_t m = __float_as_uint(D);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if (t == 0) atomicMax(&p->max_d_bits, m);
+}
+
+template <int METRIC, int KE, bool YG>
+static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts, int d,
+                                int L, const uint32_t *lohi, const float *embed_t,
+                                const float *zfrac, const uint64_t *mult, Bucket *tables,
+                                int log2cap, uint64_t *keys_out, float *D_out, int32_t *nn_out,
+                                int32_t *scale_out, DevParams *p, hipStream_t st) {
+    const int kh = METRIC == CHAMFER_L1 ? d : KE;
+    size_t lds = 0;
+    if (METRIC == CHAMFER_L1) {
+        if (!YG) lds = (size_t)kTile * (kh | 1) * sizeof(float);
+    } else {
+        lds = (size_t)kTile * ((kh | 1) + kEmbedChunk + 1) * sizeof(float);
+    }
+    const unsigned blocks = (unsigned)((n + kTile - 1) / kTile);
+    auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
+    if (mode == 0)
+        k_hash<METRIC, 0, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
+                                                              zfrac, mult, tables, log2cap, ko,
+                                                              D_out, nn_out, scale_out, p);
+    else if (mode == 1)
+        k_hash<METRIC, 1, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
+                                                              zfrac, mult, tables, log2cap, ko,
+                                                              D_out, nn_out, scale_out, p);
+    else
+        k_hash<METRIC, 2, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
+                                                              zfrac, mult, tables, log2cap, ko,
+                                                              D_out, nn_out, scale_out, p);
+    return hipGetLastError();
+}
+
+// Largest l1 dimension whose tile fits the default 64 KiB of dynamic LDS.
+constexpr int kMaxLdsL1Dim = (65536 / (kTile * 4)) - 2;
+
+hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
+                       int d, int metric, int L, int ke, const uint32_t *lohi,
+                       const float *embed_t, const float *zfrac, const uint64_t *mult,
+                       Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
+                       int32_t *nn_out, int32_t *scale_out, DevParams *p, hipStream_t st) {
+    (void)nB;
+    if (n <= 0) return hipSuccess;
+#define CH_ARGS mode, X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, keys_out, \
+                D_out, nn_out, scale_out, p, st
+    if (metric == CHAMFER_L1) {
+        if (d <= kMaxLdsL1Dim) return launch_hash_t<CHAMFER_L1, 0, false>(CH_ARGS);
+        return launch_hash_t<CHAMFER_L1, 0, true>(CH_ARGS);
+    }
+    switch (ke) {
+        case 8: return launch_hash_t<CHAMFER_L2, 8, false>(CH_ARGS);
+        case 16: return launch_hash_t<CHAMFER_L2, 16, false>(CH_ARGS);
+        case 32: return launch_hash_t<CHAMFER_L2, 32, false>(CH_ARGS);
+        case 64: return launch_hash_t<CHAMFER_L2, 64, false>(CH_ARGS);
+        default: return hipErrorInvalidValue;
+    }
+#undef CH_ARGS
+}
+
+}  // namespace chamfer

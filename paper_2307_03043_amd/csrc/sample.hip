@@ -1,0 +1,230 @@
+// Importance sampling (the Chamfer-Estimate figure, steps 1-4) on the GPU:
+// fixed-point weights w_a = ceil(D_a 2^s), their inclusive prefix P and
+// total W (two-level scan), T i.i.d. draws u ~ U[0, W) by Lemire's bounded
+// integers on Philox4x64-10 with the sample index min{a : P_a > u}, and the
+// final reweighted mean eta = (1/T) sum_l (W / w_{x_l}) m_l in double.
+//
+// Everything is integer arithmetic except the final sum, which is a fixed
+// order tree in double: results do not depend on scheduling.
+#include <cmath>
+
+#include "internal.h"
+
+namespace chamfer {
+
+__device__ __forceinline__ unsigned long long weight_of(float D, int s) {
+    return (unsigned long long)ceil(ldexp((double)D, s));
+}
+
+// s = 47 - q - e_max with max D in [2^(e_max - 1), 2^e_max).
+__device__ __forceinline__ int fixed_point_exponent(uint32_t max_d_bits, int q) {
+    int e;
+    frexp((double)__uint_as_float(max_d_bits), &e);
+    return 47 - q - e;
+}
+
+// Block-wide inclusive scan of one uint64 per thread (Hillis-Steele in LDS).
+template <int NT>
+__device__ unsigned long long block_inclusive_scan(unsigned long long v,
+                                                   unsigned long long *buf) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        const unsigned long long add = t >= off ? buf[t - off] : 0ull;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    const unsigned long long r = buf[t];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_weight_blocksum(
+    const float *__restrict__ D, int64_t nA, int q, unsigned long long *blocksums,
+    const DevParams *p) {
+    __shared__ unsigned long long buf[kScanThreads];
+    if (p->status != CHAMFER_OK) return;
+    const uint32_t mb = p->max_d_bits;
+    unsigned long long sum = 0;
+    if (__uint_as_float(mb) > 0.0f) {
+        const int s = fixed_point_exponent(mb, q);
+        const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j)
+            if (base + j < nA) sum += weight_of(D[base + j], s);
+    }
+    const unsigned long long inc = block_inclusive_scan<kScanThreads>(sum, buf);
+    if (threadIdx.x == kScanThreads - 1) blocksums[blockIdx.x] = inc;
+}
+
+// Exclusive scan of the block sums in place; W = total.
+__global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blocksums,
+                                                         int64_t nblk, int q, DevParams *p) {
+    __shared__ unsigned long long buf[1024];
+    if (p->status != CHAMFER_OK) return;
+    unsigned long long carry = 0;
+    for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const unsigned long long v = i < nblk ? blocksums[i] : 0ull;
+        const unsigned long long inc = block_inclusive_scan<1024>(v, buf);
+        if (i < nblk) blocksums[i] = carry + inc - v;
+        // total of this chunk is the last thread's inclusive value
+        __shared__ unsigned long long tot;
+        if (threadIdx.x == 1023) tot = inc;
+        __syncthreads();
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t mb = p->max_d_bits;
+        const bool zero = !(__uint_as_float(mb) > 0.0f);
+        p->W = carry;
+        p->s = zero ? 0 : fixed_point_exponent(mb, q);
+        p->all_zero = zero ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_prefix(const float *__restrict__ D, int64_t nA,
+                                                         const unsigned long long *blockoffs,
+                                                         unsigned long long *P,
+                                                         const DevParams *p) {
+    __shared__ unsigned long long buf[kScanThreads];
+    if (p->status != CHAMFER_OK) return;
+    const int s = p->s;
+    const bool zero = p->all_zero != 0;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    unsigned long long w[kScanItems];
+    unsigned long long own = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        w[j] = (!zero && base + j < nA) ? weight_of(D[base + j], s) : 0ull;
+        own += w[j];
+    }
+    const unsigned long long inc = block_inclusive_scan<kScanThreads>(own, buf);
+    unsigned long long run = blockoffs[blockIdx.x] + inc - own;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        run += w[j];
+        if (base + j < nA) P[base + j] = run;
+    }
+}
+
+hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
+                          DevParams *p, hipStream_t st) {
+    const int64_t nblk = (nA + kScanBlock - 1) / kScanBlock;
+    auto *bs = reinterpret_cast<unsigned long long *>(blocksums);
+    k_weight_blocksum<<<(unsigned)nblk, kScanThreads, 0, st>>>(D, nA, q, bs, p);
+    k_scan_blocksums<<<1, 1024, 0, st>>>(bs, nblk, q, p);
+    k_prefix<<<(unsigned)nblk, kScanThreads, 0, st>>>(D, nA, bs,
+                                                       reinterpret_cast<unsigned long long *>(P),
+                                                       p);
+    return hipGetLastError();
+}
+
+// Draw l: word 0 of Philox4x64-10 at counter (l, attempt, SAMPLE, 0), key
+// (seed, 0); Lemire: m = x W, reject while (m mod 2^64) < (2^64 - W) mod W,
+// u = m >> 64; idx = min{a : P_a > u}.  Also resets the nearest-neighbour
+// slot of the draw.
+__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P, int64_t nA,
+                         int64_t T, int32_t *idx, unsigned long long *best,
+                         const DevParams *p) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= T) return;
+    best[l] = ~0ull;
+    const uint64_t W = p->W;
+    if (p->status != CHAMFER_OK || W == 0) {
+        idx[l] = 0;
+        return;
+    }
+    uint64_t u = 0;
+    for (uint64_t attempt = 0; attempt < (1ull << 20); ++attempt) {
+        uint64_t c[4] = {(uint64_t)l, attempt, (uint64_t)kPurposeSample, 0};
+        philox4x64_10(c, seed, 0);
+        const uint64_t lo = c[0] * W;
+        u = __umul64hi(c[0], W);
+        if (lo < W) {
+            const uint64_t thr = (0ull - W) % W;
+            if (lo < thr) continue;
+        }
+        break;
+    }
+    int64_t a = 0, b = nA - 1;
+    while (a < b) {
+        const int64_t mid = a + ((b - a) >> 1);
+        if (P[mid] > u)
+            b = mid;
+        else
+            a = mid + 1;
+    }
+    idx[l] = (int32_t)a;
+}
+
+hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,
+                         unsigned long long *best, DevParams *p, hipStream_t st) {
+    if (T <= 0) return hipSuccess;
+    k_sample<<<(unsigned)((T + 255) / 256), 256, 0, st>>>(
+        seed, reinterpret_cast<const unsigned long long *>(P), nA, T, idx, best, p);
+    return hipGetLastError();
+}
+
+// eta = (1/T) sum_l (W / w_{x_l}) m_l; one block, fixed summation order.
+__global__ __launch_bounds__(256) void k_estimate_final(
+    const unsigned long long *__restrict__ best, const int32_t *__restrict__ idx,
+    const float *__restrict__ D, int64_t T, int metric, const DevParams *p, double *eta_out,
+    chamfer_aux aux) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int status = p->status;
+    const uint64_t W = p->W;
+    const int s = p->s;
+    double acc = 0.0;
+    for (int64_t l = t; l < T; l += 256) {
+        const unsigned long long b = best[l];
+        const float v = __uint_as_float((uint32_t)(b >> 32));
+        const int32_t nn = (int32_t)(uint32_t)(b & 0xffffffffu);
+        float m = metric == CHAMFER_L2 ? sqrtf(v) : v;
+        if (status != CHAMFER_OK) m = __builtin_nanf("");
+        if (status == CHAMFER_OK && W != 0) {
+            const double w = (double)weight_of(D[idx[l]], s);
+            acc += ((double)W / w) * (double)m;
+        }
+        if (aux.sample_min) aux.sample_min[l] = (status == CHAMFER_OK && W == 0) ? 0.0f : m;
+        if (aux.sample_nn) aux.sample_nn[l] = (W == 0) ? 0 : nn;
+        if (aux.sample_idx) aux.sample_idx[l] = idx[l];
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double eta = (W == 0 || T == 0) ? 0.0 : red[0] / (double)T;
+        if (status != CHAMFER_OK) eta = __builtin_nan("");
+        *eta_out = eta;
+        if (aux.D) *aux.D = ldexp((double)W, -s);
+        if (aux.W) *aux.W = W;
+        if (aux.s) *aux.s = s;
+        if (aux.status) *aux.status = status;
+    }
+}
+
+hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *idx,
+                                 const float *D, int64_t T, int metric, DevParams *p,
+                                 double *eta_out, chamfer_aux aux, hipStream_t st) {
+    k_estimate_final<<<1, 256, 0, st>>>(best, idx, D, T, metric, p, eta_out, aux);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_status(const DevParams *p, int32_t *out) {
+    if (threadIdx.x == 0) *out = p->status;
+}
+
+hipError_t launch_copy_status(const DevParams *p, int32_t *status_out, hipStream_t st) {
+    k_copy_status<<<1, 64, 0, st>>>(p, status_out);
+    return hipGetLastError();
+}
+
+}  // namespace chamfer

@@ -1,0 +1,248 @@
+"""GPU parity: every stage of the hot path against the CPU oracle on the same
+seeded inputs, through the C ABI.
+
+Integer and index outputs (bucket keys, e_top, first colliding scale,
+candidate b, D_a bit patterns, sampled indices, W, s, arg-mins) must be
+bit-identical.  Float outputs follow the tolerance of the path: the
+canonical float32 distances equal the oracle's float32 values bit for bit,
+and agree with its double-precision distances within 1e-5 relative; eta and
+CH agree with the oracle within 1e-5 relative.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_03043_amd as lib
+    lib.lib()
+    return lib
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def banner(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+SHAPES = [  # (n_a, n_b, d) spanning several tiles with ragged tails
+    (1000, 777, 3),
+    (2049, 3001, 16),
+    (513, 4100, 64),
+    (300, 2500, 128),
+    (130, 211, 37),
+    (1, 1, 5),
+    (65, 1, 32),
+]
+
+
+def clouds(n_a, n_b, d, seed):
+    A, _ = workloads.clusters_l2(seed=seed, n=n_a, d=d, k=max(2, n_a // 50), n_b=1)
+    _, B = workloads.clusters_l2(seed=seed, n=1, d=d, k=max(2, n_a // 50), n_b=n_b)
+    return A, B
+
+
+# ----------------------------------------------------------------- keys --
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", [(1000, 777, 3), (2049, 3001, 16), (300, 500, 64),
+                                   (129, 70, 128), (100, 90, 300)])
+def test_hash_keys_bit_exact(ch, orc, metric, shape):
+    n_a, n_b, d = shape
+    banner(f"hash_keys metric={metric} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=d)
+    for seed in (1, 2**35 + 11):
+        ka, kb, et = ch.chamfer_hash_keys(dev(A), dev(B), metric, 0.1, seed)
+        ref = orc.crude_nn(A, B, metric, 0.1, seed)
+        assert int(host(et)[0]) == ref["e_top"]
+        assert np.array_equal(host(ka).view(np.uint64), ref["keys_a"])
+        assert np.array_equal(host(kb).view(np.uint64), ref["keys_b"])
+
+
+def test_hash_keys_embed_dims(ch, orc):
+    A, B = clouds(300, 200, 24, seed=3)
+    for ke in (8, 16, 64):
+        ka, kb, _ = ch.chamfer_hash_keys(dev(A), dev(B), 2, 0.2, 9, embed_dim=ke, n_scales=11)
+        ref = orc.crude_nn(A, B, 2, 0.2, 9, n_scales=11, embed_dim=ke)
+        assert np.array_equal(host(ka).view(np.uint64), ref["keys_a"])
+        assert np.array_equal(host(kb).view(np.uint64), ref["keys_b"])
+
+
+# -------------------------------------------------------------- CrudeNN --
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_crude_nn_bit_exact(ch, orc, metric, shape):
+    n_a, n_b, d = shape
+    banner(f"crude_nn metric={metric} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=n_a + d)
+    for seed in (5, 123456789):
+        D, nn, sc = ch.crude_nn(dev(A), dev(B), metric, 0.1, seed)
+        ref = orc.crude_nn(A, B, metric, 0.1, seed)
+        assert np.array_equal(host(sc), ref["scale"])
+        assert np.array_equal(host(nn), ref["nn"])
+        assert np.array_equal(host(D).view(np.uint32), ref["D"].view(np.uint32))
+
+
+def test_crude_nn_self_and_single(ch, orc):
+    rng = np.random.default_rng(1)
+    P = rng.uniform(0, 1, size=(500, 3)).astype(np.float32)
+    for metric in (1, 2):
+        D, nn, sc = ch.crude_nn(dev(P), dev(P), metric, 0.1, 4)
+        ref = orc.crude_nn(P, P, metric, 0.1, 4)
+        assert np.array_equal(host(D).view(np.uint32), ref["D"].view(np.uint32))
+        assert np.array_equal(host(nn), ref["nn"])
+    b = P[:1]
+    D, nn, _ = ch.crude_nn(dev(P), dev(b), 2, 0.1, 4)
+    assert np.all(host(nn) == 0)
+
+
+# -------------------------------------------------------- nearest rows ---
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_exact_parity(ch, orc, metric, shape):
+    n_a, n_b, d = shape
+    banner(f"exact metric={metric} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=7 * d + n_b)
+    chv, rmin, rnn = ch.chamfer_exact(dev(A), dev(B), metric)
+    m32, a32 = orc.nn_f32(A, B, metric)
+    m64, _ = orc.nn_f64(A, B, metric)
+    assert np.array_equal(host(rnn), a32)
+    assert np.array_equal(host(rmin).view(np.uint32), m32.view(np.uint32))
+    np.testing.assert_allclose(host(rmin), m64, rtol=REL, atol=0)
+    ref = math.fsum(m64.tolist())
+    assert float(host(chv)[0]) == pytest.approx(ref, rel=REL)
+
+
+def test_exact_ties_lowest_index(ch):
+    A = np.array([[0.0, 0.0], [5.0, 5.0]], np.float32)
+    B = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [5.0, 6.0], [6.0, 5.0]], np.float32)
+    for metric in (1, 2):
+        _, rmin, rnn = ch.chamfer_exact(dev(A), dev(B), metric)
+        assert host(rnn).tolist() == [0, 3]
+        assert host(rmin).tolist() == [1.0, 1.0]
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_nn_min_rows(ch, orc, metric):
+    A, B = clouds(3000, 2000, 64, seed=11)
+    rows = np.random.default_rng(0).integers(0, 3000, size=777).astype(np.int32)
+    mn, arg = ch.chamfer_nn_min(dev(A), dev(B), metric, rows=dev(rows))
+    m32, a32 = orc.nn_f32(A, B, metric, rows=rows)
+    assert np.array_equal(host(arg), a32)
+    assert np.array_equal(host(mn).view(np.uint32), m32.view(np.uint32))
+
+
+# ------------------------------------------------------------ estimator --
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape,T", [((1000, 777, 3), 100), ((2049, 3001, 16), 512),
+                                     ((513, 4100, 64), 300), ((300, 2500, 128), 257),
+                                     ((130, 211, 37), 64), ((1, 1, 5), 10)])
+def test_estimate_parity(ch, orc, metric, shape, T):
+    n_a, n_b, d = shape
+    banner(f"estimate metric={metric} shape={shape} T={T}")
+    A, B = clouds(n_a, n_b, d, seed=3 * d + 1)
+    for seed in (0, 99):
+        out = ch.chamfer_estimate(dev(A), dev(B), metric, 0.2, T, seed)
+        ref = orc.chamfer_estimate(A, B, metric, 0.2, T, seed)
+        c = ref["crude"]
+        assert int(host(out["status"])[0]) == 0
+        assert np.array_equal(host(out["crude_D"]).view(np.uint32), c["D"].view(np.uint32))
+        assert np.array_equal(host(out["crude_nn"]), c["nn"])
+        assert int(host(out["W"])[0]) == ref["W"]
+        assert int(host(out["s"])[0]) == ref["s"]
+        assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+        np.testing.assert_allclose(host(out["sample_min"]), ref["m"], rtol=REL, atol=0)
+        m32, a32 = orc.nn_f32(A, B, metric, rows=ref["idx"])
+        assert np.array_equal(host(out["sample_nn"]), a32)
+        assert np.array_equal(host(out["sample_min"]).view(np.uint32), m32.view(np.uint32))
+        assert float(host(out["D"])[0]) == ref["D_norm"]
+        assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=REL)
+
+
+def test_estimate_default_T_and_L(ch, orc):
+    A, B = workloads.small_l2(seed=42, n=2000, d=16)
+    out = ch.chamfer_estimate(dev(A), dev(B), 2, 0.3, 0, 5)
+    ref = orc.chamfer_estimate(A, B, 2, 0.3, 0, 5)
+    assert out["T"] == ref["T"] == orc.default_samples(2000, 0.3)
+    assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+    assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=REL)
+
+
+def test_estimate_degenerate(ch, orc):
+    rng = np.random.default_rng(2)
+    P = rng.standard_normal((300, 8)).astype(np.float32)
+    for metric in (1, 2):
+        out = ch.chamfer_estimate(dev(P), dev(P), metric, 0.1, 50, 3)
+        assert float(host(out["eta"])[0]) == 0.0
+        same = np.ones((40, 8), np.float32)
+        out = ch.chamfer_estimate(dev(same), dev(same[:2]), metric, 0.1, 50, 3)
+        assert float(host(out["eta"])[0]) == 0.0
+        assert int(host(out["W"])[0]) == 0
+        out = ch.chamfer_estimate(dev(P[:0]), dev(P), metric, 0.1, 50, 3, with_aux=False)
+        assert float(host(out["eta"])[0]) == 0.0
+        chv, _, _ = ch.chamfer_exact(dev(P[:0]), dev(P), metric)
+        assert float(host(chv)[0]) == 0.0
+
+
+def test_nonfinite_input_reports_status(ch):
+    """A NaN coordinate is detected on the device: status -4, eta NaN."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((200, 4)).astype(np.float32)
+    B = rng.standard_normal((100, 4)).astype(np.float32)
+    A[17, 2] = np.nan
+    out = ch.chamfer_estimate(dev(A), dev(B), 2, 0.1, 20, 1)
+    assert int(host(out["status"])[0]) == -4
+    assert math.isnan(float(host(out["eta"])[0]))
+    B[3, 0] = np.inf
+    chv, _, _ = ch.chamfer_exact(dev(A * 0), dev(B), 1)
+    assert math.isnan(float(host(chv)[0]))
+
+
+def test_determinism(ch):
+    A, B = workloads.small_l2(seed=8, n=4096, d=16)
+    a, b = dev(A), dev(B)
+    outs = [ch.chamfer_estimate(a, b, 2, 0.2, 512, 77) for _ in range(3)]
+    for o in outs[1:]:
+        for k in ("eta", "sample_idx", "sample_min", "crude_D", "crude_nn"):
+            assert torch.equal(o[k], outs[0][k]), k
+    e = [ch.chamfer_exact(a, b, 2)[0] for _ in range(3)]
+    assert torch.equal(e[0], e[1]) and torch.equal(e[0], e[2])
+
+
+# -------------------------------------------------------------- coverage --
+
+def test_coverage_small_config(ch, orc):
+    """Main theorem, small configuration (l2, |A|=|B|=4096, d=16, eps=0.2,
+    T=512): within (1 +- eps) CH in >= 99% of 1000 seeds."""
+    A, B = workloads.small_l2()
+    exact, _, _ = orc.chamfer_exact(A, B, 2)
+    a, b = dev(A), dev(B)
+    etas = []
+    for seed in range(1000):
+        etas.append(ch.chamfer_estimate(a, b, 2, 0.2, 512, seed, with_aux=False)["eta"])
+    etas = host(torch.cat(etas))
+    frac = np.mean(np.abs(etas - exact) <= 0.2 * exact)
+    print(f"coverage {frac:.4f} mean rel err {np.mean(np.abs(etas - exact)) / exact:.4e}")
+    assert frac >= 0.99
