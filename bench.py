@@ -96,8 +96,14 @@ class HipEvents:
 
 
 def algorithmic_sample_pass(metric, T, n_b, d):
-    """Work of the exact pass over the draws: T * n_B * d coordinate terms."""
+    """Work of the exact pass over the draws: T * n_B * d coordinate terms.
+    l2 (12 <= d <= 256) runs on FP32 MFMA: 2 flops (one multiply-add of
+    x.b) per term.  l1 runs on the vector ALU: 2 lane-ops (subtract, add
+    |t|) per term."""
     elems = float(T) * n_b * d
+    if metric == 2 and 12 <= d <= 256:
+        return dict(bound="mfma", unit="TFLOP/s", ops=2.0 * elems, peak=FP32_MFMA_TFLOPS,
+                    note="2 flops (x.b multiply-add) per coordinate term on FP32 MFMA")
     if metric == 2:
         return dict(bound="alu", unit="TOP/s", ops=2.0 * elems, peak=VALU_LANE_TOPS,
                     note="2 VALU lane-ops (subtract, fma) per coordinate term")

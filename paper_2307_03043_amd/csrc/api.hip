@@ -133,6 +133,7 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_idx = take(h * pl.T * sizeof(int32_t));
     pl.off_best = take((size_t)nrow * sizeof(uint64_t));
     pl.off_partial = take((size_t)(nn_finalize_blocks(nrow) + 1) * sizeof(double));
+    pl.off_nb2 = take(mfma_supported(d, metric) ? (size_t)nB * sizeof(float) : 0);
     pl.off_fallback = take(0);
     pl.off_lowp = take(0);
     pl.off_lowpnorm = take(0);
@@ -189,8 +190,11 @@ hipError_t mark(void **ev, int i, hipStream_t st) {
     return hipEventRecord(static_cast<hipEvent_t>(ev[i]), st);
 }
 
+// CrudeNN into D/nn/scale.  nb2 (l2 only, may be null): |b|^2 per row of B,
+// computed while B is bucketed, for the nearest-neighbour pass.
 int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
-               int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr) {
+               int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,
+               float *nb2 = nullptr) {
     CH_TRY(mark(ev, 0, st));
     int rc = hash_prologue(pl, A, B, seed, ws, st);
     if (rc) return rc;
@@ -203,10 +207,10 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
     const float *zf = at<float>(ws, pl.off_zfrac);
     const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
     CH_TRY(launch_hash(0, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
-                       tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr, p, st));
+                       tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr, nb2, p, st));
     CH_TRY(mark(ev, 2, st));
     CH_TRY(launch_hash(1, A, pl.nA, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
-                       tables, pl.log2cap, nullptr, D, nn, scale, p, st));
+                       tables, pl.log2cap, nullptr, D, nn, scale, nullptr, p, st));
     CH_TRY(mark(ev, 3, st));
     return CHAMFER_OK;
 }
@@ -253,7 +257,12 @@ int chamfer_exact(const float *A, const float *B, int64_t n_A, int64_t n_B, int3
     CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, d, p, st));
     CH_TRY(launch_fill_u64(best, n_A, ~0ull, st));
-    CH_TRY(launch_nnmin(A, nullptr, n_A, B, n_B, d, metric, best, p, st));
+    float *nb2 = nullptr;
+    if (mfma_supported(d, metric)) {
+        nb2 = at<float>(ws, pl.off_nb2);
+        CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
+    }
+    CH_TRY(launch_nnmin(A, nullptr, n_A, B, n_B, d, metric, best, nb2, p, st));
     CH_TRY(launch_nn_finalize(best, n_A, metric, rowmin_out, rownn_out, partial, p, st));
     CH_TRY(launch_sum_final(partial, nn_finalize_blocks(n_A), p, ch_out, st));
     return CHAMFER_OK;
@@ -273,7 +282,12 @@ int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_init_params(p, nullptr, d, st));
     CH_TRY(launch_fill_u64(best, n_x, ~0ull, st));
-    CH_TRY(launch_nnmin(X, rows, n_x, B, n_B, d, metric, best, p, st));
+    float *nb2 = nullptr;
+    if (mfma_supported(d, metric)) {
+        nb2 = at<float>(ws, pl.off_nb2);
+        CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
+    }
+    CH_TRY(launch_nnmin(X, rows, n_x, B, n_B, d, metric, best, nb2, p, st));
     CH_TRY(launch_nn_finalize(best, n_x, metric, min_out, arg_out, nullptr, p, st));
     return CHAMFER_OK;
 }
@@ -314,7 +328,8 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
     int32_t *scale = ax.crude_scale;
     void **ev = ax.stage_events;
-    if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev))) return rc;
+    float *nb2 = mfma_supported(d, metric) ? at<float>(ws, pl.off_nb2) : nullptr;
+    if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2))) return rc;
     DevParams *p = at<DevParams>(ws, pl.off_params);
     uint64_t *P = at<uint64_t>(ws, pl.off_P);
     int32_t *idx = at<int32_t>(ws, pl.off_idx);
@@ -322,7 +337,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
     CH_TRY(mark(ev, 4, st));
-    CH_TRY(launch_nnmin(A, idx, pl.T, B, n_B, d, metric, best, p, st));
+    CH_TRY(launch_nnmin(A, idx, pl.T, B, n_B, d, metric, best, nb2, p, st));
     CH_TRY(mark(ev, 5, st));
     CH_TRY(launch_estimate_final(best, idx, D, pl.T, metric, p, eta_out, ax, st));
     CH_TRY(mark(ev, 6, st));
@@ -347,10 +362,10 @@ int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, 
     const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
     if (keys_A_out)
         CH_TRY(launch_hash(2, A, n_A, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
-                           pl.log2cap, keys_A_out, nullptr, nullptr, nullptr, p, st));
+                           pl.log2cap, keys_A_out, nullptr, nullptr, nullptr, nullptr, p, st));
     if (keys_B_out)
         CH_TRY(launch_hash(2, B, n_B, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
-                           pl.log2cap, keys_B_out, nullptr, nullptr, nullptr, p, st));
+                           pl.log2cap, keys_B_out, nullptr, nullptr, nullptr, nullptr, p, st));
     if (e_top_out) {
         // e_top lives in the device parameter block.
         CH_TRY(hipMemcpyAsync(e_top_out, &p->e_top, sizeof(int32_t), hipMemcpyDeviceToDevice,

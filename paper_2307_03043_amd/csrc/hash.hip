@@ -29,6 +29,8 @@ __global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
         p->nonfinite = 0;
         p->W = 0;
         p->S = 0.0;
+        p->b2max_bits = 0;
+        p->fallbacks = 0;
     }
     if (lohi != nullptr)
         for (int k = t; k < d; k += gridDim.x * blockDim.x) {
@@ -108,9 +110,73 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int
     }
 }
 
+// Same with 16-byte loads when d is a multiple of 4: thread g keeps the four
+// coordinates of float4 column (g mod d/4).
+__global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, int64_t total4,
+                                                 int d, int64_t stride4, uint32_t *lohi,
+                                                 DevParams *p) {
+    extern __shared__ uint32_t sm[];
+    const int d4 = d >> 2;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        sm[i] = 0xffffffffu;
+        sm[d + i] = 0u;
+    }
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t lo[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+    uint32_t hi[4] = {0u, 0u, 0u, 0u};
+    int bad = 0;
+    auto take = [&](const float4 v) {
+        const float c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bad |= !isfinite(c[i]);
+            const uint32_t o = float_to_ordered(c[i]);
+            lo[i] = min(lo[i], o);
+            hi[i] = max(hi[i], o);
+        }
+    };
+    if (g < stride4) {
+        int64_t e = g;
+        for (; e + 3 * stride4 < total4; e += 4 * stride4) {
+            const float4 v0 = X4[e], v1 = X4[e + stride4], v2 = X4[e + 2 * stride4],
+                         v3 = X4[e + 3 * stride4];
+            take(v0);
+            take(v1);
+            take(v2);
+            take(v3);
+        }
+        for (; e < total4; e += stride4) take(X4[e]);
+        const int k0 = (int)(g % d4) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            atomicMin(&sm[k0 + i], lo[i]);
+            atomicMax(&sm[d + k0 + i], hi[i]);
+        }
+    }
+    if (bad) atomicOr(&p->nonfinite, 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        if (sm[i] != 0xffffffffu) atomicMin(&lohi[i], sm[i]);
+        if (sm[d + i] != 0u) atomicMax(&lohi[d + i], sm[d + i]);
+    }
+}
+
 hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
                          hipStream_t st) {
     const int64_t total = n * (int64_t)d;
+    if ((d & 3) == 0 && d <= 2048 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+        const int64_t total4 = total / 4;
+        const int d4 = d / 4;
+        int64_t blocks = (total4 + 1023) / 1024;
+        if (blocks > 1024) blocks = 1024;
+        const int64_t min_blocks = (d4 + 255) / 256;
+        if (blocks < min_blocks) blocks = min_blocks;
+        const int64_t stride4 = (blocks * 256 / d4) * d4;
+        k_minmax4<<<(unsigned)blocks, 256, 2 * (size_t)d * sizeof(uint32_t), st>>>(
+            reinterpret_cast<const float4 *>(X), total4, d, stride4, lohi, p);
+        return hipGetLastError();
+    }
     int64_t blocks = (total + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     const int64_t min_blocks = (d + 255) / 256;
@@ -121,22 +187,39 @@ hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevPa
     return hipGetLastError();
 }
 
-// S = sum_k (hi_k - lo_k) in double, k ascending; e_top = ceil(log2 S).
-__global__ void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+__global__ void k_calib_final_wide(const uint32_t *lohi, int d, DevParams *p) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double S = 0.0;
-    for (int k = 0; k < d; ++k) {
-        const double hi = (double)ordered_to_float(lohi[d + k]);
-        const double lo = (double)ordered_to_float(lohi[k]);
-        S = S + (hi - lo);
-    }
+    for (int k = 0; k < d; ++k)
+        S = S + ((double)ordered_to_float(lohi[d + k]) - (double)ordered_to_float(lohi[k]));
+    p->S = S;
+    p->e_top = S > 0.0 ? ceil_log2_pos(S) : 0;
+    if (p->nonfinite) p->status = CHAMFER_ENONFINITE;
+}
+
+// S = sum_k (hi_k - lo_k) in double, k ascending; e_top = ceil(log2 S).
+// The per-coordinate spans are gathered in parallel; one thread sums them
+// in order.
+__global__ __launch_bounds__(256) void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+    extern __shared__ double span[];
+    for (int k = threadIdx.x; k < d; k += blockDim.x)
+        span[k] = (double)ordered_to_float(lohi[d + k]) - (double)ordered_to_float(lohi[k]);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double S = 0.0;
+    for (int k = 0; k < d; ++k) S = S + span[k];
     p->S = S;
     p->e_top = S > 0.0 ? ceil_log2_pos(S) : 0;
     if (p->nonfinite) p->status = CHAMFER_ENONFINITE;
 }
 
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st) {
-    k_calib_final<<<1, 64, 0, st>>>(lohi, d, p);
+    if ((size_t)d * sizeof(double) > 60000) {
+        // very wide points: spans recomputed by the summing thread
+        k_calib_final_wide<<<1, 64, 0, st>>>(lohi, d, p);
+        return hipGetLastError();
+    }
+    k_calib_final<<<1, 256, (size_t)d * sizeof(double), st>>>(lohi, d, p);
     return hipGetLastError();
 }
 
@@ -234,65 +317,50 @@ __device__ __forceinline__ int table_probe(const Bucket *__restrict__ tab, int l
     }
 }
 
-// Canonical float32 distance: k ascending, l1 acc + |t|, l2 fma(t, t, acc),
-// then a correctly rounded square root.
+// Canonical float32 distance (square root of the accumulator for l2).
 template <int METRIC>
 __device__ __forceinline__ float dist32(const float *__restrict__ a, const float *__restrict__ b,
                                         int d) {
-    float acc = 0.0f;
-    if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
-        const float4 *a4 = reinterpret_cast<const float4 *>(a);
-        const float4 *b4 = reinterpret_cast<const float4 *>(b);
-        for (int k = 0; k < (d >> 2); ++k) {
-            const float4 u = a4[k], v = b4[k];
-            const float t0 = u.x - v.x, t1 = u.y - v.y, t2 = u.z - v.z, t3 = u.w - v.w;
-            if (METRIC == CHAMFER_L1) {
-                acc = acc + fabsf(t0);
-                acc = acc + fabsf(t1);
-                acc = acc + fabsf(t2);
-                acc = acc + fabsf(t3);
-            } else {
-                acc = fmaf(t0, t0, acc);
-                acc = fmaf(t1, t1, acc);
-                acc = fmaf(t2, t2, acc);
-                acc = fmaf(t3, t3, acc);
-            }
-        }
-    } else {
-        for (int k = 0; k < d; ++k) {
-            const float t = a[k] - b[k];
-            if (METRIC == CHAMFER_L1)
-                acc = acc + fabsf(t);
-            else
-                acc = fmaf(t, t, acc);
-        }
-    }
+    const float acc = canon_acc<METRIC>(a, b, d);
     return METRIC == CHAMFER_L1 ? acc : sqrtf(acc);
 }
 
-constexpr int kTile = 64;      // points per workgroup (one wavefront)
+constexpr int kTile = 64;        // points per workgroup
+constexpr int kWaves = 4;        // wavefronts per workgroup; they split the scales
+constexpr int kThreads = 64 * kWaves;
 constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
 
 // MODE 0: insert the tile's points (B) into the L tables.
 // MODE 1: probe (A): first scale with a hit, candidate, D_a; max D_a.
 // MODE 2: write keys[L][n].
 // KE: embedding dimension for l2 (0 for l1).  YG: l1 coordinates from HBM.
+// Lane p of every wavefront works on point p of the tile; wavefront w takes
+// scales w, w + 4, w + 8, ...  For the probe each wavefront stops at its own
+// first hit (or once another wavefront has hit at a finer scale); the first
+// colliding scale is the smallest over the four.
 template <int METRIC, int MODE, int KE, bool YG>
-__global__ __launch_bounds__(kTile) void k_hash(
+__global__ __launch_bounds__(kThreads) void k_hash(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, DevParams *p) {
+    int32_t *scale_out, float *nb2_out, DevParams *p) {
     extern __shared__ float smem[];
-    const int t = threadIdx.x;
+    __shared__ float los[kEmbedChunk];
+    __shared__ int hit_scale[kTile];
+    __shared__ int hit_cand[kWaves][kTile];
+    __shared__ int wave_scale[kWaves][kTile];
+    const int tid = threadIdx.x;
+    // wave-uniform by construction; readfirstlane lets the compiler know, so
+    // the per-scale tables and the embedding columns go through scalar loads
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t p0 = (int64_t)blockIdx.x * kTile;
     const int np = (int)min<int64_t>(kTile, n - p0);
-    const int64_t pt = p0 + t;
-    const bool active = t < np;
+    const int64_t pt = p0 + lane;
+    const bool active = lane < np;
 
     if (p->status != CHAMFER_OK) {
-        if (MODE == 1 && active) {
+        if (MODE == 1 && wave == 0 && active) {
             D_out[pt] = __builtin_nanf("");
             nn_out[pt] = -1;
             if (scale_out) scale_out[pt] = -1;
@@ -300,50 +368,65 @@ __global__ __launch_bounds__(kTile) void k_hash(
         return;
     }
     const int kh = METRIC == CHAMFER_L1 ? d : KE;
-    const int khp = kh | 1;  // odd row stride
+    const int khp = kh | 1;  // odd row stride: lanes read distinct banks
     float *ys = smem;        // [kTile][khp]
     const int e_top = p->e_top;
 
     if (METRIC == CHAMFER_L1) {
-        if (!YG) {
-            for (int e = t; e < np * d; e += kTile) {
+        if (!YG)
+            for (int e = tid; e < np * d; e += kThreads) {
                 const int r = e / d, k = e - r * d;
                 ys[r * khp + k] = X[(p0 + r) * d + k] - ordered_to_float(lohi[k]);
             }
-            __syncthreads();
-        }
     } else {
-        // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k.
+        // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k; wavefront
+        // w computes the coordinates j in [w KE/4, (w+1) KE/4) of point lane.
+        // The raw rows are staged (x - lo is formed on read, the same float
+        // subtraction); for B, wavefront 0 also accumulates |x|^2 per row for
+        // the l2 nearest-neighbour pass.
+        constexpr int JW = KE / kWaves;
         float *xs = smem + kTile * khp;  // [kTile][kEmbedChunk + 1]
-        float y[KE > 0 ? KE : 1];
+        float y[JW > 0 ? JW : 1];
 #pragma unroll
-        for (int j = 0; j < KE; ++j) y[j] = 0.0f;
+        for (int j = 0; j < JW; ++j) y[j] = 0.0f;
+        float n2 = 0.0f;
+        const bool want_n2 = MODE == 0 && nb2_out != nullptr && wave == 0;
         for (int k0 = 0; k0 < d; k0 += kEmbedChunk) {
             const int kc = min(kEmbedChunk, d - k0);
             __syncthreads();
-            for (int e = t; e < np * kc; e += kTile) {
+            for (int e = tid; e < np * kc; e += kThreads) {
                 const int r = e / kc, k = e - r * kc;
-                xs[r * (kEmbedChunk + 1) + k] =
-                    X[(p0 + r) * d + k0 + k] - ordered_to_float(lohi[k0 + k]);
+                xs[r * (kEmbedChunk + 1) + k] = X[(p0 + r) * d + k0 + k];
             }
+            if (tid < kc) los[tid] = ordered_to_float(lohi[k0 + tid]);
             __syncthreads();
             if (active) {
                 for (int k = 0; k < kc; ++k) {
-                    const float xv = xs[t * (kEmbedChunk + 1) + k];
-                    const float *zc = embed_t + (size_t)(k0 + k) * KE;
+                    const float xraw = xs[lane * (kEmbedChunk + 1) + k];
+                    const float xv = xraw - los[k];
+                    const float *zc = embed_t + (size_t)(k0 + k) * KE + wave * JW;
 #pragma unroll
-                    for (int j = 0; j < KE; ++j) y[j] = fmaf(zc[j], xv, y[j]);
+                    for (int j = 0; j < JW; ++j) y[j] = fmaf(zc[j], xv, y[j]);
+                    if (want_n2) n2 = fmaf(xraw, xraw, n2);
                 }
             }
         }
         if (active) {
 #pragma unroll
-            for (int j = 0; j < KE; ++j) ys[t * khp + j] = y[j];
+            for (int j = 0; j < JW; ++j) ys[lane * khp + wave * JW + j] = y[j];
+            if (want_n2) nb2_out[pt] = n2;
         }
-        __syncthreads();
+        if (want_n2) {
+            uint32_t m = __float_as_uint(n2);
+            for (int off = 32; off > 0; off >>= 1)
+                m = max(m, (uint32_t)__shfl_xor((int)m, off));
+            if (lane == 0) atomicMax(&p->b2max_bits, m);
+        }
     }
+    if (MODE == 1 && wave == 0) hit_scale[lane] = L;
+    __syncthreads();
 
-    const float *yrow = ys + t * khp;
+    const float *yrow = ys + lane * khp;
     const float *xrow = X + pt * d;
     auto key_at = [&](int i) -> unsigned long long {
         const int e = e_top - (L - 1 - i);
@@ -354,37 +437,72 @@ __global__ __launch_bounds__(kTile) void k_hash(
     };
 
     if (MODE == 0) {
-        if (active)
-            for (int i = 0; i < L; ++i)
-                table_insert(tables + ((size_t)i << log2cap), log2cap, key_at(i), (int)pt);
+        // At coarse scales most lanes share a bucket.  A lane skips its
+        // insert when a lower lane holds the same key (it has a lower index),
+        // so the lowest index per bucket is unchanged and the hot buckets see
+        // one access per wavefront instead of one per point.
+        // Up to kLeaders distinct keys of the wavefront are deduplicated by
+        // leader election (the leader is the lowest lane holding the key);
+        // all remaining inserts then run in parallel.
+        constexpr int kLeaders = 4;
+        for (int i = wave; i < L; i += kWaves) {
+            const unsigned long long key = active ? key_at(i) : kEmptyKey;
+            unsigned long long rest = __ballot(active);
+            bool mine = false;
+            for (int it = 0; it < kLeaders && rest != 0; ++it) {
+                const int leader = __ffsll((long long)rest) - 1;
+                const unsigned long long lk = __shfl(key, leader);
+                rest &= ~__ballot(active && key == lk);
+                mine |= lane == leader;
+            }
+            mine |= ((rest >> lane) & 1ull) != 0;
+            if (mine) table_insert(tables + ((size_t)i << log2cap), log2cap, key, (int)pt);
+        }
         return;
     }
     if (MODE == 2) {
         if (active)
-            for (int i = 0; i < L; ++i) keys_out[(size_t)i * n + pt] = key_at(i);
+            for (int i = wave; i < L; i += kWaves) keys_out[(size_t)i * n + pt] = key_at(i);
         return;
     }
     // MODE 1: probe.
-    float D = 0.0f;
+    int found = L, cand = 0;
     if (active) {
-        int found = L, cand = 0;
-        for (int i = 0; i < L; ++i) {
+        for (int i = wave; i < L; i += kWaves) {
+            if (i > __hip_atomic_load(&hit_scale[lane], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP))
+                break;  // a finer scale already collided
             const int v = table_probe(tables + ((size_t)i << log2cap), log2cap, key_at(i));
             if (v >= 0) {
                 found = i;
                 cand = v;
+                atomicMin(&hit_scale[lane], i);
                 break;
             }
         }
-        D = dist32<METRIC>(xrow, Bpts + (size_t)cand * d, d);
-        D_out[pt] = D;
-        nn_out[pt] = cand;
-        if (scale_out) scale_out[pt] = found;
     }
-    // wave max of D (all lanes take part; D >= 0 so bits order as floats)
+    wave_scale[wave][lane] = found;
+    hit_cand[wave][lane] = cand;
+    __syncthreads();
+    if (wave != 0) return;
+    float D = 0.0f;
+    if (active) {
+        int best_s = L, best_c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            if (wave_scale[w][lane] < best_s) {
+                best_s = wave_scale[w][lane];
+                best_c = hit_cand[w][lane];
+            }
+        D = dist32<METRIC>(xrow, Bpts + (size_t)best_c * d, d);
+        D_out[pt] = D;
+        nn_out[pt] = best_c;
+        if (scale_out) scale_out[pt] = best_s;
+    }
+    // wavefront max of D (D >= 0, so its bits order as floats)
     uint32_t m = __float_as_uint(D);
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if (t == 0) atomicMax(&p->max_d_bits, m);
+    if (lane == 0) atomicMax(&p->max_d_bits, m);
 }
 
 template <int METRIC, int KE, bool YG>
@@ -392,7 +510,8 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
                                 int L, const uint32_t *lohi, const float *embed_t,
                                 const float *zfrac, const uint64_t *mult, Bucket *tables,
                                 int log2cap, uint64_t *keys_out, float *D_out, int32_t *nn_out,
-                                int32_t *scale_out, DevParams *p, hipStream_t st) {
+                                int32_t *scale_out, float *nb2_out, DevParams *p,
+                                hipStream_t st) {
     const int kh = METRIC == CHAMFER_L1 ? d : KE;
     size_t lds = 0;
     if (METRIC == CHAMFER_L1) {
@@ -403,32 +522,33 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
     const unsigned blocks = (unsigned)((n + kTile - 1) / kTile);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
     if (mode == 0)
-        k_hash<METRIC, 0, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
-                                                              zfrac, mult, tables, log2cap, ko,
-                                                              D_out, nn_out, scale_out, p);
+        k_hash<METRIC, 0, KE, YG><<<blocks, kThreads, lds, st>>>(
+            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
+            scale_out, nb2_out, p);
     else if (mode == 1)
-        k_hash<METRIC, 1, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
-                                                              zfrac, mult, tables, log2cap, ko,
-                                                              D_out, nn_out, scale_out, p);
+        k_hash<METRIC, 1, KE, YG><<<blocks, kThreads, lds, st>>>(
+            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
+            scale_out, nb2_out, p);
     else
-        k_hash<METRIC, 2, KE, YG><<<blocks, kTile, lds, st>>>(X, n, Bpts, d, L, lohi, embed_t,
-                                                              zfrac, mult, tables, log2cap, ko,
-                                                              D_out, nn_out, scale_out, p);
+        k_hash<METRIC, 2, KE, YG><<<blocks, kThreads, lds, st>>>(
+            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
+            scale_out, nb2_out, p);
     return hipGetLastError();
 }
 
 // Largest l1 dimension whose tile fits the default 64 KiB of dynamic LDS.
-constexpr int kMaxLdsL1Dim = (65536 / (kTile * 4)) - 2;
+constexpr int kMaxLdsL1Dim = 240;  // 64 x 241 floats + static LDS < 64 KiB
 
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
                        const float *embed_t, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
-                       int32_t *nn_out, int32_t *scale_out, DevParams *p, hipStream_t st) {
+                       int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
+                       hipStream_t st) {
     (void)nB;
     if (n <= 0) return hipSuccess;
 #define CH_ARGS mode, X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, keys_out, \
-                D_out, nn_out, scale_out, p, st
+                D_out, nn_out, scale_out, nb2_out, p, st
     if (metric == CHAMFER_L1) {
         if (d <= kMaxLdsL1Dim) return launch_hash_t<CHAMFER_L1, 0, false>(CH_ARGS);
         return launch_hash_t<CHAMFER_L1, 0, true>(CH_ARGS);

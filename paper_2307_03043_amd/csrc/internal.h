@@ -27,7 +27,9 @@ struct DevParams {
     uint32_t nonfinite;  // an input coordinate is NaN or Inf
     uint64_t W;          // fixed-point total
     double S;            // sum_k (hi_k - lo_k)
-    uint64_t pad[3];
+    uint32_t b2max_bits; // bits of max_b |b|^2 (float32, >= 0)
+    uint32_t fallbacks;  // (query, chunk) pairs rescanned exactly by the MFMA pass
+    uint64_t pad[2];
 };
 
 // One bucket of a scale's open-addressing table: key -> lowest b index.
@@ -67,6 +69,60 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
     }
 }
 
+// Canonical float32 distance accumulator between rows a and b: k ascending,
+// one rounding per operation; l1: acc + |a_k - b_k|, l2: fma(t, t, acc) with
+// t = a_k - b_k (the caller takes the square root for l2).  Loads are issued
+// in batches of 8 x 16 bytes ahead of the (sequential) arithmetic, so a row
+// costs a few memory round trips instead of one per 16 bytes.
+template <int METRIC>
+__device__ __forceinline__ float canon_acc(const float *__restrict__ a,
+                                           const float *__restrict__ b, int d) {
+    float acc = 0.0f;
+    auto step = [&](float x, float y) {
+        const float t = x - y;
+        acc = METRIC == CHAMFER_L1 ? acc + fabsf(t) : fmaf(t, t, acc);
+    };
+    if ((d & 3) == 0 &&
+        ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+        const float4 *a4 = reinterpret_cast<const float4 *>(a);
+        const float4 *b4 = reinterpret_cast<const float4 *>(b);
+        const int d4 = d >> 2;
+        constexpr int kBatch = 8;
+        for (int k0 = 0; k0 < d4; k0 += kBatch) {
+            float4 u[kBatch], v[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i)
+                if (k0 + i < d4) {
+                    u[i] = a4[k0 + i];
+                    v[i] = b4[k0 + i];
+                }
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i)
+                if (k0 + i < d4) {
+                    step(u[i].x, v[i].x);
+                    step(u[i].y, v[i].y);
+                    step(u[i].z, v[i].z);
+                    step(u[i].w, v[i].w);
+                }
+        }
+        return acc;
+    }
+    constexpr int kBatch = 16;
+    for (int k0 = 0; k0 < d; k0 += kBatch) {
+        float u[kBatch], v[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (k0 + i < d) {
+                u[i] = a[k0 + i];
+                v[i] = b[k0 + i];
+            }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (k0 + i < d) step(u[i], v[i]);
+    }
+    return acc;
+}
+
 // smallest e with 2^e >= x (x > 0)
 __device__ __forceinline__ int ceil_log2_pos(double x) {
     int e;
@@ -84,7 +140,7 @@ struct Plan {
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
-        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_fallback,
+        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_fallback,
         off_lowp, off_lowpnorm, total;
 };
 
@@ -103,12 +159,14 @@ hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevPa
                          hipStream_t st);
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st);
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st);
-// mode 0: insert B into the tables; 1: probe A (CrudeNN); 2: write keys
+// mode 0: insert B into the tables (l2: also |b|^2 into nb2_out and
+// p->b2max_bits when nb2_out is set); 1: probe A (CrudeNN); 2: write keys
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
                        const float *embed_t, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
-                       int32_t *nn_out, int32_t *scale_out, DevParams *p, hipStream_t st);
+                       int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
+                       hipStream_t st);
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
                           DevParams *p, hipStream_t st);
 hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,
@@ -118,9 +176,17 @@ hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *
                                  double *eta_out, chamfer_aux aux, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t st);
+// Exact nearest neighbours; nb2 (float [nB], or nullptr) selects the l2 MFMA
+// form, which needs launch_rownorm to have filled nb2 and p->b2max_bits.
 hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const float *B,
                         int64_t nB, int d, int metric, unsigned long long *best,
-                        const DevParams *p, hipStream_t st);
+                        const float *nb2, DevParams *p, hipStream_t st);
+hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevParams *p,
+                          hipStream_t st);
+bool mfma_supported(int d, int metric);
+hipError_t launch_nnmin_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
+                             int64_t nB, int d, unsigned long long *best, const float *nb2,
+                             DevParams *p, hipStream_t st);
 hipError_t launch_nn_finalize(const unsigned long long *best, int64_t nx, int metric,
                               float *min_out, int32_t *arg_out, double *partial,
                               const DevParams *p, hipStream_t st);

@@ -198,8 +198,10 @@ static hipError_t go_metric(const float *X, const int32_t *rows, int64_t nx, con
 
 hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const float *B,
                         int64_t nB, int d, int metric, unsigned long long *best,
-                        const DevParams *p, hipStream_t st) {
+                        const float *nb2, DevParams *p, hipStream_t st) {
     if (nx <= 0) return hipSuccess;
+    if (nb2 != nullptr && mfma_supported(d, metric))
+        return launch_nnmin_mfma(X, rows, nx, B, nB, d, best, nb2, p, st);
     if (metric == CHAMFER_L1) return go_metric<CHAMFER_L1>(X, rows, nx, B, nB, d, best, p, st);
     return go_metric<CHAMFER_L2>(X, rows, nx, B, nB, d, best, p, st);
 }
