@@ -29,13 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC_NAME = "Chamfer points/s at ε=0.1 vs GPU brute force; %HBM/MFMA peak; p50/p99 ms"
 
-# MI355X published peaks and unit counts.
+# MI355X published peaks.
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_TFLOPS = 157.3
+FP32_VECTOR_TFLOPS = 157.3   # 256 CUs x 256 FP32 flops/clk x 2.4 GHz
 BF16_MFMA_TFLOPS = 2500.0
-# Plain (non-packed) FP32 vector lane operations: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz.
-VALU_LANE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FP8_MFMA_TFLOPS = 5000.0
 
 WORKLOADS = {
     # name: (generator, kwargs, metric, eps, T, L, description)
@@ -98,30 +97,55 @@ class HipEvents:
 def algorithmic_sample_pass(metric, T, n_b, d):
     """Work of the exact pass over the draws: T * n_B * d coordinate terms.
     l2 (12 <= d <= 256) runs on FP32 MFMA: 2 flops (one multiply-add of
-    x.b) per term.  l1 runs on the vector ALU: 2 lane-ops (subtract, add
-    |t|) per term."""
+    x.b) per term.  l1 runs on the vector ALU: 2 flops (subtract, add |t|)
+    per term, against the FP32 vector peak."""
     elems = float(T) * n_b * d
     if metric == 2 and 12 <= d <= 256:
         return dict(bound="mfma", unit="TFLOP/s", ops=2.0 * elems, peak=FP32_MFMA_TFLOPS,
                     note="2 flops (x.b multiply-add) per coordinate term on FP32 MFMA")
     if metric == 2:
-        return dict(bound="alu", unit="TOP/s", ops=2.0 * elems, peak=VALU_LANE_TOPS,
-                    note="2 VALU lane-ops (subtract, fma) per coordinate term")
-    return dict(bound="alu", unit="TOP/s", ops=2.0 * elems, peak=VALU_LANE_TOPS,
-                note="2 VALU lane-ops (subtract, add |t|) per coordinate term")
+        return dict(bound="alu", unit="TFLOP/s", ops=3.0 * elems, peak=FP32_VECTOR_TFLOPS,
+                    note="3 FP32 flops (subtract, fma) per coordinate term on the vector ALU")
+    return dict(bound="alu", unit="TFLOP/s", ops=2.0 * elems, peak=FP32_VECTOR_TFLOPS,
+                note="2 FP32 flops (subtract, add |t|) per coordinate term on the vector ALU")
+
+
+def measured_traffic(workload, kernel_ms):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (FETCH_SIZE/WRITE_SIZE, copy-calibrated), or None when there is no
+    record for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["traffic_bytes"]
+
+
+# Points per set for the CPU oracle's timed sample (full workload when smaller).
+CPU_SAMPLE_POINTS = 250_000
 
 
 def cpu_baseline(args, A, B, metric, eps, T, L, seed):
     import oracle
-    n_a = A.shape[0]
+    n_a = min(A.shape[0], CPU_SAMPLE_POINTS)
+    n_b = min(B.shape[0], CPU_SAMPLE_POINTS)
+    full = n_a == A.shape[0] and n_b == B.shape[0]
+    As, Bs = A[:n_a], B[:n_b]
     t0 = time.perf_counter()
-    ref = oracle.chamfer_estimate(A, B, metric, eps, T, seed, n_scales=L)
+    ref = oracle.chamfer_estimate(As, Bs, metric, eps, T, seed, n_scales=L)
     dt = time.perf_counter() - t0
-    return dict(value=(A.shape[0] + B.shape[0]) / dt, unit="points/s", cores=oracle.threads(),
+    what = (f"full workload (|A|={n_a}, |B|={n_b})" if full else
+            f"the first {n_a} points of A and {n_b} of B (same generator)")
+    return dict(value=(n_a + n_b) / dt, unit="points/s", cores=oracle.threads(),
                 kind="oracle", seconds=dt,
-                sample=f"full workload (|A|={n_a}, |B|={B.shape[0]}), one estimate; "
-                       f"double-precision exact pass on {oracle.threads()} OpenMP threads, "
-                       f"hashing single-threaded"), ref
+                sample=f"{what}, one estimate with the same eps, T and L; double-precision "
+                       f"exact pass on {oracle.threads()} OpenMP threads, hashing "
+                       f"single-threaded"), (ref if full else None)
 
 
 def main():
@@ -134,6 +158,9 @@ def main():
     ap.add_argument("--brute-steps", type=int, default=2)
     ap.add_argument("--no-brute", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run --steps plain device-to-device copies of MIB MiB "
+                         "(calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -141,6 +168,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": args.steps}))
+        return
+
     import paper_2307_03043_amd as ch
     import workloads
 
@@ -199,7 +237,8 @@ def main():
     achieved = work["ops"] / (kernel_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_nnmin (exact pass over the T draws)", "bound": work["bound"],
                 "achieved": achieved, "peak": work["peak"], "unit": work["unit"],
-                "frac": achieved / work["peak"], "traffic": None, "kernel_ms": kernel_ms,
+                "frac": achieved / work["peak"],
+                "traffic": measured_traffic(args.workload, kernel_ms), "kernel_ms": kernel_ms,
                 "algorithmic": work["note"]}
 
     result = {
@@ -244,8 +283,9 @@ def main():
     if not args.no_cpu:
         base, ref = cpu_baseline(args, A, B, metric, eps, T, L, seed)
         result["cpu_baseline"] = base
-        result["accuracy"] = dict(result.get("accuracy", {}),
-                                  oracle_eta=ref["eta"], gpu_vs_oracle_rel=abs(eta - ref["eta"]) / ref["eta"])
+        if ref is not None:
+            result["accuracy"] = dict(result.get("accuracy", {}), oracle_eta=ref["eta"],
+                                      gpu_vs_oracle_rel=abs(eta - ref["eta"]) / ref["eta"])
         print(f"[bench] cpu oracle {base['seconds']:.2f} s", file=sys.stderr, flush=True)
 
     print(json.dumps(result))
