@@ -47,6 +47,9 @@ WORKLOADS = {
     "l1_1m_d64": ("mixed_l1", dict(n=1_000_000, d=64, k=5000), 1, 0.1, 2000, 24,
                   "l1, |A|=|B|=1000000, d=64, 70% 5000-cluster Laplace(0,0.5) mixture + "
                   "30% uniform [-50,50]^64; eps=0.1, T=2000, L=24"),
+    "l2_1m_d256": ("precision_l2", dict(n=1_000_000, d=256, k=10_000), 2, 0.1, 2000, 24,
+                   "l2, |A|=|B|=1000000, d=256, 10000-cluster Gaussian mixture (centres "
+                   "N(0,I), sigma=0.3); eps=0.1, T=2000, L=24"),
     "l2_4k_d16": ("small_l2", dict(n=4096, d=16), 2, 0.2, 512, 15,
                   "l2, |A|=|B|=4096, d=16, 16-centre mixture; eps=0.2, T=512, L=15"),
 }
@@ -148,6 +151,65 @@ def cpu_baseline(args, A, B, metric, eps, T, L, seed):
                        f"single-threaded"), (ref if full else None)
 
 
+def precision_report(args, ch, torch, A, B, At, Bt, metric, eps, T, L, desc):
+    """Exact CH and the estimator with float32, BF16 and FP8-E4M3 distance
+    tiles (float32 re-rank of each row's top candidates, float64 sums).
+    Errors: full CH against the canonical float32 CH (each row of which is
+    within (d+4) 2^-24 relative of float64), and a seeded sample of rows
+    against the float64 oracle."""
+    import oracle
+    n_a, d = A.shape
+    seed = 1
+    rows = np.random.default_rng(7).choice(n_a, size=min(n_a, 1000), replace=False)
+    rows = np.sort(rows).astype(np.int32)
+    t0 = time.perf_counter()
+    m64, a64 = oracle.nn_f64(A, B, metric, rows=rows)
+    oracle_s = time.perf_counter() - t0
+    res = {"workload": desc, "sample_rows": int(len(rows)), "oracle_rows_seconds": oracle_s}
+    ref = {}
+    for prec, name in ((0, "fp32"), (1, "bf16"), (2, "fp8")):
+        ch.chamfer_exact(At, Bt, metric, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.brute_steps):
+            chv, rmin, rnn = ch.chamfer_exact(At, Bt, metric, precision=prec)
+        torch.cuda.synchronize()
+        bt = (time.perf_counter() - t0) / args.brute_steps
+        for _ in range(args.warmup):
+            ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, precision=prec)
+        torch.cuda.synchronize()
+        et = (time.perf_counter() - t0) / args.steps
+        chf = float(chv.item())
+        eta = float(out["eta"].item())
+        rm = rmin.cpu().numpy()
+        rn = rnn.cpu().numpy()
+        if prec == 0:
+            ref = dict(ch=chf, eta=eta, rnn=rn, smin=out["sample_min"].cpu().numpy())
+        rel = np.abs(rm[rows].astype(np.float64) - m64) / np.maximum(m64, 1e-30)
+        res[name] = {
+            "exact_ms": bt * 1e3, "estimate_ms": et * 1e3, "CH": chf, "eta": eta,
+            "exact_points_per_s": 2 * n_a / bt, "estimate_points_per_s": 2 * n_a / et,
+            "CH_rel_err_vs_fp32_canonical": abs(chf - ref["ch"]) / ref["ch"],
+            "rows_exact_argmin_frac": float(np.mean(rn == ref["rnn"])),
+            "sampled_rows_vs_fp64": {"max_rel_err": float(rel.max()),
+                                      "mean_rel_err": float(rel.mean()),
+                                      "argmin_match_frac": float(np.mean(rn[rows] == a64))},
+            "eta_rel_err_vs_fp32_eta": abs(eta - ref["eta"]) / ref["eta"],
+            "eta_rel_err_vs_CH": abs(eta - ref["ch"]) / ref["ch"],
+            "sample_min_exact_frac": float(np.mean(out["sample_min"].cpu().numpy() == ref["smin"])),
+        }
+        print(f"[bench] {name}: exact {bt * 1e3:.1f} ms, estimate {et * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+    for name in ("bf16", "fp8"):
+        res[name]["exact_speedup_vs_fp32"] = res["fp32"]["exact_ms"] / res[name]["exact_ms"]
+        res[name]["estimate_speedup_vs_fp32"] = res["fp32"]["estimate_ms"] / res[name]["estimate_ms"]
+    return {"precision_report": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +220,9 @@ def main():
     ap.add_argument("--brute-steps", type=int, default=2)
     ap.add_argument("--no-brute", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="time exact CH and the estimator in FP32, BF16 and FP8 and report "
+                         "their errors (l2 workloads)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run --steps plain device-to-device copies of MIB MiB "
                          "(calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -191,6 +256,11 @@ def main():
     Bt = torch.from_numpy(B).to(dev)
     torch.cuda.synchronize()
     seed = 1
+
+    if args.precision_report:
+        print(json.dumps(precision_report(args, ch, torch, A, B, At, Bt, metric, eps, T, L,
+                                          desc)))
+        return
 
     def step():
         return ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, with_aux=False)

@@ -135,8 +135,12 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_partial = take((size_t)(nn_finalize_blocks(nrow) + 1) * sizeof(double));
     pl.off_nb2 = take(mfma_supported(d, metric) ? (size_t)nB * sizeof(float) : 0);
     pl.off_fallback = take(0);
-    pl.off_lowp = take(0);
-    pl.off_lowpnorm = take(0);
+    // low precision: cast rows of B and of the queries, scales and norms
+    const bool lp = lowp_supported(d, metric, pl.precision);
+    const size_t rb = lp ? lowp_row_bytes(d, pl.precision) : 0;
+    pl.off_bq = take(rb * (size_t)nB);
+    pl.off_xq = take(rb * (size_t)nrow);
+    pl.off_lpf = take(lp ? 2 * ((size_t)nB + (size_t)nrow) * sizeof(float) : 0);
     pl.total = off;
     return CHAMFER_OK;
 }
@@ -215,6 +219,27 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
     return CHAMFER_OK;
 }
 
+// Exact pass over queries (rows of X, or X[rows[q]]): the low-precision
+// form when requested and supported, else the float32 form (MFMA for l2
+// when nb2 is given, vector ALU otherwise).
+int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64_t nx,
+            const float *B, int64_t nB, unsigned long long *best, float *nb2, DevParams *p,
+            hipStream_t st) {
+    if (lowp_supported(pl.d, pl.metric, pl.precision)) {
+        uint8_t *bq = at<uint8_t>(ws, pl.off_bq);
+        uint8_t *xq = at<uint8_t>(ws, pl.off_xq);
+        float *lpf = at<float>(ws, pl.off_lpf);
+        float *bsc = lpf, *bn2 = lpf + nB, *xsc = lpf + 2 * nB, *xn2 = xsc + nx;
+        CH_TRY(launch_cast_rows(pl.precision, B, nullptr, nB, pl.d, bq, bsc, bn2, p, st));
+        CH_TRY(launch_cast_rows(pl.precision, X, rows, nx, pl.d, xq, xsc, xn2, p, st));
+        CH_TRY(launch_nnmin_lowp(pl.precision, xq, xsc, nx, X, rows, bq, bsc, bn2, B, nB, pl.d,
+                                 best, p, st));
+        return CHAMFER_OK;
+    }
+    CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, nb2, p, st));
+    return CHAMFER_OK;
+}
+
 __global__ void k_store_zero(double *out, int32_t *status) {
     if (threadIdx.x == 0) {
         if (out) *out = 0.0;
@@ -258,11 +283,12 @@ int chamfer_exact(const float *A, const float *B, int64_t n_A, int64_t n_B, int3
     CH_TRY(launch_calib_final(lohi, d, p, st));
     CH_TRY(launch_fill_u64(best, n_A, ~0ull, st));
     float *nb2 = nullptr;
-    if (mfma_supported(d, metric)) {
+    const bool lp = lowp_supported(d, metric, pl.precision);
+    if (!lp && mfma_supported(d, metric)) {
         nb2 = at<float>(ws, pl.off_nb2);
         CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
     }
-    CH_TRY(launch_nnmin(A, nullptr, n_A, B, n_B, d, metric, best, nb2, p, st));
+    if ((rc = nn_pass(pl, ws, A, nullptr, n_A, B, n_B, best, nb2, p, st))) return rc;
     CH_TRY(launch_nn_finalize(best, n_A, metric, rowmin_out, rownn_out, partial, p, st));
     CH_TRY(launch_sum_final(partial, nn_finalize_blocks(n_A), p, ch_out, st));
     return CHAMFER_OK;
@@ -283,11 +309,12 @@ int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float
     CH_TRY(launch_init_params(p, nullptr, d, st));
     CH_TRY(launch_fill_u64(best, n_x, ~0ull, st));
     float *nb2 = nullptr;
-    if (mfma_supported(d, metric)) {
+    const bool lp = lowp_supported(d, metric, pl.precision);
+    if (!lp && mfma_supported(d, metric)) {
         nb2 = at<float>(ws, pl.off_nb2);
         CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
     }
-    CH_TRY(launch_nnmin(X, rows, n_x, B, n_B, d, metric, best, nb2, p, st));
+    if ((rc = nn_pass(pl, ws, X, rows, n_x, B, n_B, best, nb2, p, st))) return rc;
     CH_TRY(launch_nn_finalize(best, n_x, metric, min_out, arg_out, nullptr, p, st));
     return CHAMFER_OK;
 }
@@ -337,7 +364,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
     CH_TRY(mark(ev, 4, st));
-    CH_TRY(launch_nnmin(A, idx, pl.T, B, n_B, d, metric, best, nb2, p, st));
+    if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st))) return rc;
     CH_TRY(mark(ev, 5, st));
     CH_TRY(launch_estimate_final(best, idx, D, pl.T, metric, p, eta_out, ax, st));
     CH_TRY(mark(ev, 6, st));

@@ -141,7 +141,7 @@ struct Plan {
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
         off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_fallback,
-        off_lowp, off_lowpnorm, total;
+        off_bq, off_xq, off_lpf, total;
 };
 
 // Row block of the fixed-point scan: 256 threads x 4 items.
@@ -187,6 +187,18 @@ bool mfma_supported(int d, int metric);
 hipError_t launch_nnmin_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
                              int64_t nB, int d, unsigned long long *best, const float *nb2,
                              DevParams *p, hipStream_t st);
+// Low-precision (BF16 / FP8-E4M3) l2 nearest neighbours with float32 re-rank.
+int lowp_dpad(int d, int precision);
+bool lowp_supported(int d, int metric, int precision);
+size_t lowp_row_bytes(int d, int precision);
+hipError_t launch_cast_rows(int precision, const float *X, const int32_t *rows, int64_t n, int d,
+                            uint8_t *out, float *scale, float *n2, const DevParams *p,
+                            hipStream_t st);
+hipError_t launch_nnmin_lowp(int precision, const uint8_t *Xq, const float *xsc, int64_t nx,
+                             const float *X, const int32_t *rows, const uint8_t *Bq,
+                             const float *bsc, const float *bn2, const float *B, int64_t nB,
+                             int d, unsigned long long *best, const DevParams *p,
+                             hipStream_t st);
 hipError_t launch_nn_finalize(const unsigned long long *best, int64_t nx, int metric,
                               float *min_out, int32_t *arg_out, double *partial,
                               const DevParams *p, hipStream_t st);

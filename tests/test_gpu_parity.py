@@ -246,3 +246,66 @@ def test_coverage_small_config(ch, orc):
     frac = np.mean(np.abs(etas - exact) <= 0.2 * exact)
     print(f"coverage {frac:.4f} mean rel err {np.mean(np.abs(etas - exact)) / exact:.4e}")
     assert frac >= 0.99
+
+
+# ------------------------------------------------- precision (BF16 / FP8) --
+
+PRECISIONS = [(1, "bf16", 0.99, 1e-3), (2, "fp8", 0.90, 1e-2)]
+
+
+@pytest.mark.parametrize("prec,name,min_exact,ch_tol", PRECISIONS)
+@pytest.mark.parametrize("shape", [(1000, 1500, 16), (700, 2000, 64), (513, 3001, 128),
+                                   (300, 2500, 200), (257, 2049, 256)])
+def test_lowp_exact_rerank(ch, orc, prec, name, min_exact, ch_tol, shape):
+    """Low-precision tiles + float32 re-rank: every reported minimum is the
+    canonical float32 distance to the reported row (so never below the true
+    minimum), most arg-mins are exact, and CH is within the stated error."""
+    n_a, n_b, d = shape
+    banner(f"lowp {name} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=d + prec)
+    chv, rmin, rnn = ch.chamfer_exact(dev(A), dev(B), 2, precision=prec)
+    rmin, rnn = host(rmin), host(rnn)
+    m32, a32 = orc.nn_f32(A, B, 2)
+    m64, _ = orc.nn_f64(A, B, 2)
+    chosen = np.array([orc.dist32(A[i], B[rnn[i]], 2) for i in range(n_a)], np.float32)
+    assert np.array_equal(chosen.view(np.uint32), rmin.view(np.uint32))
+    assert np.all(rmin >= m32)
+    frac = np.mean(rnn == a32)
+    err = abs(float(host(chv)[0]) - math.fsum(m64.tolist())) / math.fsum(m64.tolist())
+    print(f"{name} d={d}: exact arg-min {frac:.4f}, CH rel err {err:.2e}")
+    assert frac >= min_exact
+    assert err <= ch_tol
+
+
+@pytest.mark.parametrize("prec,name,min_exact,ch_tol", PRECISIONS)
+def test_lowp_estimate(ch, orc, prec, name, min_exact, ch_tol):
+    """The estimator with a low-precision exact pass: CrudeNN and the draws
+    are the float32 path's (bit-exact); each sample minimum is a true float32
+    distance, never below the oracle's minimum."""
+    A, B = workloads.precision_l2(seed=3, n=3000, d=256, k=60)
+    T = 400
+    out = ch.chamfer_estimate(dev(A), dev(B), 2, 0.1, T, 11, precision=prec)
+    ref = ch.chamfer_estimate(dev(A), dev(B), 2, 0.1, T, 11)
+    assert torch.equal(out["sample_idx"], ref["sample_idx"])
+    assert torch.equal(out["crude_D"], ref["crude_D"])
+    m = host(out["sample_min"])
+    m32 = host(ref["sample_min"])
+    assert np.all(m >= m32)
+    assert np.mean(m == m32) >= min_exact
+    e_lp, e_32 = float(host(out["eta"])[0]), float(host(ref["eta"])[0])
+    assert abs(e_lp - e_32) / e_32 <= ch_tol
+
+
+def test_lowp_deterministic(ch):
+    A, B = workloads.precision_l2(seed=4, n=2000, d=128, k=40)
+    a, b = dev(A), dev(B)
+    for prec in (1, 2):
+        r = [ch.chamfer_exact(a, b, 2, precision=prec) for _ in range(2)]
+        assert torch.equal(r[0][1], r[1][1]) and torch.equal(r[0][2], r[1][2])
+
+
+def test_lowp_l1_ignores_precision(ch, orc):
+    A, B = clouds(300, 400, 64, seed=9)
+    _, rmin, rnn = ch.chamfer_exact(dev(A), dev(B), 1, precision=1)
+    m32, a32 = orc.nn_f32(A, B, 1)
+    assert np.array_equal(host(rnn), a32)
