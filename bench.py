@@ -210,6 +210,109 @@ def precision_report(args, ch, torch, A, B, At, Bt, metric, eps, T, L, desc):
     return {"precision_report": res}
 
 
+SERVE_POOL_SURFACES = 64
+SERVE_POOL_CLUSTERS = 8
+SERVE_N_MAX = 200_000
+
+
+def serve_pool(torch, workloads):
+    """Pinned host pool of cloud pairs at the largest request size; a request
+    uses prefixes of one pair (its points are i.i.d., so a prefix is a sample
+    of the same cloud)."""
+    pool = {"surface": [], "clusters": []}
+    for e in range(SERVE_POOL_SURFACES):
+        rng = np.random.default_rng(1000 + e)
+        a, b = workloads.surface_pair(rng, SERVE_N_MAX, SERVE_N_MAX)
+        pool["surface"].append((torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory()))
+    for e in range(SERVE_POOL_CLUSTERS):
+        rng = np.random.default_rng(2000 + e)
+        centres = 4.0 * rng.standard_normal((64, 128))
+        sig = rng.uniform(0.2, 1.0, size=64)
+        a = workloads.mixture(rng, SERVE_N_MAX, centres, sig).astype(np.float32)
+        b = workloads.mixture(rng, SERVE_N_MAX, centres, sig).astype(np.float32)
+        pool["clusters"].append((torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory()))
+    return pool
+
+
+def serve_run(ch, reqs, pool, arena, slots, precision, saturate=False):
+    """Drive the server in real time: submit each request at its arrival
+    time (or all at t = 0 when saturating), progress, drain results."""
+    n = len(reqs)
+    etas = np.zeros(n)
+    lat = np.zeros(n)
+    wait = np.zeros(n)
+    id2i = {}
+    done = 0
+    with ch.ChamferServer(arena, slots) as srv:
+        t0 = time.monotonic()
+        i = 0
+        in_flight_sum = 0
+        polls = 0
+        while done < n:
+            now = time.monotonic() - t0
+            while i < n and (saturate or reqs[i].arrival_s <= now):
+                r = reqs[i]
+                src = pool[r.kind][r.rid % len(pool[r.kind])]
+                prec = precision if (r.metric == 2 and r.d >= 12) else 0
+                rid = srv.submit(src[0][:r.n_a], src[1][:r.n_b], r.metric, r.eps, 0, r.seed,
+                                 precision=prec)
+                id2i[rid] = i
+                i += 1
+            srv.progress()
+            for res in srv.results():
+                k = id2i.pop(res["id"])
+                arrival = t0 + (0.0 if saturate else reqs[k].arrival_s)
+                lat[k] = res["done_s"] - arrival
+                wait[k] = res["admit_s"] - arrival
+                etas[k] = res["eta"] if res["status"] == 0 else np.nan
+                done += 1
+            st = srv.stats()
+            in_flight_sum += st["in_flight"]
+            polls += 1
+        wall = time.monotonic() - t0
+        st = srv.stats()
+    return dict(completed=done, wall_s=wall, req_per_s=done / wall,
+                p50_ms=float(np.percentile(lat, 50) * 1e3),
+                p99_ms=float(np.percentile(lat, 99) * 1e3),
+                max_ms=float(lat.max() * 1e3),
+                admit_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
+                mean_in_flight=in_flight_sum / max(polls, 1),
+                arena_peak_gib=st["arena_peak"] / 2**30, failed=int(np.isnan(etas).sum())), etas
+
+
+def serve_bench(args, ch, torch, workloads):
+    reqs = workloads.serving_stream(seed=args.seed, count=args.requests, rate_hz=args.rate)
+    pool = serve_pool(torch, workloads)
+    arena = int(args.arena_gib * 2**30)
+    out = {"workload": (f"{args.requests} requests, Poisson {args.rate} req/s; 80% d=3 surface "
+                        f"clouds, 20% d=128 clusters; sizes log-uniform [1k, 200k]; l2 70% / "
+                        f"l1 30%; eps in {{0.1, 0.2}}; arena {args.arena_gib} GiB, "
+                        f"{args.slots} slots"),
+           "mix": {"d128": sum(r.d == 128 for r in reqs), "l2": sum(r.metric == 2 for r in reqs)}}
+    # warm up kernels and the allocator
+    serve_run(ch, reqs[:64], pool, arena, args.slots, 0, saturate=True)
+    serve_run(ch, reqs[:64], pool, arena, args.slots, 1, saturate=True)
+    for name, prec in (("fp32", 0), ("bf16", 1)):
+        res, eta = serve_run(ch, reqs, pool, arena, args.slots, prec)
+        sat, _ = serve_run(ch, reqs, pool, arena, args.slots, prec, saturate=True)
+        res["saturated"] = {k: sat[k] for k in ("req_per_s", "p50_ms", "p99_ms", "wall_s")}
+        out[name] = res
+        out[name + "_eta"] = eta
+        print(f"[bench] serve {name}: p50 {res['p50_ms']:.2f} ms, p99 {res['p99_ms']:.2f} ms, "
+              f"{res['req_per_s']:.0f} req/s; saturated {sat['req_per_s']:.0f} req/s",
+              file=sys.stderr, flush=True)
+    e32, e16 = out.pop("fp32_eta"), out.pop("bf16_eta")
+    rel = np.abs(e16 - e32) / np.maximum(np.abs(e32), 1e-300)
+    d128 = np.array([r.d == 128 and r.metric == 2 for r in reqs])
+    out["bf16_vs_fp32"] = {"p99_speedup": out["fp32"]["p99_ms"] / out["bf16"]["p99_ms"],
+                           "saturated_throughput_ratio": out["bf16"]["saturated"]["req_per_s"]
+                           / out["fp32"]["saturated"]["req_per_s"],
+                           "eta_max_rel_diff": float(rel.max()),
+                           "eta_max_rel_diff_d128_l2": float(rel[d128].max()) if d128.any() else 0.0,
+                           "identical_eta_frac": float(np.mean(e16 == e32))}
+    return {"serving": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +326,13 @@ def main():
     ap.add_argument("--precision-report", action="store_true",
                     help="time exact CH and the estimator in FP32, BF16 and FP8 and report "
                          "their errors (l2 workloads)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: Poisson stream of mixed requests through the "
+                         "continuous-batching server, FP32 and BF16-refined")
+    ap.add_argument("--requests", type=int, default=20000)
+    ap.add_argument("--rate", type=float, default=500.0)
+    ap.add_argument("--arena-gib", type=float, default=8.0)
+    ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run --steps plain device-to-device copies of MIB MiB "
                          "(calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -246,6 +356,10 @@ def main():
 
     import paper_2307_03043_amd as ch
     import workloads
+
+    if args.serve:
+        print(json.dumps(serve_bench(args, ch, torch, workloads)))
+        return
 
     gen, kw, metric, eps, T, L, desc = WORKLOADS[args.workload]
     A, B = getattr(workloads, gen)(seed=args.seed, **kw)

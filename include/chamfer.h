@@ -179,6 +179,63 @@ int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float
                    int64_t n_B, int32_t d, int32_t metric, float *min_out, int32_t *arg_out,
                    const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Serving: continuous batching of chamfer_estimate requests.
+ *
+ * A server owns one device arena of arena_bytes (allocated once, by
+ * chamfer_server_create; nothing is allocated afterwards) and `slots` request
+ * slots, each with its own stream.  chamfer_server_submit queues a request
+ * (host side only).  chamfer_server_progress admits queued requests while a
+ * slot is free and the arena can hold the request's footprint (its two
+ * point sets, its workspace and its outputs), copies the inputs in and
+ * enqueues the estimate on the slot's stream, and retires finished requests,
+ * which frees their slot and memory at once; it never blocks.  Admission is
+ * first-in first-out with a look-ahead of 8 requests past a head that does
+ * not fit.  chamfer_server_results drains finished requests.  A request's
+ * host arrays A, B (row-major float32; pinned memory makes the copy-in
+ * asynchronous) must stay valid until its result is drained.  Results are
+ * bit-identical to a direct chamfer_estimate call with the same arguments.
+ * A server is not thread-safe: call it from one host thread.
+ * Errors: EINVAL for bad arguments (as chamfer_estimate), EWORKSPACE if a
+ * request can never fit the arena, EHIP for runtime failures (a failed
+ * request is also reported through its result's status).
+ */
+typedef struct chamfer_server chamfer_server;
+
+typedef struct chamfer_request {
+    const float *A, *B;  /* host [n_A, d], [n_B, d] */
+    int64_t n_A, n_B;
+    int32_t d, metric;
+    double eps;
+    int64_t T;           /* 0 => default */
+    uint64_t seed;
+    chamfer_opts opts;
+} chamfer_request;
+
+typedef struct chamfer_result {
+    uint64_t id;         /* as returned by chamfer_server_submit */
+    int32_t status;      /* CHAMFER_OK, CHAMFER_ENONFINITE or a launch error */
+    int32_t s;           /* fixed-point exponent */
+    double eta;          /* the estimate */
+    double D;            /* normaliser */
+    uint64_t W;
+    double submit_s, admit_s, done_s;  /* host steady-clock seconds */
+    size_t footprint;    /* arena bytes the request held */
+} chamfer_result;
+
+typedef struct chamfer_server_stat {
+    int64_t queued;
+    int32_t in_flight;
+    size_t arena_bytes, arena_used, arena_peak;
+} chamfer_server_stat;
+
+int chamfer_server_create(size_t arena_bytes, int32_t slots, chamfer_server **out);
+int chamfer_server_submit(chamfer_server *srv, const chamfer_request *req, uint64_t *id_out);
+int chamfer_server_progress(chamfer_server *srv); /* returns requests finished */
+int chamfer_server_results(chamfer_server *srv, chamfer_result *out, int32_t max);
+int chamfer_server_stats(const chamfer_server *srv, chamfer_server_stat *out);
+int chamfer_server_destroy(chamfer_server *srv);
+
 /* Host helpers (no device work). */
 int64_t chamfer_default_samples(int64_t n_A, double eps);            /* T default */
 int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps); /* L default */

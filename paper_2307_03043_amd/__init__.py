@@ -70,6 +70,12 @@ _SIGS = {
     "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
     "chamfer_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "chamfer_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, _VP]),
+    "chamfer_server_submit": (ctypes.c_int, [_VP, _VP, _VP]),
+    "chamfer_server_progress": (ctypes.c_int, [_VP]),
+    "chamfer_server_results": (ctypes.c_int, [_VP, _VP, _I32]),
+    "chamfer_server_stats": (ctypes.c_int, [_VP, _VP]),
+    "chamfer_server_destroy": (ctypes.c_int, [_VP]),
 }
 
 
@@ -302,3 +308,102 @@ def chamfer_hash_keys(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):
                                    _ptr(kb), _ptr(et), ctypes.byref(o), _ptr(ws), ws.numel(),
                                    _stream(dev)), "chamfer_hash_keys")
     return ka, kb, et
+
+
+# -------------------------------------------------------------- serving ---
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("n_A", ctypes.c_int64),
+                ("n_B", ctypes.c_int64), ("d", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("T", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("opts", Opts)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("s", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("D", ctypes.c_double), ("W", ctypes.c_uint64),
+                ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
+class ServerStat(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("in_flight", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t)]
+
+
+def chamfer_server_create(arena_bytes: int, slots: int = 16):
+    h = ctypes.c_void_p()
+    _check(lib().chamfer_server_create(arena_bytes, slots, ctypes.byref(h)),
+           "chamfer_server_create")
+    return h
+
+
+class ChamferServer:
+    """Continuous-batching server (see chamfer_server_* in chamfer.h).
+
+    Host point sets are numpy float32 arrays or CPU torch tensors (pinned
+    tensors make the copy-in asynchronous); they are kept alive here until the
+    request's result has been drained."""
+
+    def __init__(self, arena_bytes: int, slots: int = 16):
+        self.h = chamfer_server_create(arena_bytes, slots)
+        self._keep = {}
+
+    @staticmethod
+    def _host_ptr(x, name):
+        if hasattr(x, "data_ptr"):
+            if x.is_cuda or x.dtype.__str__() != "torch.float32" or not x.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous float32 CPU tensor")
+            return x.data_ptr(), x.shape
+        x = np.ascontiguousarray(x)
+        if x.dtype != np.float32:
+            raise TypeError(f"{name} must be float32")
+        return x.ctypes.data, x.shape
+
+    def submit(self, A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0, precision=0):
+        pa, sa = self._host_ptr(A, "A")
+        pb, sb = self._host_ptr(B, "B")
+        if len(sa) != 2 or len(sb) != 2 or sa[1] != sb[1]:
+            raise ValueError("A and B must be [n, d] with the same d")
+        req = Request(pa, pb, sa[0], sb[0], sa[1], metric, eps, T, seed,
+                      _opts(n_scales, embed_dim, precision))
+        rid = ctypes.c_uint64()
+        _check(lib().chamfer_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)),
+               "chamfer_server_submit")
+        self._keep[rid.value] = (A, B)
+        return rid.value
+
+    def progress(self) -> int:
+        n = lib().chamfer_server_progress(self.h)
+        if n < 0:
+            raise ChamferError(n, "chamfer_server_progress")
+        return n
+
+    def results(self, max_n: int = 1024):
+        buf = (Result * max_n)()
+        n = lib().chamfer_server_results(self.h, buf, max_n)
+        if n < 0:
+            raise ChamferError(n, "chamfer_server_results")
+        out = []
+        for i in range(n):
+            r = buf[i]
+            self._keep.pop(r.id, None)
+            out.append({f: getattr(r, f) for f, _ in Result._fields_})
+        return out
+
+    def stats(self):
+        st = ServerStat()
+        _check(lib().chamfer_server_stats(self.h, ctypes.byref(st)), "chamfer_server_stats")
+        return {f: getattr(st, f) for f, _ in ServerStat._fields_}
+
+    def close(self):
+        if self.h is not None:
+            lib().chamfer_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -36,7 +36,7 @@ int lowp_dpad(int d, int precision) {
 }
 
 bool lowp_supported(int d, int metric, int precision) {
-    return metric == CHAMFER_L2 && precision != CHAMFER_FP32 && d >= 1 && d <= 256;
+    return metric == CHAMFER_L2 && precision != CHAMFER_FP32 && d >= 12 && d <= 256;
 }
 
 size_t lowp_row_bytes(int d, int precision) {

@@ -111,3 +111,14 @@ def test_argument_errors_are_host_side():
                         1 << 20, None) == -1
     assert lib.chamfer_nn_min(dummy, None, -1, dummy, 5, 3, 2, None, None, None, dummy, 1 << 20,
                               None) == -1
+
+
+def test_server_argument_errors_are_host_side():
+    lib = ch.lib()
+    h = ctypes.c_void_p()
+    assert lib.chamfer_server_create(1 << 20, 0, ctypes.byref(h)) == -1
+    assert lib.chamfer_server_create(1 << 20, 1000, ctypes.byref(h)) == -1
+    assert lib.chamfer_server_create(16, 4, ctypes.byref(h)) == -1
+    assert lib.chamfer_server_submit(None, None, None) == -1
+    assert lib.chamfer_server_progress(None) == -1
+    assert lib.chamfer_server_destroy(None) == -1
