@@ -221,16 +221,21 @@ void or_hash_keys(const float *X, int64_t n, int d, int metric, const float *lo,
                   const uint64_t *mult, uint64_t *keys)
 {
     int kh = metric == OR_L1 ? d : ke;
-    float *y = (float *)malloc(sizeof(float) * (size_t)kh);
-    for (int64_t p = 0; p < n; ++p) {
-        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
-        for (int i = 0; i < L; ++i) {
-            int e = e_top - (L - 1 - i);
-            keys[(size_t)i * n + p] =
-                bucket_key(y, kh, e, zfrac + (size_t)i * kh, mult + (size_t)i * kh);
+    /* points are independent; the loop is split over threads */
+#pragma omp parallel
+    {
+        float *y = (float *)malloc(sizeof(float) * (size_t)kh);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
+            for (int i = 0; i < L; ++i) {
+                int e = e_top - (L - 1 - i);
+                keys[(size_t)i * n + p] =
+                    bucket_key(y, kh, e, zfrac + (size_t)i * kh, mult + (size_t)i * kh);
+            }
         }
+        free(y);
     }
-    free(y);
 }
 
 /* Canonical single-precision distance (see header). */
@@ -289,6 +294,7 @@ void or_crude_nn(const uint64_t *keysA, int64_t nA, const uint64_t *keysB, int64
     for (int i = 0; i < L; ++i) {
         for (int64_t b = 0; b < nB; ++b) { tab[b].key = keysB[(size_t)i * nB + b]; tab[b].idx = b; }
         qsort(tab, (size_t)nB, sizeof(kv_t), kv_cmp);
+#pragma omp parallel for schedule(static)
         for (int64_t a = 0; a < nA; ++a) {
             if (scale_out[a] >= 0) continue;
             uint64_t k = keysA[(size_t)i * nA + a];
@@ -300,6 +306,7 @@ void or_crude_nn(const uint64_t *keysA, int64_t nA, const uint64_t *keysB, int64
             if (lo < nB && tab[lo].key == k) { scale_out[a] = i; nn_out[a] = (int32_t)tab[lo].idx; }
         }
     }
+#pragma omp parallel for schedule(static)
     for (int64_t a = 0; a < nA; ++a) {
         if (scale_out[a] < 0) { scale_out[a] = L; nn_out[a] = 0; }
         D_out[a] = or_dist32(A + (size_t)a * d, B + (size_t)nn_out[a] * d, d, metric);

@@ -1,0 +1,93 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+For each workload the GPU estimate (same generator, seed, eps, T, L) is
+compared with the oracle run on the full inputs: CrudeNN (scale, candidate,
+D_a bits) for every point, the fixed-point exponent and total, every sampled
+index, the sample minima (float64 oracle, 1e-5 relative; canonical float32
+arg-min bit-exact) and eta.  Exact CH is checked on a seeded sample of rows
+(canonical float32 bit-exact, float64 within 1e-5), since the float64 oracle
+over all 10^12 pairs does not fit a test.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+CONFIGS = {
+    # name: generator, kwargs, metric, eps, T, L, rows of T checked in float64
+    "l2_100k_d128": ("clusters_l2", dict(n=100_000, d=128, k=1000), 2, 0.1, 2000, 20, 2000),
+    "l1_1m_d64": ("mixed_l1", dict(n=1_000_000, d=64, k=5000), 1, 0.1, 2000, 24, 2000),
+    "l2_1m_d256": ("precision_l2", dict(n=1_000_000, d=256, k=10_000), 2, 0.1, 2000, 24, 300),
+}
+
+
+@pytest.fixture(scope="module")
+def ch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_03043_amd as lib
+    lib.lib()
+    return lib
+
+
+_data = {}
+
+
+def data(name):
+    if name not in _data:
+        _data.clear()
+        gen, kw, *_ = CONFIGS[name]
+        A, B = getattr(workloads, gen)(seed=42, **kw)
+        _data[name] = (A, B, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    return _data[name]
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_fullsize_estimate(ch, orc, name):
+    print(f"[case] fullsize estimate {name}", flush=True)
+    gen, kw, metric, eps, T, L, nrows = CONFIGS[name]
+    A, B, At, Bt = data(name)
+    out = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L)
+    torch.cuda.synchronize()
+    crude = orc.crude_nn(A, B, metric, eps, 1, n_scales=L)
+    assert np.array_equal(out["crude_scale"].cpu().numpy(), crude["scale"])
+    assert np.array_equal(out["crude_nn"].cpu().numpy(), crude["nn"])
+    assert np.array_equal(out["crude_D"].cpu().numpy().view(np.uint32), crude["D"].view(np.uint32))
+    s, w, P, W, zero = orc.weights(crude["D"])
+    assert int(out["s"].item()) == s and int(out["W"].item()) == W
+    idx = orc.sample(1, P, W, T)
+    assert np.array_equal(out["sample_idx"].cpu().numpy(), idx)
+    sm = out["sample_min"].cpu().numpy()
+    m64, _ = orc.nn_f64(A, B, metric, rows=idx[:nrows])
+    np.testing.assert_allclose(sm[:nrows], m64, rtol=REL, atol=0)
+    m32, a32 = orc.nn_f32(A, B, metric, rows=idx[:nrows])
+    assert np.array_equal(out["sample_nn"].cpu().numpy()[:nrows], a32)
+    assert np.array_equal(sm[:nrows].view(np.uint32), m32.view(np.uint32))
+    if nrows == T:
+        eta = math.fsum(((float(W) / float(w[i])) * m for i, m in zip(idx.tolist(), m64.tolist()))) / T
+        assert float(out["eta"].item()) == pytest.approx(eta, rel=REL)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_fullsize_exact_rows(ch, orc, name):
+    print(f"[case] fullsize exact {name}", flush=True)
+    gen, kw, metric, eps, T, L, nrows = CONFIGS[name]
+    A, B, At, Bt = data(name)
+    chv, rmin, rnn = ch.chamfer_exact(At, Bt, metric)
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(3).choice(A.shape[0], size=300, replace=False)).astype(np.int32)
+    m32, a32 = orc.nn_f32(A, B, metric, rows=rows)
+    m64, _ = orc.nn_f64(A, B, metric, rows=rows)
+    got_min = rmin.cpu().numpy()[rows]
+    assert np.array_equal(rnn.cpu().numpy()[rows], a32)
+    assert np.array_equal(got_min.view(np.uint32), m32.view(np.uint32))
+    np.testing.assert_allclose(got_min, m64, rtol=REL, atol=0)
+    assert math.isfinite(float(chv.item()))
