@@ -234,8 +234,8 @@ def serve_pool(torch, workloads):
     return pool
 
 
-def serve_run(ch, reqs, pool, arena, slots, precision, saturate=False):
-    """Drive the server in real time: submit each request at its arrival
+def serve_run(srv, reqs, pool, precision, saturate=False):
+    """Drive a server in real time: submit each request at its arrival
     time (or all at t = 0 when saturating), progress, drain results."""
     n = len(reqs)
     etas = np.zeros(n)
@@ -243,41 +243,47 @@ def serve_run(ch, reqs, pool, arena, slots, precision, saturate=False):
     wait = np.zeros(n)
     id2i = {}
     done = 0
-    with ch.ChamferServer(arena, slots) as srv:
-        t0 = time.monotonic()
-        i = 0
-        in_flight_sum = 0
-        polls = 0
-        while done < n:
-            now = time.monotonic() - t0
-            while i < n and (saturate or reqs[i].arrival_s <= now):
-                r = reqs[i]
-                src = pool[r.kind][r.rid % len(pool[r.kind])]
-                prec = precision if (r.metric == 2 and r.d >= 12) else 0
-                rid = srv.submit(src[0][:r.n_a], src[1][:r.n_b], r.metric, r.eps, 0, r.seed,
-                                 precision=prec)
-                id2i[rid] = i
-                i += 1
-            srv.progress()
-            for res in srv.results():
-                k = id2i.pop(res["id"])
-                arrival = t0 + (0.0 if saturate else reqs[k].arrival_s)
-                lat[k] = res["done_s"] - arrival
-                wait[k] = res["admit_s"] - arrival
-                etas[k] = res["eta"] if res["status"] == 0 else np.nan
-                done += 1
-            st = srv.stats()
-            in_flight_sum += st["in_flight"]
-            polls += 1
-        wall = time.monotonic() - t0
+    st0 = srv.stats()
+    t0 = time.monotonic()
+    i = 0
+    in_flight_sum = 0
+    polls = 0
+    while done < n:
+        now = time.monotonic() - t0
+        while i < n and (saturate or reqs[i].arrival_s <= now):
+            r = reqs[i]
+            src = pool[r.kind][r.rid % len(pool[r.kind])]
+            prec = precision if (r.metric == 2 and r.d >= 12) else 0
+            rid = srv.submit(src[0][:r.n_a], src[1][:r.n_b], r.metric, r.eps, 0, r.seed,
+                             precision=prec)
+            id2i[rid] = i
+            i += 1
+        srv.progress()
+        for res in srv.results():
+            k = id2i.pop(res["id"])
+            arrival = t0 + (0.0 if saturate else reqs[k].arrival_s)
+            lat[k] = res["done_s"] - arrival
+            wait[k] = res["admit_s"] - arrival
+            etas[k] = res["eta"] if res["status"] == 0 else np.nan
+            done += 1
         st = srv.stats()
+        in_flight_sum += st["in_flight"]
+        polls += 1
+    wall = time.monotonic() - t0
+    st = srv.stats()
+    batches = st["batches"] - st0["batches"]
     return dict(completed=done, wall_s=wall, req_per_s=done / wall,
                 p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3),
                 max_ms=float(lat.max() * 1e3),
                 admit_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 mean_in_flight=in_flight_sum / max(polls, 1),
+                batches=batches, mean_batch=(st["batched"] - st0["batched"]) / max(batches, 1),
+                admission_stalls=st["stalls"] - st0["stalls"],
                 arena_peak_gib=st["arena_peak"] / 2**30, failed=int(np.isnan(etas).sum())), etas
+
+
+SERVE_CLASSES = ((3, 1), (3, 2), (128, 1), (128, 2))
 
 
 def serve_bench(args, ch, torch, workloads):
@@ -287,21 +293,28 @@ def serve_bench(args, ch, torch, workloads):
     out = {"workload": (f"{args.requests} requests, Poisson {args.rate} req/s; 80% d=3 surface "
                         f"clouds, 20% d=128 clusters; sizes log-uniform [1k, 200k]; l2 70% / "
                         f"l1 30%; eps in {{0.1, 0.2}}; arena {args.arena_gib} GiB, "
-                        f"{args.slots} slots"),
+                        f"{args.lanes} batch lanes"),
            "mix": {"d128": sum(r.d == 128 for r in reqs), "l2": sum(r.metric == 2 for r in reqs)}}
-    # warm up kernels and the allocator
-    serve_run(ch, reqs[:64], pool, arena, args.slots, 0, saturate=True)
-    serve_run(ch, reqs[:64], pool, arena, args.slots, 1, saturate=True)
+    etas = {}
     for name, prec in (("fp32", 0), ("bf16", 1)):
-        res, eta = serve_run(ch, reqs, pool, arena, args.slots, prec)
-        sat, _ = serve_run(ch, reqs, pool, arena, args.slots, prec, saturate=True)
-        res["saturated"] = {k: sat[k] for k in ("req_per_s", "p50_ms", "p99_ms", "wall_s")}
+        with ch.ChamferServer(arena, args.lanes) as srv:
+            # graphs of every request class on every lane, then a short burst
+            # to warm the kernels and the host paths
+            for d, metric in SERVE_CLASSES:
+                srv.warm(d, metric, precision=prec if (metric == 2 and d >= 12) else 0)
+            serve_run(srv, reqs[:256], pool, prec, saturate=True)
+            res, etas[name] = serve_run(srv, reqs, pool, prec)
+            sat, _ = serve_run(srv, reqs, pool, prec, saturate=True)
+            res["graphs"] = srv.stats()["graphs"]
+        res["saturated"] = {k: sat[k] for k in ("req_per_s", "p50_ms", "p99_ms", "wall_s",
+                                                "batches", "mean_batch", "admission_stalls",
+                                                "arena_peak_gib")}
         out[name] = res
-        out[name + "_eta"] = eta
         print(f"[bench] serve {name}: p50 {res['p50_ms']:.2f} ms, p99 {res['p99_ms']:.2f} ms, "
-              f"{res['req_per_s']:.0f} req/s; saturated {sat['req_per_s']:.0f} req/s",
+              f"{res['req_per_s']:.0f} req/s, mean batch {res['mean_batch']:.2f}; saturated "
+              f"{sat['req_per_s']:.0f} req/s, mean batch {sat['mean_batch']:.1f}",
               file=sys.stderr, flush=True)
-    e32, e16 = out.pop("fp32_eta"), out.pop("bf16_eta")
+    e32, e16 = etas["fp32"], etas["bf16"]
     rel = np.abs(e16 - e32) / np.maximum(np.abs(e32), 1e-300)
     d128 = np.array([r.d == 128 and r.metric == 2 for r in reqs])
     out["bf16_vs_fp32"] = {"p99_speedup": out["fp32"]["p99_ms"] / out["bf16"]["p99_ms"],
@@ -332,7 +345,7 @@ def main():
     ap.add_argument("--requests", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=500.0)
     ap.add_argument("--arena-gib", type=float, default=8.0)
-    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run --steps plain device-to-device copies of MIB MiB "
                          "(calibrates the FETCH_SIZE/WRITE_SIZE counters)")

@@ -180,25 +180,33 @@ int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float
                    const chamfer_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Serving: continuous batching of chamfer_estimate requests.
+ * Serving: continuous batching of chamfer_estimate requests (importance
+ * sampling, the Chamfer-Estimate figure, run for many independent pairs).
  *
- * A server owns one device arena of arena_bytes (allocated once, by
- * chamfer_server_create; nothing is allocated afterwards) and `slots` request
- * slots, each with its own stream.  chamfer_server_submit queues a request
- * (host side only).  chamfer_server_progress admits queued requests while a
- * slot is free and the arena can hold the request's footprint (its two
- * point sets, its workspace and its outputs), copies the inputs in and
- * enqueues the estimate on the slot's stream, and retires finished requests,
- * which frees their slot and memory at once; it never blocks.  Admission is
- * first-in first-out with a look-ahead of 8 requests past a head that does
- * not fit.  chamfer_server_results drains finished requests.  A request's
- * host arrays A, B (row-major float32; pinned memory makes the copy-in
- * asynchronous) must stay valid until its result is drained.  Results are
- * bit-identical to a direct chamfer_estimate call with the same arguments.
+ * A server owns one device arena of arena_bytes, allocated once by
+ * chamfer_server_create, and `lanes` (1..16) batch lanes, each with its own
+ * stream (default priority), a device batch descriptor and pinned staging.
+ * chamfer_server_submit queues a request (host side only; a request with
+ * n_A == 0 is finished at once with eta = 0).  chamfer_server_progress never
+ * blocks: it retires finished batches, which frees their lanes and arena
+ * blocks at once, and while a lane is free forms the next batch.  The first
+ * of the 9 oldest queued requests whose footprint (its two point sets and
+ * its workspace, chamfer_workspace_bytes) fits the arena sets the batch's
+ * class: (d, metric, embed_dim, precision, where precision counts as FP32
+ * if the low-precision pass does not apply).  When that request is the
+ * oldest, up to 64 requests of the same class among the 256 oldest that fit
+ * the arena join it.  Inputs are copied in on the lane's stream and the
+ * batch runs as ONE replay of a HIP graph captured once per lane and class,
+ * in which each stage of the estimator is a single persistent-grid launch
+ * over every request of the batch.  chamfer_server_results drains finished
+ * requests (members of one batch share admit_s).  A request's host arrays A,
+ * B (row-major float32; pinned memory makes the copy-in asynchronous) must
+ * stay valid until its result is drained.  Results are bit-identical to a
+ * direct chamfer_estimate call with the same arguments.  Requires d <= 2048.
  * A server is not thread-safe: call it from one host thread.
- * Errors: EINVAL for bad arguments (as chamfer_estimate), EWORKSPACE if a
- * request can never fit the arena, EHIP for runtime failures (a failed
- * request is also reported through its result's status).
+ * Errors: EINVAL for bad arguments (as chamfer_estimate, or d > 2048),
+ * EWORKSPACE if a request can never fit the arena, EHIP for runtime
+ * failures (a failed request is also reported through its result's status).
  */
 typedef struct chamfer_server chamfer_server;
 
@@ -225,11 +233,21 @@ typedef struct chamfer_result {
 
 typedef struct chamfer_server_stat {
     int64_t queued;
-    int32_t in_flight;
+    int32_t in_flight;   /* requests admitted and not yet finished */
+    int32_t lanes_busy;
     size_t arena_bytes, arena_used, arena_peak;
+    int64_t batches;     /* batches launched */
+    int64_t batched;     /* requests launched in those batches */
+    int64_t graphs;      /* graphs instantiated (one per lane and class) */
+    int64_t stalls;      /* admissions that found a free lane but no room in the arena */
 } chamfer_server_stat;
 
-int chamfer_server_create(size_t arena_bytes, int32_t slots, chamfer_server **out);
+int chamfer_server_create(size_t arena_bytes, int32_t lanes, chamfer_server **out);
+/* Capture and instantiate, on every lane, the graph of the class of requests
+ * with this d, metric, embed_dim (0 = default) and precision, so that the
+ * first such request does not pay for it.  Optional. */
+int chamfer_server_warm(chamfer_server *srv, int32_t d, int32_t metric, int32_t embed_dim,
+                        int32_t precision);
 int chamfer_server_submit(chamfer_server *srv, const chamfer_request *req, uint64_t *id_out);
 int chamfer_server_progress(chamfer_server *srv); /* returns requests finished */
 int chamfer_server_results(chamfer_server *srv, chamfer_result *out, int32_t max);

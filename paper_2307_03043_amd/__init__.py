@@ -71,6 +71,7 @@ _SIGS = {
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
     "chamfer_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "chamfer_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, _VP]),
+    "chamfer_server_warm": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
     "chamfer_server_submit": (ctypes.c_int, [_VP, _VP, _VP]),
     "chamfer_server_progress": (ctypes.c_int, [_VP]),
     "chamfer_server_results": (ctypes.c_int, [_VP, _VP, _I32]),
@@ -328,13 +329,16 @@ class Result(ctypes.Structure):
 
 class ServerStat(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int64), ("in_flight", ctypes.c_int32),
+                ("lanes_busy", ctypes.c_int32),
                 ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
-                ("arena_peak", ctypes.c_size_t)]
+                ("arena_peak", ctypes.c_size_t), ("batches", ctypes.c_int64),
+                ("batched", ctypes.c_int64), ("graphs", ctypes.c_int64),
+                ("stalls", ctypes.c_int64)]
 
 
-def chamfer_server_create(arena_bytes: int, slots: int = 16):
+def chamfer_server_create(arena_bytes: int, lanes: int = 4):
     h = ctypes.c_void_p()
-    _check(lib().chamfer_server_create(arena_bytes, slots, ctypes.byref(h)),
+    _check(lib().chamfer_server_create(arena_bytes, lanes, ctypes.byref(h)),
            "chamfer_server_create")
     return h
 
@@ -346,8 +350,8 @@ class ChamferServer:
     tensors make the copy-in asynchronous); they are kept alive here until the
     request's result has been drained."""
 
-    def __init__(self, arena_bytes: int, slots: int = 16):
-        self.h = chamfer_server_create(arena_bytes, slots)
+    def __init__(self, arena_bytes: int, lanes: int = 4):
+        self.h = chamfer_server_create(arena_bytes, lanes)
         self._keep = {}
 
     @staticmethod
@@ -373,6 +377,11 @@ class ChamferServer:
                "chamfer_server_submit")
         self._keep[rid.value] = (A, B)
         return rid.value
+
+    def warm(self, d, metric, *, embed_dim=0, precision=0):
+        """Instantiate the graph of a request class on every lane now."""
+        _check(lib().chamfer_server_warm(self.h, d, metric, embed_dim, precision),
+               "chamfer_server_warm")
 
     def progress(self) -> int:
         n = lib().chamfer_server_progress(self.h)

@@ -61,6 +61,15 @@ void embedding_host(uint64_t seed, int d, int ke, float *Z) {
         }
 }
 
+// The same, transposed to [d][ke] (the layout the hash kernels read).
+void embedding_transposed(uint64_t seed, int d, int ke, float *zt) {
+    thread_local std::vector<float> z;
+    z.resize((size_t)ke * d);
+    embedding_host(seed, d, ke, z.data());
+    for (int j = 0; j < ke; ++j)
+        for (int k = 0; k < d; ++k) zt[(size_t)k * ke + j] = z[(size_t)j * d + k];
+}
+
 bool valid_ke(int ke) { return ke == 8 || ke == 16 || ke == 32 || ke == 64; }
 
 int default_scales(int64_t nA, int64_t nB, double eps) {
@@ -171,12 +180,9 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
     if (pl.metric == CHAMFER_L2) {
         // The embedding matrix is drawn on the host (it needs log and cos in
         // double precision) and uploaded transposed, [d][ke].
-        thread_local std::vector<float> z, zt;
-        z.resize((size_t)pl.ke * pl.d);
+        thread_local std::vector<float> zt;
         zt.resize((size_t)pl.ke * pl.d);
-        embedding_host(seed, pl.d, pl.ke, z.data());
-        for (int j = 0; j < pl.ke; ++j)
-            for (int k = 0; k < pl.d; ++k) zt[(size_t)k * pl.ke + j] = z[(size_t)j * pl.d + k];
+        embedding_transposed(seed, pl.d, pl.ke, zt.data());
         CH_TRY(hipMemcpyAsync(at<float>(ws, pl.off_embed), zt.data(), zt.size() * sizeof(float),
                               hipMemcpyHostToDevice, st));
     }
@@ -248,6 +254,143 @@ __global__ void k_store_zero(double *out, int32_t *status) {
 }
 
 }  // namespace
+
+// ------------------------------------------------------------ batching
+
+namespace chamfer {
+
+int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t d,
+                int32_t metric, double eps, int64_t T, uint64_t seed, const chamfer_opts *opts,
+                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const float *embed_dev,
+                float *embed_host, Job *job) {
+    Plan pl;
+    int rc = make_plan(pl, nA, nB, d, metric, eps, T, opts, true);
+    if (rc) return rc;
+    if (nA < 1 || d > 2048 || A == nullptr || B == nullptr || eta == nullptr || job == nullptr)
+        return CHAMFER_EINVAL;
+    if (metric == CHAMFER_L2 && (embed_dev == nullptr || embed_host == nullptr))
+        return CHAMFER_EINVAL;
+    if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
+    const bool lp = lowp_supported(d, metric, pl.precision);
+    Job &J = *job;
+    std::memset(&J, 0, sizeof(J));
+    J.A = A;
+    J.B = B;
+    J.nA = nA;
+    J.nB = nB;
+    J.T = pl.T;
+    J.seed = seed;
+    J.d = d;
+    J.metric = metric;
+    J.L = pl.L;
+    J.ke = pl.ke;
+    J.kh = pl.kh;
+    J.q = pl.q;
+    J.log2cap = pl.log2cap;
+    J.precision = lp ? pl.precision : CHAMFER_FP32;
+    J.p = at<DevParams>(ws, pl.off_params);
+    J.lohi = at<uint32_t>(ws, pl.off_lohi);
+    J.zfrac = at<float>(ws, pl.off_zfrac);
+    J.mult = at<uint64_t>(ws, pl.off_mult);
+    J.embed = metric == CHAMFER_L2 ? embed_dev : nullptr;
+    J.tables = at<Bucket>(ws, pl.off_tables);
+    J.table_count = (int64_t)pl.L << pl.log2cap;
+    J.D = at<float>(ws, pl.off_D);
+    J.nn = at<int32_t>(ws, pl.off_nn);
+    J.blocksums = at<unsigned long long>(ws, pl.off_blocksums);
+    J.P = at<unsigned long long>(ws, pl.off_P);
+    J.idx = at<int32_t>(ws, pl.off_idx);
+    J.best = at<unsigned long long>(ws, pl.off_best);
+    J.nb2 = mfma_supported(d, metric) ? at<float>(ws, pl.off_nb2) : nullptr;
+    J.bq = lp ? at<uint8_t>(ws, pl.off_bq) : nullptr;
+    J.xq = lp ? at<uint8_t>(ws, pl.off_xq) : nullptr;
+    J.lpf = lp ? at<float>(ws, pl.off_lpf) : nullptr;
+    J.eta = eta;
+    J.aux = aux;
+    J.aux.stage_events = nullptr;
+    // geometry: the block counts of the direct launches
+    J.nb_init = (int32_t)init_blocks(d);
+    J.nb_grid = (int32_t)grid_table_blocks(pl.L, pl.kh);
+    J.nb_fill = (int32_t)table_fill_blocks((size_t)J.table_count);
+    J.mm_vec4 = minmax_vec4(A, d) && minmax_vec4(B, d);
+    int64_t blocks, stride;
+    minmax_geom(nA, d, J.mm_vec4 != 0, &blocks, &stride);
+    J.nb_mmA = (int32_t)blocks;
+    J.mm_strideA = stride;
+    minmax_geom(nB, d, J.mm_vec4 != 0, &blocks, &stride);
+    J.nb_mmB = (int32_t)blocks;
+    J.mm_strideB = stride;
+    J.nb_hashB = (int32_t)hash_blocks(nB);
+    J.nb_hashA = (int32_t)hash_blocks(nA);
+    J.nb_scan = (int32_t)scan_blocks(nA);
+    J.nb_sample = (int32_t)sample_blocks(pl.T);
+    NNGeom g;
+    if (lp) {
+        J.nb_castB = (int32_t)cast_blocks(nB);
+        J.nb_castX = (int32_t)cast_blocks(pl.T);
+        g = lowp_geom(pl.T, nB, d, pl.precision);
+    } else if (mfma_supported(d, metric)) {
+        g = mfma_geom(pl.T, nB, d);
+    } else {
+        g = valu_geom(pl.T, nB, d);
+    }
+    J.nn_chunk = g.chunk;
+    J.nn_nchunk = g.nchunk;
+    J.nb_nn = (int32_t)g.blocks;
+    if (metric == CHAMFER_L2) embedding_transposed(seed, d, pl.ke, embed_host);
+    return CHAMFER_OK;
+}
+
+void job_stage_blocks(const Job &J, int64_t out[kBsCount]) {
+    out[kBsSetup] = (int64_t)J.nb_init + J.nb_grid + J.nb_fill;
+    out[kBsMinmax] = (int64_t)J.nb_mmA + J.nb_mmB;
+    out[kBsCalib] = 1;
+    out[kBsInsert] = J.nb_hashB;
+    out[kBsProbe] = J.nb_hashA;
+    out[kBsWsum] = J.nb_scan;
+    out[kBsWscan] = 1;
+    out[kBsPrefix] = J.nb_scan;
+    out[kBsSample] = J.nb_sample;
+    out[kBsCast] = (int64_t)J.nb_castB + J.nb_castX;
+    out[kBsNN] = J.nb_nn;
+    out[kBsFinal] = 1;
+}
+
+void job_share_nn(Job *jobs, int n) {
+    if (n <= 1) return;
+    const Job &J0 = jobs[0];
+    if (lowp_supported(J0.d, J0.metric, J0.precision)) return;
+    const bool mfma = mfma_supported(J0.d, J0.metric);
+    double total = 0.0;
+    for (int j = 0; j < n; ++j) total += (double)jobs[j].T * (double)jobs[j].nB;
+    const double target = mfma ? 4096.0 : (double)kValuTargetWGs;
+    for (int j = 0; j < n; ++j) {
+        Job &J = jobs[j];
+        const double share = target * ((double)J.T * (double)J.nB) / total;
+        const int64_t t = share < 1.0 ? 1 : (int64_t)std::ceil(share);
+        const NNGeom g = mfma ? mfma_geom(J.T, J.nB, J.d, t) : valu_geom(J.T, J.nB, J.d, t);
+        J.nn_chunk = g.chunk;
+        J.nn_nchunk = g.nchunk;
+        J.nb_nn = (int32_t)g.blocks;
+    }
+}
+
+int launch_estimate_batch(const Batch *bt, int d, int metric, int ke, int precision,
+                          hipStream_t st) {
+    CH_TRY(launch_batch_setup(bt, st));
+    CH_TRY(launch_batch_minmax(bt, d, st));
+    CH_TRY(launch_batch_calib(bt, d, st));
+    CH_TRY(launch_batch_hash(0, bt, d, metric, ke, st));
+    CH_TRY(launch_batch_hash(1, bt, d, metric, ke, st));
+    CH_TRY(launch_batch_weights(bt, st));
+    CH_TRY(launch_batch_sample(bt, st));
+    if (lowp_supported(d, metric, precision)) CH_TRY(launch_batch_cast(bt, d, precision, st));
+    CH_TRY(launch_batch_nn(bt, d, metric, precision, st));
+    CH_TRY(launch_batch_final(bt, metric, st));
+    return CHAMFER_OK;
+}
+
+}  // namespace chamfer
 
 extern "C" {
 

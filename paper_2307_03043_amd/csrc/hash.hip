@@ -18,8 +18,8 @@ namespace chamfer {
 
 // ------------------------------------------------------------- parameters
 
-__global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_params(DevParams *p, uint32_t *lohi, int d, Blk b) {
+    const int64_t t = b.id * blockDim.x + threadIdx.x;
     if (t == 0) {
         p->status = CHAMFER_OK;
         p->e_top = 0;
@@ -33,22 +33,29 @@ __global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
         p->fallbacks = 0;
     }
     if (lohi != nullptr)
-        for (int k = t; k < d; k += gridDim.x * blockDim.x) {
+        for (int64_t k = t; k < d; k += b.n * blockDim.x) {
             lohi[k] = 0xffffffffu;  // running min (ordered encoding)
             lohi[d + k] = 0u;       // running max
         }
 }
 
+__global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
+    init_params(p, lohi, d, grid_blk());
+}
+
+int64_t init_blocks(int d) { return (d + 255) / 256; }
+
 hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t st) {
-    const int blocks = lohi ? (d + 255) / 256 : 1;
+    const int blocks = lohi ? (int)init_blocks(d) : 1;
     k_init_params<<<blocks, 256, 0, st>>>(p, lohi, d);
     return hipGetLastError();
 }
 
 // Shifts z'_ik (cell units, 24-bit lattice in [0,1)) and odd multipliers
 // M_ik from Philox4x64-10, counter (k, i, GRID, 0), key (seed, 0).
-__global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void grid_tables(uint64_t seed, int L, int kh, float *zfrac,
+                                            uint64_t *mult, Blk b) {
+    const int t = (int)(b.id * blockDim.x + threadIdx.x);
     if (t >= L * kh) return;
     const int i = t / kh, k = t - i * kh;
     uint64_t c[4] = {(uint64_t)k, (uint64_t)i, (uint64_t)kPurposeGrid, 0};
@@ -57,10 +64,15 @@ __global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64
     mult[t] = c[1] | 1ull;
 }
 
+__global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult) {
+    grid_tables(seed, L, kh, zfrac, mult, grid_blk());
+}
+
+int64_t grid_table_blocks(int L, int kh) { return ((int64_t)L * kh + 255) / 256; }
+
 hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
                               hipStream_t st) {
-    const int n = L * kh;
-    k_grid_tables<<<(n + 255) / 256, 256, 0, st>>>(seed, L, kh, zfrac, mult);
+    k_grid_tables<<<(unsigned)grid_table_blocks(L, kh), 256, 0, st>>>(seed, L, kh, zfrac, mult);
     return hipGetLastError();
 }
 
@@ -68,9 +80,8 @@ hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64
 // flat element e has coordinate e mod d; the grid stride is a multiple of d,
 // so every thread keeps one coordinate.  Min/max use integer atomics on an
 // order-preserving encoding, whose result does not depend on their order.
-__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int64_t total,
-                                                int d, int64_t stride, uint32_t *lohi,
-                                                DevParams *p) {
+__device__ __forceinline__ void minmax(const float *__restrict__ X, int64_t total, int d,
+                                       int64_t stride, uint32_t *lohi, DevParams *p, Blk b) {
     extern __shared__ uint32_t sm[];
     const bool use_lds = d <= 2048;
     if (use_lds) {
@@ -80,12 +91,12 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int
         }
         __syncthreads();
     }
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = b.id * blockDim.x + threadIdx.x;
     uint32_t lo = 0xffffffffu, hi = 0u;
     int bad = 0;
     if (g < stride) {
         for (int64_t e = g; e < total; e += stride) {
-            const float v = X[e];
+            const float v = ro(X)[e];
             bad |= !isfinite(v);
             const uint32_t o = float_to_ordered(v);
             lo = min(lo, o);
@@ -110,11 +121,16 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int
     }
 }
 
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ X, int64_t total,
+                                                int d, int64_t stride, uint32_t *lohi,
+                                                DevParams *p) {
+    minmax(X, total, d, stride, lohi, p, grid_blk());
+}
+
 // Same with 16-byte loads when d is a multiple of 4: thread g keeps the four
 // coordinates of float4 column (g mod d/4).
-__global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, int64_t total4,
-                                                 int d, int64_t stride4, uint32_t *lohi,
-                                                 DevParams *p) {
+__device__ __forceinline__ void minmax4(const float4 *__restrict__ X4, int64_t total4, int d,
+                                        int64_t stride4, uint32_t *lohi, DevParams *p, Blk b) {
     extern __shared__ uint32_t sm[];
     const int d4 = d >> 2;
     for (int i = threadIdx.x; i < d; i += blockDim.x) {
@@ -122,7 +138,7 @@ __global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, 
         sm[d + i] = 0u;
     }
     __syncthreads();
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = b.id * blockDim.x + threadIdx.x;
     uint32_t lo[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
     uint32_t hi[4] = {0u, 0u, 0u, 0u};
     int bad = 0;
@@ -138,15 +154,16 @@ __global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, 
     };
     if (g < stride4) {
         int64_t e = g;
+        const auto *Xr = ro(X4);
         for (; e + 3 * stride4 < total4; e += 4 * stride4) {
-            const float4 v0 = X4[e], v1 = X4[e + stride4], v2 = X4[e + 2 * stride4],
-                         v3 = X4[e + 3 * stride4];
+            const float4 v0 = ld(Xr + e), v1 = ld(Xr + e + stride4),
+                         v2 = ld(Xr + e + 2 * stride4), v3 = ld(Xr + e + 3 * stride4);
             take(v0);
             take(v1);
             take(v2);
             take(v3);
         }
-        for (; e < total4; e += stride4) take(X4[e]);
+        for (; e < total4; e += stride4) take(ld(Xr + e));
         const int k0 = (int)(g % d4) * 4;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -162,26 +179,50 @@ __global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, 
     }
 }
 
-hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
-                         hipStream_t st) {
+__global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, int64_t total4,
+                                                 int d, int64_t stride4, uint32_t *lohi,
+                                                 DevParams *p) {
+    minmax4(X4, total4, d, stride4, lohi, p, grid_blk());
+}
+
+bool minmax_vec4(const float *X, int d) {
+    return (d & 3) == 0 && d <= 2048 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+}
+
+void minmax_geom(int64_t n, int d, bool vec4, int64_t *blocks_out, int64_t *stride_out) {
     const int64_t total = n * (int64_t)d;
-    if ((d & 3) == 0 && d <= 2048 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+    int64_t blocks;
+    // about 64 coordinates per thread: each block ends with 2d global atomics
+    // on the same 2d words, so small inputs want few blocks
+    if (vec4) {
         const int64_t total4 = total / 4;
         const int d4 = d / 4;
-        int64_t blocks = (total4 + 1023) / 1024;
+        blocks = (total4 + 4095) / 4096;
         if (blocks > 1024) blocks = 1024;
         const int64_t min_blocks = (d4 + 255) / 256;
         if (blocks < min_blocks) blocks = min_blocks;
-        const int64_t stride4 = (blocks * 256 / d4) * d4;
+        *stride_out = (blocks * 256 / d4) * d4;
+    } else {
+        blocks = (total + 16383) / 16384;
+        if (blocks > 2048) blocks = 2048;
+        const int64_t min_blocks = (d + 255) / 256;
+        if (blocks < min_blocks) blocks = min_blocks;
+        *stride_out = (blocks * 256 / d) * d;
+    }
+    *blocks_out = blocks;
+}
+
+hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
+                         hipStream_t st) {
+    const int64_t total = n * (int64_t)d;
+    int64_t blocks, stride;
+    if (minmax_vec4(X, d)) {
+        minmax_geom(n, d, true, &blocks, &stride);
         k_minmax4<<<(unsigned)blocks, 256, 2 * (size_t)d * sizeof(uint32_t), st>>>(
-            reinterpret_cast<const float4 *>(X), total4, d, stride4, lohi, p);
+            reinterpret_cast<const float4 *>(X), total / 4, d, stride, lohi, p);
         return hipGetLastError();
     }
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    const int64_t min_blocks = (d + 255) / 256;
-    if (blocks < min_blocks) blocks = min_blocks;
-    const int64_t stride = (blocks * 256 / d) * d;
+    minmax_geom(n, d, false, &blocks, &stride);
     const size_t lds = d <= 2048 ? 2 * (size_t)d * sizeof(uint32_t) : 0;
     k_minmax<<<(unsigned)blocks, 256, lds, st>>>(X, total, d, stride, lohi, p);
     return hipGetLastError();
@@ -200,7 +241,7 @@ __global__ void k_calib_final_wide(const uint32_t *lohi, int d, DevParams *p) {
 // S = sum_k (hi_k - lo_k) in double, k ascending; e_top = ceil(log2 S).
 // The per-coordinate spans are gathered in parallel; one thread sums them
 // in order.
-__global__ __launch_bounds__(256) void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+__device__ __forceinline__ void calib_final(const uint32_t *lohi, int d, DevParams *p) {
     extern __shared__ double span[];
     for (int k = threadIdx.x; k < d; k += blockDim.x)
         span[k] = (double)ordered_to_float(lohi[d + k]) - (double)ordered_to_float(lohi[k]);
@@ -213,6 +254,10 @@ __global__ __launch_bounds__(256) void k_calib_final(const uint32_t *lohi, int d
     if (p->nonfinite) p->status = CHAMFER_ENONFINITE;
 }
 
+__global__ __launch_bounds__(256) void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+    calib_final(lohi, d, p);
+}
+
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st) {
     if ((size_t)d * sizeof(double) > 60000) {
         // very wide points: spans recomputed by the summing thread
@@ -223,9 +268,9 @@ hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t s
     return hipGetLastError();
 }
 
-__global__ void k_table_fill(Bucket *t, size_t count) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+__device__ __forceinline__ void table_fill(Bucket *t, size_t count, Blk b) {
+    const size_t stride = (size_t)b.n * blockDim.x;
+    for (size_t i = (size_t)b.id * blockDim.x + threadIdx.x; i < count; i += stride) {
         Bucket b;
         b.key = kEmptyKey;
         b.val = INT_MAX;
@@ -234,10 +279,16 @@ __global__ void k_table_fill(Bucket *t, size_t count) {
     }
 }
 
-hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
+__global__ void k_table_fill(Bucket *t, size_t count) { table_fill(t, count, grid_blk()); }
+
+int64_t table_fill_blocks(size_t count) {
     size_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    k_table_fill<<<(unsigned)blocks, 256, 0, st>>>(tables, count);
+    return (int64_t)blocks;
+}
+
+hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
+    k_table_fill<<<(unsigned)table_fill_blocks(count), 256, 0, st>>>(tables, count);
     return hipGetLastError();
 }
 
@@ -246,9 +297,9 @@ hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
 // Key of hashed coordinates y (stride 1) at the scale of side 2^e:
 // cell_k = ceil(y_k 2^-e + z'_k) + 0 (the +0 turns -0 into +0, so equal
 // cells have equal bits), key = (sum_k bits(cell_k) M_k mod 2^64) >> 1.
-__device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh, int e,
-                                                         const float *__restrict__ zf,
-                                                         const uint64_t *__restrict__ M) {
+template <class PZ, class PM>
+__device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh, int e, PZ zf,
+                                                         PM M) {
     unsigned long long acc = 0;
     for (int k = 0; k < kh; ++k) {
         const float q = ldexpf(y[k], -e) + zf[k];
@@ -259,9 +310,9 @@ __device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh,
 }
 
 // Same, with y_k = x_k - lo_k read from HBM (l1 with d too large for LDS).
-__device__ __forceinline__ unsigned long long bucket_key_global(
-    const float *__restrict__ x, const uint32_t *__restrict__ lohi, int kh, int e,
-    const float *__restrict__ zf, const uint64_t *__restrict__ M) {
+template <class PX, class PL, class PZ, class PM>
+__device__ __forceinline__ unsigned long long bucket_key_global(PX x, PL lohi, int kh, int e,
+                                                                PZ zf, PM M) {
     unsigned long long acc = 0;
     for (int k = 0; k < kh; ++k) {
         const float y = x[k] - ordered_to_float(lohi[k]);
@@ -318,14 +369,15 @@ __device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, i
 }
 
 // Lowest b stored under key, or -1.  Runs in a later kernel than every insert.
-__device__ __forceinline__ int table_probe(const Bucket *__restrict__ tab, int log2cap,
+__device__ __forceinline__ int table_probe(const CH_RO Bucket *tab, int log2cap,
                                            unsigned long long key) {
     const uint64_t mask = (1ull << log2cap) - 1;
     uint64_t slot = home_slot(key, log2cap);
     for (;;) {
-        const Bucket e = tab[slot];
-        if (e.key == key) return e.val;
-        if (e.key == kEmptyKey) return -1;
+        const uint4 w = ld(reinterpret_cast<const CH_RO uint4 *>(tab + slot));  // {key, val, pad}
+        const unsigned long long k = (unsigned long long)w.x | ((unsigned long long)w.y << 32);
+        if (k == key) return (int)w.z;
+        if (k == kEmptyKey) return -1;
         slot = (slot + 1) & mask;
     }
 }
@@ -352,12 +404,12 @@ constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
 // first hit (or once another wavefront has hit at a finer scale); the first
 // colliding scale is the smallest over the four.
 template <int METRIC, int MODE, int KE, bool YG>
-__global__ __launch_bounds__(kThreads) void k_hash(
+__device__ __forceinline__ void hash_tile(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, float *nb2_out, DevParams *p) {
+    int32_t *scale_out, float *nb2_out, DevParams *p, Blk blk) {
     extern __shared__ float smem[];
     __shared__ float los[kEmbedChunk];
     __shared__ int hit_scale[kTile];
@@ -367,7 +419,7 @@ __global__ __launch_bounds__(kThreads) void k_hash(
     // wave-uniform by construction; readfirstlane lets the compiler know, so
     // the per-scale tables and the embedding columns go through scalar loads
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t p0 = (int64_t)blockIdx.x * kTile;
+    const int64_t p0 = blk.id * kTile;
     const int np = (int)min<int64_t>(kTile, n - p0);
     const int64_t pt = p0 + lane;
     const bool active = lane < np;
@@ -389,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_hash(
         if (!YG)
             for (int e = tid; e < np * d; e += kThreads) {
                 const int r = e / d, k = e - r * d;
-                ys[r * khp + k] = X[(p0 + r) * d + k] - ordered_to_float(lohi[k]);
+                ys[r * khp + k] = ro(X)[(p0 + r) * d + k] - ordered_to_float(ro(lohi)[k]);
             }
     } else {
         // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k; wavefront
@@ -409,15 +461,15 @@ __global__ __launch_bounds__(kThreads) void k_hash(
             __syncthreads();
             for (int e = tid; e < np * kc; e += kThreads) {
                 const int r = e / kc, k = e - r * kc;
-                xs[r * (kEmbedChunk + 1) + k] = X[(p0 + r) * d + k0 + k];
+                xs[r * (kEmbedChunk + 1) + k] = ro(X)[(p0 + r) * d + k0 + k];
             }
-            if (tid < kc) los[tid] = ordered_to_float(lohi[k0 + tid]);
+            if (tid < kc) los[tid] = ordered_to_float(ro(lohi)[k0 + tid]);
             __syncthreads();
             if (active) {
                 for (int k = 0; k < kc; ++k) {
                     const float xraw = xs[lane * (kEmbedChunk + 1) + k];
                     const float xv = xraw - los[k];
-                    const float *zc = embed_t + (size_t)(k0 + k) * KE + wave * JW;
+                    const auto *zc = ro(embed_t) + (size_t)(k0 + k) * KE + wave * JW;
 #pragma unroll
                     for (int j = 0; j < JW; ++j) y[j] = fmaf(zc[j], xv, y[j]);
                     if (want_n2) n2 = fmaf(xraw, xraw, n2);
@@ -444,9 +496,9 @@ __global__ __launch_bounds__(kThreads) void k_hash(
     auto key_at = [&](int i) -> unsigned long long {
         const int e = e_top - (L - 1 - i);
         if (METRIC == CHAMFER_L1 && YG)
-            return bucket_key_global(xrow, lohi, kh, e, zfrac + (size_t)i * kh,
-                                     mult + (size_t)i * kh);
-        return bucket_key(yrow, kh, e, zfrac + (size_t)i * kh, mult + (size_t)i * kh);
+            return bucket_key_global(ro(xrow), ro(lohi), kh, e, ro(zfrac) + (size_t)i * kh,
+                                     ro(mult) + (size_t)i * kh);
+        return bucket_key(yrow, kh, e, ro(zfrac) + (size_t)i * kh, ro(mult) + (size_t)i * kh);
     };
 
     if (MODE == 0) {
@@ -485,7 +537,8 @@ __global__ __launch_bounds__(kThreads) void k_hash(
             if (i > __hip_atomic_load(&hit_scale[lane], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WORKGROUP))
                 break;  // a finer scale already collided
-            const int v = table_probe(tables + ((size_t)i << log2cap), log2cap, key_at(i));
+            const int v = table_probe(ro((const Bucket *)tables) + ((size_t)i << log2cap), log2cap,
+                                      key_at(i));
             if (v >= 0) {
                 found = i;
                 cand = v;
@@ -518,6 +571,26 @@ __global__ __launch_bounds__(kThreads) void k_hash(
     if (lane == 0) atomicMax(&p->max_d_bits, m);
 }
 
+template <int METRIC, int MODE, int KE, bool YG>
+__global__ __launch_bounds__(kThreads) void k_hash(
+    const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
+    const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
+    const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
+    int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
+    int32_t *scale_out, float *nb2_out, DevParams *p) {
+    hash_tile<METRIC, MODE, KE, YG>(X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap,
+                                    keys_out, D_out, nn_out, scale_out, nb2_out, p, grid_blk());
+}
+
+int64_t hash_blocks(int64_t n) { return (n + kTile - 1) / kTile; }
+
+template <int METRIC, int KE, bool YG>
+static size_t hash_lds(int d) {
+    const int kh = METRIC == CHAMFER_L1 ? d : KE;
+    if (METRIC == CHAMFER_L1) return YG ? 0 : (size_t)kTile * (kh | 1) * sizeof(float);
+    return (size_t)kTile * ((kh | 1) + kEmbedChunk + 1) * sizeof(float);
+}
+
 template <int METRIC, int KE, bool YG>
 static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts, int d,
                                 int L, const uint32_t *lohi, const float *embed_t,
@@ -525,14 +598,8 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
                                 int log2cap, uint64_t *keys_out, float *D_out, int32_t *nn_out,
                                 int32_t *scale_out, float *nb2_out, DevParams *p,
                                 hipStream_t st) {
-    const int kh = METRIC == CHAMFER_L1 ? d : KE;
-    size_t lds = 0;
-    if (METRIC == CHAMFER_L1) {
-        if (!YG) lds = (size_t)kTile * (kh | 1) * sizeof(float);
-    } else {
-        lds = (size_t)kTile * ((kh | 1) + kEmbedChunk + 1) * sizeof(float);
-    }
-    const unsigned blocks = (unsigned)((n + kTile - 1) / kTile);
+    const size_t lds = hash_lds<METRIC, KE, YG>(d);
+    const unsigned blocks = (unsigned)hash_blocks(n);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
     if (mode == 0)
         k_hash<METRIC, 0, KE, YG><<<blocks, kThreads, lds, st>>>(
@@ -549,8 +616,8 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
     return hipGetLastError();
 }
 
-// Largest l1 dimension whose tile fits the default 64 KiB of dynamic LDS.
-constexpr int kMaxLdsL1Dim = 240;  // 64 x 241 floats + static LDS < 64 KiB
+// kMaxLdsL1Dim: largest l1 dimension whose tile (64 x (d|1) floats) plus the
+// static LDS fits the default 64 KiB.
 
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
@@ -574,6 +641,105 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
         default: return hipErrorInvalidValue;
     }
 #undef CH_ARGS
+}
+
+// ---------------------------------------------------------------- batched
+// Persistent grids over all jobs of a batch (see batch_loop).  A job's
+// blocks are the blocks of its direct launches, so every job computes what
+// chamfer_estimate computes for it alone.
+
+constexpr unsigned kGridSetup = 512, kGridMinmax = 1024, kGridCalib = kBatchMax,
+                   kGridHash = 2048;
+
+__global__ __launch_bounds__(256) void kb_setup(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsSetup, [&](const Job &J, Blk b) {
+        if (b.id < J.nb_init) {
+            init_params(J.p, J.lohi, J.d, Blk{b.id, J.nb_init});
+            return;
+        }
+        int64_t r = b.id - J.nb_init;
+        if (r < J.nb_grid) {
+            grid_tables(J.seed, J.L, J.kh, J.zfrac, J.mult, Blk{r, J.nb_grid});
+            return;
+        }
+        r -= J.nb_grid;
+        table_fill(J.tables, (size_t)J.table_count, Blk{r, J.nb_fill});
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_minmax(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsMinmax, [&](const Job &J, Blk b) {
+        const bool isA = b.id < J.nb_mmA;
+        const float *X = isA ? J.A : J.B;
+        const int64_t total = (isA ? J.nA : J.nB) * (int64_t)J.d;
+        const int64_t stride = isA ? J.mm_strideA : J.mm_strideB;
+        const Blk c = isA ? Blk{b.id, J.nb_mmA} : Blk{b.id - J.nb_mmA, J.nb_mmB};
+        if (J.mm_vec4)
+            minmax4(reinterpret_cast<const float4 *>(X), total / 4, J.d, stride, J.lohi, J.p, c);
+        else
+            minmax(X, total, J.d, stride, J.lohi, J.p, c);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_calib(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsCalib, [&](const Job &J, Blk) { calib_final(J.lohi, J.d, J.p); });
+}
+
+template <int METRIC, int MODE, int KE, bool YG>
+__global__ __launch_bounds__(kThreads) void kb_hash(const Batch *__restrict__ bt) {
+    batch_loop(bt, MODE == 0 ? kBsInsert : kBsProbe, [&](const Job &J, Blk b) {
+        if (MODE == 0)
+            hash_tile<METRIC, 0, KE, YG>(J.B, J.nB, J.B, J.d, J.L, J.lohi, J.embed, J.zfrac,
+                                         J.mult, J.tables, J.log2cap, nullptr, nullptr, nullptr,
+                                         nullptr, J.nb2, J.p, b);
+        else
+            hash_tile<METRIC, 1, KE, YG>(J.A, J.nA, J.B, J.d, J.L, J.lohi, J.embed, J.zfrac,
+                                         J.mult, J.tables, J.log2cap, nullptr, J.D, J.nn,
+                                         nullptr, nullptr, J.p, b);
+    });
+}
+
+hipError_t launch_batch_setup(const Batch *bt, hipStream_t st) {
+    kb_setup<<<kGridSetup, 256, 0, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_minmax(const Batch *bt, int d, hipStream_t st) {
+    if (d > 2048) return hipErrorInvalidValue;
+    kb_minmax<<<kGridMinmax, 256, 2 * (size_t)d * sizeof(uint32_t), st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_calib(const Batch *bt, int d, hipStream_t st) {
+    if (d > 2048) return hipErrorInvalidValue;
+    kb_calib<<<kGridCalib, 256, (size_t)d * sizeof(double), st>>>(bt);
+    return hipGetLastError();
+}
+
+template <int METRIC, int KE, bool YG>
+static hipError_t launch_batch_hash_t(int mode, const Batch *bt, int d, hipStream_t st) {
+    const size_t lds = hash_lds<METRIC, KE, YG>(d);
+    if (mode == 0)
+        kb_hash<METRIC, 0, KE, YG><<<kGridHash, kThreads, lds, st>>>(bt);
+    else
+        kb_hash<METRIC, 1, KE, YG><<<kGridHash, kThreads, lds, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_hash(int mode, const Batch *bt, int d, int metric, int ke,
+                             hipStream_t st) {
+    if (mode != 0 && mode != 1) return hipErrorInvalidValue;
+    if (metric == CHAMFER_L1) {
+        if (d <= kMaxLdsL1Dim) return launch_batch_hash_t<CHAMFER_L1, 0, false>(mode, bt, d, st);
+        return launch_batch_hash_t<CHAMFER_L1, 0, true>(mode, bt, d, st);
+    }
+    switch (ke) {
+        case 8: return launch_batch_hash_t<CHAMFER_L2, 8, false>(mode, bt, d, st);
+        case 16: return launch_batch_hash_t<CHAMFER_L2, 16, false>(mode, bt, d, st);
+        case 32: return launch_batch_hash_t<CHAMFER_L2, 32, false>(mode, bt, d, st);
+        case 64: return launch_batch_hash_t<CHAMFER_L2, 64, false>(mode, bt, d, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace chamfer

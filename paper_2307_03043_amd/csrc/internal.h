@@ -69,60 +69,6 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
     }
 }
 
-// Canonical float32 distance accumulator between rows a and b: k ascending,
-// one rounding per operation; l1: acc + |a_k - b_k|, l2: fma(t, t, acc) with
-// t = a_k - b_k (the caller takes the square root for l2).  Loads are issued
-// in batches of 8 x 16 bytes ahead of the (sequential) arithmetic, so a row
-// costs a few memory round trips instead of one per 16 bytes.
-template <int METRIC>
-__device__ __forceinline__ float canon_acc(const float *__restrict__ a,
-                                           const float *__restrict__ b, int d) {
-    float acc = 0.0f;
-    auto step = [&](float x, float y) {
-        const float t = x - y;
-        acc = METRIC == CHAMFER_L1 ? acc + fabsf(t) : fmaf(t, t, acc);
-    };
-    if ((d & 3) == 0 &&
-        ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
-        const float4 *a4 = reinterpret_cast<const float4 *>(a);
-        const float4 *b4 = reinterpret_cast<const float4 *>(b);
-        const int d4 = d >> 2;
-        constexpr int kBatch = 8;
-        for (int k0 = 0; k0 < d4; k0 += kBatch) {
-            float4 u[kBatch], v[kBatch];
-#pragma unroll
-            for (int i = 0; i < kBatch; ++i)
-                if (k0 + i < d4) {
-                    u[i] = a4[k0 + i];
-                    v[i] = b4[k0 + i];
-                }
-#pragma unroll
-            for (int i = 0; i < kBatch; ++i)
-                if (k0 + i < d4) {
-                    step(u[i].x, v[i].x);
-                    step(u[i].y, v[i].y);
-                    step(u[i].z, v[i].z);
-                    step(u[i].w, v[i].w);
-                }
-        }
-        return acc;
-    }
-    constexpr int kBatch = 16;
-    for (int k0 = 0; k0 < d; k0 += kBatch) {
-        float u[kBatch], v[kBatch];
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i)
-            if (k0 + i < d) {
-                u[i] = a[k0 + i];
-                v[i] = b[k0 + i];
-            }
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i)
-            if (k0 + i < d) step(u[i], v[i]);
-    }
-    return acc;
-}
-
 // smallest e with 2^e >= x (x > 0)
 __device__ __forceinline__ int ceil_log2_pos(double x) {
     int e;
@@ -148,6 +94,181 @@ struct Plan {
 constexpr int kScanItems = 4;
 constexpr int kScanThreads = 256;
 constexpr int kScanBlock = kScanItems * kScanThreads;
+
+// ------------------------------------------------------- block coordinates
+// Every stage kernel is a device body over workgroup coordinates (id, n): a
+// direct launch runs it with (blockIdx.x, gridDim.x); a batched launch runs
+// the blocks of every request of a batch with request-local coordinates.
+struct Blk {
+    int64_t id, n;
+};
+__device__ __forceinline__ Blk grid_blk() { return Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}; }
+
+// ---------------------------------------------------------------- batches
+// One request of a batched estimate: its inputs, workspace regions, output
+// slots and the block counts of each of its launches (the same counts its
+// direct launch would use).
+struct Job {
+    const float *A, *B;
+    int64_t nA, nB, T;
+    uint64_t seed;
+    int32_t d, metric, L, ke, kh, q, log2cap, precision;
+    DevParams *p;
+    uint32_t *lohi;
+    float *zfrac;
+    uint64_t *mult;
+    const float *embed;
+    Bucket *tables;
+    int64_t table_count;
+    float *D;
+    int32_t *nn;
+    unsigned long long *blocksums, *P;
+    int32_t *idx;
+    unsigned long long *best;
+    float *nb2;
+    uint8_t *bq, *xq;
+    float *lpf;
+    double *eta;
+    chamfer_aux aux;
+    // geometry
+    int32_t nb_init, nb_grid, nb_fill;
+    int32_t nb_mmA, nb_mmB, mm_vec4;
+    int64_t mm_strideA, mm_strideB;
+    int32_t nb_hashB, nb_hashA, nb_scan, nb_sample;
+    int32_t nb_castB, nb_castX, nn_nchunk, nb_nn;
+    int64_t nn_chunk;
+};
+
+// Stages of a batched estimate, one launch each.
+enum BatchStage {
+    kBsSetup,   // parameter block, shifts and multipliers, empty tables
+    kBsMinmax,  // per-coordinate min/max of A and of B
+    kBsCalib,   // S and e_top
+    kBsInsert,  // B into the tables
+    kBsProbe,   // CrudeNN of A
+    kBsWsum,    // fixed-point weights: block sums
+    kBsWscan,   // scan of the block sums, W and s
+    kBsPrefix,  // prefix P
+    kBsSample,  // T draws
+    kBsCast,    // low-precision copies of B and of the sampled rows
+    kBsNN,      // exact nearest neighbours of the samples
+    kBsFinal,   // eta and the per-request outputs
+    kBsCount
+};
+
+constexpr int kBatchMax = 64;
+
+struct alignas(16) Batch {
+    int32_t njobs;
+    int32_t pad[3];
+    int32_t start[kBsCount][kBatchMax + 1];  // prefix of the jobs' block counts
+    Job job[kBatchMax];
+};
+
+// Pointers read from a batch descriptor are generic to the compiler (flat
+// loads and stores).  glb() states that one points to global memory, so the
+// accesses compile as they do from a kernel argument; ro() also states that
+// the memory is not written while the kernel runs, so loads at wave-uniform
+// addresses go through the scalar cache (which every dispatch invalidates
+// at its start).
+template <class T>
+__device__ __forceinline__ T *glb(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)p;
+}
+#define CH_RO __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CH_RO T *ro(const T *p) {
+    return (const CH_RO T *)p;
+}
+// 16-byte loads through such a pointer (HIP's vector classes cannot be
+// copied out of another address space).
+__device__ __forceinline__ float4 ld(const CH_RO float4 *p) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const CH_RO v4 *>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 ld(const CH_RO uint4 *p) {
+    typedef unsigned v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *reinterpret_cast<const CH_RO v4 *>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Canonical float32 distance accumulator between rows a and b: k ascending,
+// one rounding per operation; l1: acc + |a_k - b_k|, l2: fma(t, t, acc) with
+// t = a_k - b_k (the caller takes the square root for l2).  Loads are issued
+// in batches of 8 x 16 bytes ahead of the (sequential) arithmetic, so a row
+// costs a few memory round trips instead of one per 16 bytes.  Both rows
+// must be read-only for the kernel that calls it (they are read through
+// the constant address space).
+template <int METRIC>
+__device__ __forceinline__ float canon_acc(const float *__restrict__ a,
+                                           const float *__restrict__ b, int d) {
+    float acc = 0.0f;
+    auto step = [&](float x, float y) {
+        const float t = x - y;
+        acc = METRIC == CHAMFER_L1 ? acc + fabsf(t) : fmaf(t, t, acc);
+    };
+    if ((d & 3) == 0 &&
+        ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+        const auto *a4 = reinterpret_cast<const CH_RO float4 *>(ro(a));
+        const auto *b4 = reinterpret_cast<const CH_RO float4 *>(ro(b));
+        const int d4 = d >> 2;
+        constexpr int kBatch = 8;
+        for (int k0 = 0; k0 < d4; k0 += kBatch) {
+            float4 u[kBatch], v[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i)
+                if (k0 + i < d4) {
+                    u[i] = ld(a4 + k0 + i);
+                    v[i] = ld(b4 + k0 + i);
+                }
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i)
+                if (k0 + i < d4) {
+                    step(u[i].x, v[i].x);
+                    step(u[i].y, v[i].y);
+                    step(u[i].z, v[i].z);
+                    step(u[i].w, v[i].w);
+                }
+        }
+        return acc;
+    }
+    constexpr int kBatch = 16;
+    for (int k0 = 0; k0 < d; k0 += kBatch) {
+        float u[kBatch], v[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (k0 + i < d) {
+                u[i] = ro(a)[k0 + i];
+                v[i] = ro(b)[k0 + i];
+            }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i)
+            if (k0 + i < d) step(u[i], v[i]);
+    }
+    return acc;
+}
+
+// Persistent loop of a batched stage: workgroup g takes the batch's blocks
+// g, g + gridDim.x, ... of the stage (jobs in order, each job's blocks
+// consecutive) and runs body(job, request-local coordinates).  The bodies
+// have no barrier after a wave-dependent return, so the barrier that closes
+// each iteration is reached by every wavefront.
+template <class Body>
+__device__ __forceinline__ void batch_loop(const Batch *__restrict__ bt, int stage, Body &&body) {
+    __shared__ int32_t st[kBatchMax + 1];
+    const int nj = bt->njobs;
+    for (int i = threadIdx.x; i <= nj; i += blockDim.x) st[i] = bt->start[stage][i];
+    __syncthreads();
+    const int total = st[nj];
+    int j = 0;
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        while (st[j + 1] <= v) ++j;
+        j = __builtin_amdgcn_readfirstlane(j);
+        body(bt->job[j], Blk{(int64_t)(v - st[j]), (int64_t)(st[j + 1] - st[j])});
+        __syncthreads();
+    }
+}
 
 // --------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipGetLastError().
@@ -206,5 +327,64 @@ hipError_t launch_sum_final(const double *partial, int64_t nparts, const DevPara
                             double *out, hipStream_t st);
 hipError_t launch_copy_status(const DevParams *p, int32_t *status_out, hipStream_t st);
 int nn_finalize_blocks(int64_t nx);
+
+// ------------------------------------------------------------ geometry
+// Block counts of the direct launches, shared with the batched ones.
+int64_t init_blocks(int d);
+int64_t grid_table_blocks(int L, int kh);
+int64_t table_fill_blocks(size_t count);
+// minmax over n rows: float4 form when vec4; stride in elements (or float4)
+void minmax_geom(int64_t n, int d, bool vec4, int64_t *blocks, int64_t *stride);
+bool minmax_vec4(const float *X, int d);
+int64_t hash_blocks(int64_t n);
+int64_t scan_blocks(int64_t nA);
+int64_t sample_blocks(int64_t T);
+int64_t cast_blocks(int64_t n);
+struct NNGeom {
+    int64_t blocks, chunk;
+    int32_t nchunk;
+};
+// target: workgroups the split of B aims for (0: the direct-launch target)
+NNGeom valu_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
+NNGeom mfma_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
+constexpr int64_t kValuTargetWGs = 4096;
+NNGeom lowp_geom(int64_t nx, int64_t nB, int d, int precision);
+constexpr int kMaxLdsL1Dim = 240;  // widest l1 tile staged in LDS by the hash
+
+// --------------------------------------------------------- batched launches
+// Each launches one persistent grid over every job of *bt (device memory);
+// d, metric, ke and precision are the same for every job of the batch.
+hipError_t launch_batch_setup(const Batch *bt, hipStream_t st);
+hipError_t launch_batch_minmax(const Batch *bt, int d, hipStream_t st);
+hipError_t launch_batch_calib(const Batch *bt, int d, hipStream_t st);
+hipError_t launch_batch_hash(int mode, const Batch *bt, int d, int metric, int ke,
+                             hipStream_t st);
+hipError_t launch_batch_weights(const Batch *bt, hipStream_t st);
+hipError_t launch_batch_sample(const Batch *bt, hipStream_t st);
+hipError_t launch_batch_cast(const Batch *bt, int d, int precision, hipStream_t st);
+hipError_t launch_batch_nn(const Batch *bt, int d, int metric, int precision, hipStream_t st);
+hipError_t launch_batch_mfma(const Batch *bt, int d, hipStream_t st);
+hipError_t launch_batch_lowp(const Batch *bt, int d, int precision, hipStream_t st);
+hipError_t launch_batch_final(const Batch *bt, int metric, hipStream_t st);
+
+// Host side of batching (api.hip): validate a request and fill its job with
+// the layout of chamfer_estimate in workspace ws; for l2, embed_host
+// receives the transposed embedding ([d][ke] floats) that the caller must
+// place at embed_dev before the batch runs.
+int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t d,
+                int32_t metric, double eps, int64_t T, uint64_t seed, const chamfer_opts *opts,
+                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const float *embed_dev,
+                float *embed_host, Job *job);
+// Block counts of every stage of a job.
+void job_stage_blocks(const Job &job, int64_t out[kBsCount]);
+// Re-split B for the exact pass of a job in a batch: the exact float32
+// passes give the exact nearest neighbour for any split, so a batch shares
+// one workgroup target among its jobs in proportion to their work instead
+// of every job splitting B finely enough to fill the device alone.  The
+// low-precision pass keeps the direct split (its candidates depend on it).
+void job_share_nn(Job *jobs, int n);
+// The launch sequence of a batched estimate (what a captured graph holds).
+int launch_estimate_batch(const Batch *bt, int d, int metric, int ke, int precision,
+                          hipStream_t st);
 
 }  // namespace chamfer

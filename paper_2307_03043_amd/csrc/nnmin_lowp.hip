@@ -30,10 +30,13 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 constexpr int kLpTileRows = 32;
 constexpr float kFp8Range = 240.0f;
 
-int lowp_dpad(int d, int precision) {
+// Row length after zero padding to whole MFMA K steps (32 BF16 / 128 FP8).
+__host__ __device__ inline int padded_dim(int d, int precision) {
     if (precision == CHAMFER_BF16) return (d + 31) / 32 * 32;
     return (d + 127) / 128 * 128;
 }
+
+int lowp_dpad(int d, int precision) { return padded_dim(d, precision); }
 
 bool lowp_supported(int d, int metric, int precision) {
     return metric == CHAMFER_L2 && precision != CHAMFER_FP32 && d >= 12 && d <= 256;
@@ -55,16 +58,16 @@ __device__ __forceinline__ float bf16_to_float(uint16_t h) {
 
 // One wavefront per row: lane l takes coordinates 4l .. 4l+3 (dpad <= 256).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_cast_rows(const float *__restrict__ X,
-                                                   const int32_t *__restrict__ rows, int64_t n,
-                                                   int d, int dpad, uint8_t *out, float *scale,
-                                                   float *n2, const DevParams *p) {
+__device__ __forceinline__ void cast_rows(const float *__restrict__ X,
+                                          const int32_t *__restrict__ rows, int64_t n, int d,
+                                          int dpad, uint8_t *out, float *scale, float *n2,
+                                          const DevParams *p, Blk blk) {
     if (p->status != CHAMFER_OK) return;
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = blk.id * 4 + (threadIdx.x >> 6);
     if (r >= n) return;  // whole wavefront
-    const int64_t src = rows ? (int64_t)rows[r] : r;
-    const float *x = X + src * d;
+    const int64_t src = rows ? (int64_t)ro(rows)[r] : r;
+    const auto *x = ro(X) + src * d;
     float v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -107,12 +110,22 @@ __global__ __launch_bounds__(256) void k_cast_rows(const float *__restrict__ X,
     if (lane == 0) n2[r] = sq;
 }
 
+template <int PREC>
+__global__ __launch_bounds__(256) void k_cast_rows(const float *__restrict__ X,
+                                                   const int32_t *__restrict__ rows, int64_t n,
+                                                   int d, int dpad, uint8_t *out, float *scale,
+                                                   float *n2, const DevParams *p) {
+    cast_rows<PREC>(X, rows, n, d, dpad, out, scale, n2, p, grid_blk());
+}
+
+int64_t cast_blocks(int64_t n) { return (n + 3) / 4; }
+
 hipError_t launch_cast_rows(int precision, const float *X, const int32_t *rows, int64_t n, int d,
                             uint8_t *out, float *scale, float *n2, const DevParams *p,
                             hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int dpad = lowp_dpad(d, precision);
-    const unsigned blocks = (unsigned)((n + 3) / 4);
+    const unsigned blocks = (unsigned)cast_blocks(n);
     if (precision == CHAMFER_BF16)
         k_cast_rows<CHAMFER_BF16><<<blocks, 256, 0, st>>>(X, rows, n, d, dpad, out, scale, n2, p);
     else
@@ -126,12 +139,13 @@ __device__ __forceinline__ unsigned long long pack_lp(float v, int64_t b) {
 
 // Queries q < nx are rows of Xq (cast), their float32 originals rows[q] of X.
 template <int PREC, int DP, int NB>
-__global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
+__device__ __forceinline__ void nnmin_l2_lowp(
     const uint8_t *__restrict__ Xq, const float *__restrict__ xsc, int64_t nx,
     const float *__restrict__ X, const int32_t *__restrict__ rows,
     const uint8_t *__restrict__ Bq, const float *__restrict__ bsc,
     const float *__restrict__ bn2, const float *__restrict__ B, int64_t nB, int d,
-    int64_t chunk, int nchunk, unsigned long long *best, const DevParams *__restrict__ p) {
+    int64_t chunk, int nchunk, unsigned long long *best, const DevParams *__restrict__ p,
+    Blk blk) {
     constexpr int ES = PREC == CHAMFER_BF16 ? 2 : 1;  // bytes per element
     constexpr int RB = DP * ES;                       // bytes per row
     constexpr int QB = RB / 4;                        // bytes per 16-lane group
@@ -147,8 +161,8 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int cb = blockIdx.x % nchunk;
-    const int64_t qbase = ((int64_t)(blockIdx.x / nchunk) * 4 + wave) * (16 * NB);
+    const int cb = (int)(blk.id % nchunk);
+    const int64_t qbase = ((blk.id / nchunk) * 4 + wave) * (16 * NB);
     const int64_t b0 = (int64_t)cb * chunk;
     const int64_t b1 = min(nB, b0 + chunk);
     if (b0 >= b1) return;
@@ -161,10 +175,10 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
         const int64_t r = qi < nx ? qi : 0;
-        const uint4 *src = reinterpret_cast<const uint4 *>(Xq + (size_t)r * RB + g * QB);
+        const auto *src = reinterpret_cast<const CH_RO uint4 *>(ro(Xq) + (size_t)r * RB + g * QB);
 #pragma unroll
-        for (int u = 0; u < QB / 16; ++u) qf[nb][u] = src[u];
-        qs[nb] = xsc[r];
+        for (int u = 0; u < QB / 16; ++u) qf[nb][u] = ld(src + u);
+        qs[nb] = ro(xsc)[r];
     }
     float b1v[NB], b2v[NB];
     int32_t b1i[NB], b2i[NB];
@@ -187,14 +201,14 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
                 const int row = v / (RB / 16);
                 const int u = v - row * (RB / 16);
                 if (t0 + row < b1)
-                    val = reinterpret_cast<const uint4 *>(Bq + (size_t)(t0 + row) * RB)[u];
+                    val = ld(reinterpret_cast<const CH_RO uint4 *>(ro(Bq) + (size_t)(t0 + row) * RB) + u);
             }
             pf[i] = val;
         }
         if (tid < kLpTileRows) {
             const bool ok = t0 + tid < b1;
-            pn2 = ok ? bn2[t0 + tid] : INFINITY;
-            psc = ok ? bsc[t0 + tid] : 0.0f;
+            pn2 = ok ? ro(bn2)[t0 + tid] : INFINITY;
+            psc = ok ? ro(bsc)[t0 + tid] : 0.0f;
         }
     };
 
@@ -297,7 +311,7 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
         const bool valid = qi < nx;
-        const int64_t xr = valid ? (rows ? (int64_t)rows[qi] : qi) : 0;
+        const int64_t xr = valid ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
         unsigned long long mine = ~0ull;
         if (valid && b1i[nb] >= 0)
             mine = pack_lp(canon_acc<CHAMFER_L2>(X + xr * d, B + (int64_t)b1i[nb] * d, d), b1i[nb]);
@@ -311,11 +325,24 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
 }
 
 template <int PREC, int DP, int NB>
-static hipError_t go_lowp(const uint8_t *Xq, const float *xsc, int64_t nx, const float *X,
-                          const int32_t *rows, const uint8_t *Bq, const float *bsc,
-                          const float *bn2, const float *B, int64_t nB, int d,
-                          unsigned long long *best, const DevParams *p, hipStream_t st) {
-    const int64_t per_wg = 64 * NB;
+__global__ __launch_bounds__(256) void k_nnmin_l2_lowp(
+    const uint8_t *__restrict__ Xq, const float *__restrict__ xsc, int64_t nx,
+    const float *__restrict__ X, const int32_t *__restrict__ rows,
+    const uint8_t *__restrict__ Bq, const float *__restrict__ bsc,
+    const float *__restrict__ bn2, const float *__restrict__ B, int64_t nB, int d,
+    int64_t chunk, int nchunk, unsigned long long *best, const DevParams *__restrict__ p) {
+    nnmin_l2_lowp<PREC, DP, NB>(Xq, xsc, nx, X, rows, Bq, bsc, bn2, B, nB, d, chunk, nchunk, best,
+                                p, grid_blk());
+}
+
+// 16-query blocks per wavefront for (precision, padded dimension).
+static int lowp_nb(int precision, int dp) {
+    if (precision == CHAMFER_BF16) return dp <= 64 ? 4 : 2;
+    return dp == 128 ? 4 : 2;
+}
+
+NNGeom lowp_geom(int64_t nx, int64_t nB, int d, int precision) {
+    const int64_t per_wg = 64 * lowp_nb(precision, lowp_dpad(d, precision));
     const int64_t nq = (nx + per_wg - 1) / per_wg;
     // large chunks (the re-rank runs once per chunk), enough workgroups
     int64_t nc = (2048 + nq - 1) / nq;
@@ -323,10 +350,21 @@ static hipError_t go_lowp(const uint8_t *Xq, const float *xsc, int64_t nx, const
     if (nc > cmax) nc = cmax;
     if (nc < 1) nc = 1;
     if (nc > 1) nc = (nc + 7) / 8 * 8;
-    const int64_t chunk = (nB + nc - 1) / nc;
-    const int nchunk = (int)((nB + chunk - 1) / chunk);
-    k_nnmin_l2_lowp<PREC, DP, NB><<<(unsigned)(nq * nchunk), 256, 0, st>>>(
-        Xq, xsc, nx, X, rows, Bq, bsc, bn2, B, nB, d, chunk, nchunk, best, p);
+    NNGeom g;
+    g.chunk = (nB + nc - 1) / nc;
+    g.nchunk = (int)((nB + g.chunk - 1) / g.chunk);
+    g.blocks = nq * g.nchunk;
+    return g;
+}
+
+template <int PREC, int DP, int NB>
+static hipError_t go_lowp(const uint8_t *Xq, const float *xsc, int64_t nx, const float *X,
+                          const int32_t *rows, const uint8_t *Bq, const float *bsc,
+                          const float *bn2, const float *B, int64_t nB, int d,
+                          unsigned long long *best, const DevParams *p, hipStream_t st) {
+    const NNGeom g = lowp_geom(nx, nB, d, PREC);
+    k_nnmin_l2_lowp<PREC, DP, NB><<<(unsigned)g.blocks, 256, 0, st>>>(
+        Xq, xsc, nx, X, rows, Bq, bsc, bn2, B, nB, d, g.chunk, g.nchunk, best, p);
     return hipGetLastError();
 }
 
@@ -353,6 +391,66 @@ hipError_t launch_nnmin_lowp(int precision, const uint8_t *Xq, const float *xsc,
     if (dp == 128) return go_lowp<CHAMFER_FP8, 128, 4>(LP_ARGS);
     return go_lowp<CHAMFER_FP8, 256, 2>(LP_ARGS);
 #undef LP_ARGS
+}
+
+// ---------------------------------------------------------------- batched
+// Low-precision copies of each job's B and sampled rows, then the pass.  The
+// float sidecars of a job live at lpf: scale and |.|^2 of B (nB each), then
+// of the samples (T each).
+
+constexpr unsigned kGridCast = 1024, kGridNNLowp = 2048;
+
+template <int PREC>
+__global__ __launch_bounds__(256) void kb_cast(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsCast, [&](const Job &J, Blk b) {
+        const int dpad = padded_dim(J.d, PREC);
+        float *bsc = J.lpf, *bn2 = J.lpf + J.nB, *xsc = J.lpf + 2 * J.nB, *xn2 = xsc + J.T;
+        if (b.id < J.nb_castB)
+            cast_rows<PREC>(J.B, nullptr, J.nB, J.d, dpad, J.bq, bsc, bn2, J.p,
+                            Blk{b.id, J.nb_castB});
+        else
+            cast_rows<PREC>(J.A, J.idx, J.T, J.d, dpad, J.xq, xsc, xn2, J.p,
+                            Blk{b.id - J.nb_castB, J.nb_castX});
+    });
+}
+
+template <int PREC, int DP, int NB>
+__global__ __launch_bounds__(256) void kb_nn_lowp(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
+        const float *bsc = J.lpf, *bn2 = J.lpf + J.nB, *xsc = J.lpf + 2 * J.nB;
+        nnmin_l2_lowp<PREC, DP, NB>(J.xq, xsc, J.T, J.A, J.idx, J.bq, bsc, bn2, J.B, J.nB, J.d,
+                                    J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
+    });
+}
+
+hipError_t launch_batch_cast(const Batch *bt, int d, int precision, hipStream_t st) {
+    (void)d;
+    if (precision == CHAMFER_BF16)
+        kb_cast<CHAMFER_BF16><<<kGridCast, 256, 0, st>>>(bt);
+    else
+        kb_cast<CHAMFER_FP8><<<kGridCast, 256, 0, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_lowp(const Batch *bt, int d, int precision, hipStream_t st) {
+    const int dp = lowp_dpad(d, precision);
+    if (precision == CHAMFER_BF16) {
+        switch (dp) {
+            case 32: kb_nn_lowp<CHAMFER_BF16, 32, 4><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 64: kb_nn_lowp<CHAMFER_BF16, 64, 4><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 96: kb_nn_lowp<CHAMFER_BF16, 96, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 128: kb_nn_lowp<CHAMFER_BF16, 128, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 160: kb_nn_lowp<CHAMFER_BF16, 160, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 192: kb_nn_lowp<CHAMFER_BF16, 192, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            case 224: kb_nn_lowp<CHAMFER_BF16, 224, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+            default: kb_nn_lowp<CHAMFER_BF16, 256, 2><<<kGridNNLowp, 256, 0, st>>>(bt); break;
+        }
+    } else if (dp == 128) {
+        kb_nn_lowp<CHAMFER_FP8, 128, 4><<<kGridNNLowp, 256, 0, st>>>(bt);
+    } else {
+        kb_nn_lowp<CHAMFER_FP8, 256, 2><<<kGridNNLowp, 256, 0, st>>>(bt);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace chamfer

@@ -100,10 +100,10 @@ hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevPara
 }
 
 template <int DP, int NB>
-__global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
+__device__ __forceinline__ void nnmin_l2_mfma(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const float *__restrict__ B, int64_t nB, int d, const float *__restrict__ nb2,
-    int64_t chunk, int nchunk, unsigned long long *best, DevParams *p) {
+    int64_t chunk, int nchunk, unsigned long long *best, DevParams *p, Blk blk) {
     constexpr int KQ = DP / 4;                // coordinates per 16-lane group
     constexpr int LDR = DP + 4;               // padded LDS row (floats)
     constexpr int NV4 = kTileRows * DP / 4;   // float4 per tile
@@ -115,8 +115,8 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int cb = blockIdx.x % nchunk;
-    const int64_t qbase = ((int64_t)(blockIdx.x / nchunk) * 4 + wave) * (16 * NB);
+    const int cb = (int)(blk.id % nchunk);
+    const int64_t qbase = ((blk.id / nchunk) * 4 + wave) * (16 * NB);
     const int64_t b0 = (int64_t)cb * chunk;
     const int64_t b1 = min(nB, b0 + chunk);
     if (b0 >= b1) return;  // uniform over the workgroup
@@ -131,9 +131,9 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
-        const int64_t r = qi < nx ? (rows ? (int64_t)rows[qi] : qi) : 0;
+        const int64_t r = qi < nx ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
         qrow[nb] = r;
-        const float *xr = X + r * d;
+        const auto *xr = ro(X) + r * d;
         float s2 = 0.0f;
 #pragma unroll
         for (int s = 0; s < KQ; ++s) {
@@ -168,9 +168,9 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
                 const int k0 = (v - row * (DP / 4)) * 4;
                 const int64_t br = t0 + row;
                 if (br < b1 && k0 < d) {
-                    const float *src = B + br * d + k0;
+                    const CH_RO float *src = ro(B) + br * d + k0;
                     if (vec_ok) {
-                        val = *reinterpret_cast<const float4 *>(src);
+                        val = ld(reinterpret_cast<const CH_RO float4 *>(src));
                     } else {
                         val.x = src[0];
                         if (k0 + 1 < d) val.y = src[1];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
             }
             pf[i] = val;
         }
-        if (tid < kTileRows) pn2 = (t0 + tid < b1) ? nb2[t0 + tid] : INFINITY;
+        if (tid < kTileRows) pn2 = (t0 + tid < b1) ? ro(nb2)[t0 + tid] : INFINITY;
     };
 
     int64_t t0 = b0;
@@ -305,25 +305,48 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
     }
 }
 
+template <int DP, int NB>
+__global__ __launch_bounds__(256) void k_nnmin_l2_mfma(
+    const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const float *__restrict__ B, int64_t nB, int d, const float *__restrict__ nb2,
+    int64_t chunk, int nchunk, unsigned long long *best, DevParams *p) {
+    nnmin_l2_mfma<DP, NB>(X, rows, nx, B, nB, d, nb2, chunk, nchunk, best, p, grid_blk());
+}
+
 bool mfma_supported(int d, int metric) { return metric == CHAMFER_L2 && d >= 12 && d <= 256; }
 
-template <int DP, int NB>
-static hipError_t go_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                          int64_t nB, int d, unsigned long long *best, const float *nb2,
-                          DevParams *p, hipStream_t st) {
-    const int64_t per_wg = 64 * NB;
+// Queries per 16-lane group (NB) of the padded-dimension class of d.
+static int mfma_nb(int d) {
+    if (d <= 64) return 2;
+    if (d <= 128) return kMfmaNB128;
+    return 1;
+}
+
+NNGeom mfma_geom(int64_t nx, int64_t nB, int d, int64_t target) {
+    const int64_t per_wg = 64 * mfma_nb(d);
     const int64_t nq = (nx + per_wg - 1) / per_wg;
     // enough workgroups to fill 256 CUs several times; chunks of 256..8192 rows
-    int64_t nc = (kMfmaTargetWGs + nq - 1) / nq;
+    if (target <= 0) target = kMfmaTargetWGs;
+    int64_t nc = (target + nq - 1) / nq;
     const int64_t cmin = (nB + 8191) / 8192, cmax = (nB + 255) / 256;
     if (nc < cmin) nc = cmin;
     if (nc > cmax) nc = cmax;
     if (nc < 1) nc = 1;
     if (nc > 1) nc = (nc + 7) / 8 * 8;  // one chunk's workgroups share an XCD
-    const int64_t chunk = (nB + nc - 1) / nc;
-    const int nchunk = (int)((nB + chunk - 1) / chunk);
-    k_nnmin_l2_mfma<DP, NB><<<(unsigned)(nq * nchunk), 256, 0, st>>>(
-        X, rows, nx, B, nB, d, nb2, chunk, nchunk, best, p);
+    NNGeom g;
+    g.chunk = (nB + nc - 1) / nc;
+    g.nchunk = (int)((nB + g.chunk - 1) / g.chunk);
+    g.blocks = nq * g.nchunk;
+    return g;
+}
+
+template <int DP, int NB>
+static hipError_t go_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
+                          int64_t nB, int d, unsigned long long *best, const float *nb2,
+                          DevParams *p, hipStream_t st) {
+    const NNGeom g = mfma_geom(nx, nB, d);
+    k_nnmin_l2_mfma<DP, NB><<<(unsigned)g.blocks, 256, 0, st>>>(X, rows, nx, B, nB, d, nb2, g.chunk,
+                                                                 g.nchunk, best, p);
     return hipGetLastError();
 }
 
@@ -336,6 +359,32 @@ hipError_t launch_nnmin_mfma(const float *X, const int32_t *rows, int64_t nx, co
     if (d <= 64) return go_mfma<64, 2>(X, rows, nx, B, nB, d, best, nb2, p, st);
     if (d <= 128) return go_mfma<128, kMfmaNB128>(X, rows, nx, B, nB, d, best, nb2, p, st);
     return go_mfma<256, 1>(X, rows, nx, B, nB, d, best, nb2, p, st);
+}
+
+// ---------------------------------------------------------------- batched
+
+constexpr unsigned kGridNNMfma = 2048;
+
+template <int DP, int NB>
+__global__ __launch_bounds__(256) void kb_nn_mfma(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
+        nnmin_l2_mfma<DP, NB>(J.A, J.idx, J.T, J.B, J.nB, J.d, J.nb2, J.nn_chunk, J.nn_nchunk,
+                              J.best, J.p, b);
+    });
+}
+
+hipError_t launch_batch_mfma(const Batch *bt, int d, hipStream_t st) {
+    if (d <= 16)
+        kb_nn_mfma<16, 2><<<kGridNNMfma, 256, 0, st>>>(bt);
+    else if (d <= 32)
+        kb_nn_mfma<32, 2><<<kGridNNMfma, 256, 0, st>>>(bt);
+    else if (d <= 64)
+        kb_nn_mfma<64, 2><<<kGridNNMfma, 256, 0, st>>>(bt);
+    else if (d <= 128)
+        kb_nn_mfma<128, kMfmaNB128><<<kGridNNMfma, 256, 0, st>>>(bt);
+    else
+        kb_nn_mfma<256, 1><<<kGridNNMfma, 256, 0, st>>>(bt);
+    return hipGetLastError();
 }
 
 }  // namespace chamfer

@@ -41,27 +41,33 @@ __device__ unsigned long long block_inclusive_scan(unsigned long long v,
     return r;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_weight_blocksum(
-    const float *__restrict__ D, int64_t nA, int q, unsigned long long *blocksums,
-    const DevParams *p) {
+__device__ __forceinline__ void weight_blocksum(const float *__restrict__ D, int64_t nA, int q,
+                                                unsigned long long *blocksums, const DevParams *p,
+                                                Blk b) {
     __shared__ unsigned long long buf[kScanThreads];
     if (p->status != CHAMFER_OK) return;
     const uint32_t mb = p->max_d_bits;
     unsigned long long sum = 0;
     if (__uint_as_float(mb) > 0.0f) {
         const int s = fixed_point_exponent(mb, q);
-        const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+        const int64_t base = b.id * kScanBlock + threadIdx.x * kScanItems;
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j)
-            if (base + j < nA) sum += weight_of(D[base + j], s);
+            if (base + j < nA) sum += weight_of(ro(D)[base + j], s);
     }
     const unsigned long long inc = block_inclusive_scan<kScanThreads>(sum, buf);
-    if (threadIdx.x == kScanThreads - 1) blocksums[blockIdx.x] = inc;
+    if (threadIdx.x == kScanThreads - 1) blocksums[b.id] = inc;
 }
 
-// Exclusive scan of the block sums in place; W = total.
-__global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blocksums,
-                                                         int64_t nblk, int q, DevParams *p) {
+__global__ __launch_bounds__(kScanThreads) void k_weight_blocksum(
+    const float *__restrict__ D, int64_t nA, int q, unsigned long long *blocksums,
+    const DevParams *p) {
+    weight_blocksum(D, nA, q, blocksums, p, grid_blk());
+}
+
+// Exclusive scan of the block sums in place; W = total.  One block of 1024.
+__device__ __forceinline__ void scan_blocksums(unsigned long long *blocksums, int64_t nblk, int q,
+                                               DevParams *p) {
     __shared__ unsigned long long buf[1024];
     if (p->status != CHAMFER_OK) return;
     unsigned long long carry = 0;
@@ -86,24 +92,28 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blo
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_prefix(const float *__restrict__ D, int64_t nA,
-                                                         const unsigned long long *blockoffs,
-                                                         unsigned long long *P,
-                                                         const DevParams *p) {
+__global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blocksums,
+                                                         int64_t nblk, int q, DevParams *p) {
+    scan_blocksums(blocksums, nblk, q, p);
+}
+
+__device__ __forceinline__ void prefix(const float *__restrict__ D, int64_t nA,
+                                       const unsigned long long *blockoffs,
+                                       unsigned long long *P, const DevParams *p, Blk b) {
     __shared__ unsigned long long buf[kScanThreads];
     if (p->status != CHAMFER_OK) return;
     const int s = p->s;
     const bool zero = p->all_zero != 0;
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    const int64_t base = b.id * kScanBlock + threadIdx.x * kScanItems;
     unsigned long long w[kScanItems];
     unsigned long long own = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        w[j] = (!zero && base + j < nA) ? weight_of(D[base + j], s) : 0ull;
+        w[j] = (!zero && base + j < nA) ? weight_of(ro(D)[base + j], s) : 0ull;
         own += w[j];
     }
     const unsigned long long inc = block_inclusive_scan<kScanThreads>(own, buf);
-    unsigned long long run = blockoffs[blockIdx.x] + inc - own;
+    unsigned long long run = ro(blockoffs)[b.id] + inc - own;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         run += w[j];
@@ -111,9 +121,18 @@ __global__ __launch_bounds__(kScanThreads) void k_prefix(const float *__restrict
     }
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_prefix(const float *__restrict__ D, int64_t nA,
+                                                         const unsigned long long *blockoffs,
+                                                         unsigned long long *P,
+                                                         const DevParams *p) {
+    prefix(D, nA, blockoffs, P, p, grid_blk());
+}
+
+int64_t scan_blocks(int64_t nA) { return (nA + kScanBlock - 1) / kScanBlock; }
+
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
                           DevParams *p, hipStream_t st) {
-    const int64_t nblk = (nA + kScanBlock - 1) / kScanBlock;
+    const int64_t nblk = scan_blocks(nA);
     auto *bs = reinterpret_cast<unsigned long long *>(blocksums);
     k_weight_blocksum<<<(unsigned)nblk, kScanThreads, 0, st>>>(D, nA, q, bs, p);
     k_scan_blocksums<<<1, 1024, 0, st>>>(bs, nblk, q, p);
@@ -127,10 +146,10 @@ hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums
 // (seed, 0); Lemire: m = x W, reject while (m mod 2^64) < (2^64 - W) mod W,
 // u = m >> 64; idx = min{a : P_a > u}.  Also resets the nearest-neighbour
 // slot of the draw.
-__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P, int64_t nA,
-                         int64_t T, int32_t *idx, unsigned long long *best,
-                         const DevParams *p) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *__restrict__ P,
+                                       int64_t nA, int64_t T, int32_t *idx,
+                                       unsigned long long *best, const DevParams *p, Blk blk) {
+    const int64_t l = blk.id * blockDim.x + threadIdx.x;
     if (l >= T) return;
     best[l] = ~0ull;
     const uint64_t W = p->W;
@@ -153,7 +172,7 @@ __global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P
     int64_t a = 0, b = nA - 1;
     while (a < b) {
         const int64_t mid = a + ((b - a) >> 1);
-        if (P[mid] > u)
+        if (ro(P)[mid] > u)
             b = mid;
         else
             a = mid + 1;
@@ -161,19 +180,28 @@ __global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P
     idx[l] = (int32_t)a;
 }
 
+__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P, int64_t nA,
+                         int64_t T, int32_t *idx, unsigned long long *best,
+                         const DevParams *p) {
+    sample(seed, P, nA, T, idx, best, p, grid_blk());
+}
+
+int64_t sample_blocks(int64_t T) { return (T + 255) / 256; }
+
 hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,
                          unsigned long long *best, DevParams *p, hipStream_t st) {
     if (T <= 0) return hipSuccess;
-    k_sample<<<(unsigned)((T + 255) / 256), 256, 0, st>>>(
+    k_sample<<<(unsigned)sample_blocks(T), 256, 0, st>>>(
         seed, reinterpret_cast<const unsigned long long *>(P), nA, T, idx, best, p);
     return hipGetLastError();
 }
 
 // eta = (1/T) sum_l (W / w_{x_l}) m_l; one block, fixed summation order.
-__global__ __launch_bounds__(256) void k_estimate_final(
-    const unsigned long long *__restrict__ best, const int32_t *__restrict__ idx,
-    const float *__restrict__ D, int64_t T, int metric, const DevParams *p, double *eta_out,
-    chamfer_aux aux) {
+__device__ __forceinline__ void estimate_final(const unsigned long long *__restrict__ best,
+                                               const int32_t *__restrict__ idx,
+                                               const float *__restrict__ D, int64_t T, int metric,
+                                               const DevParams *p, double *eta_out,
+                                               const chamfer_aux &aux) {
     __shared__ double red[256];
     const int t = threadIdx.x;
     const int status = p->status;
@@ -181,13 +209,13 @@ __global__ __launch_bounds__(256) void k_estimate_final(
     const int s = p->s;
     double acc = 0.0;
     for (int64_t l = t; l < T; l += 256) {
-        const unsigned long long b = best[l];
+        const unsigned long long b = ro(best)[l];
         const float v = __uint_as_float((uint32_t)(b >> 32));
         const int32_t nn = (int32_t)(uint32_t)(b & 0xffffffffu);
         float m = metric == CHAMFER_L2 ? sqrtf(v) : v;
         if (status != CHAMFER_OK) m = __builtin_nanf("");
         if (status == CHAMFER_OK && W != 0) {
-            const double w = (double)weight_of(D[idx[l]], s);
+            const double w = (double)weight_of(ro(D)[ro(idx)[l]], s);
             acc += ((double)W / w) * (double)m;
         }
         if (aux.sample_min) aux.sample_min[l] = (status == CHAMFER_OK && W == 0) ? 0.0f : m;
@@ -211,6 +239,13 @@ __global__ __launch_bounds__(256) void k_estimate_final(
     }
 }
 
+__global__ __launch_bounds__(256) void k_estimate_final(
+    const unsigned long long *__restrict__ best, const int32_t *__restrict__ idx,
+    const float *__restrict__ D, int64_t T, int metric, const DevParams *p, double *eta_out,
+    chamfer_aux aux) {
+    estimate_final(best, idx, D, T, metric, p, eta_out, aux);
+}
+
 hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *idx,
                                  const float *D, int64_t T, int metric, DevParams *p,
                                  double *eta_out, chamfer_aux aux, hipStream_t st) {
@@ -224,6 +259,58 @@ __global__ void k_copy_status(const DevParams *p, int32_t *out) {
 
 hipError_t launch_copy_status(const DevParams *p, int32_t *status_out, hipStream_t st) {
     k_copy_status<<<1, 64, 0, st>>>(p, status_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched
+
+constexpr unsigned kGridScan = 1024, kGridWscan = kBatchMax, kGridSample = 256,
+                   kGridFinal = kBatchMax;
+
+__global__ __launch_bounds__(kScanThreads) void kb_wsum(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsWsum, [&](const Job &J, Blk b) {
+        weight_blocksum(J.D, J.nA, J.q, J.blocksums, J.p, b);
+    });
+}
+
+__global__ __launch_bounds__(1024) void kb_wscan(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsWscan, [&](const Job &J, Blk) {
+        scan_blocksums(J.blocksums, J.nb_scan, J.q, J.p);
+    });
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_prefix(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsPrefix, [&](const Job &J, Blk b) {
+        prefix(J.D, J.nA, J.blocksums, J.P, J.p, b);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_sample(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsSample, [&](const Job &J, Blk b) {
+        sample(J.seed, J.P, J.nA, J.T, J.idx, J.best, J.p, b);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_final(const Batch *__restrict__ bt, int metric) {
+    batch_loop(bt, kBsFinal, [&](const Job &J, Blk) {
+        estimate_final(J.best, J.idx, J.D, J.T, metric, J.p, J.eta, J.aux);
+    });
+}
+
+hipError_t launch_batch_weights(const Batch *bt, hipStream_t st) {
+    kb_wsum<<<kGridScan, kScanThreads, 0, st>>>(bt);
+    kb_wscan<<<kGridWscan, 1024, 0, st>>>(bt);
+    kb_prefix<<<kGridScan, kScanThreads, 0, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sample(const Batch *bt, hipStream_t st) {
+    kb_sample<<<kGridSample, 256, 0, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_final(const Batch *bt, int metric, hipStream_t st) {
+    kb_final<<<kGridFinal, 256, 0, st>>>(bt, metric);
     return hipGetLastError();
 }
 

@@ -120,5 +120,6 @@ def test_server_argument_errors_are_host_side():
     assert lib.chamfer_server_create(1 << 20, 1000, ctypes.byref(h)) == -1
     assert lib.chamfer_server_create(16, 4, ctypes.byref(h)) == -1
     assert lib.chamfer_server_submit(None, None, None) == -1
+    assert lib.chamfer_server_warm(None, 3, 2, 0, 0) == -1
     assert lib.chamfer_server_progress(None) == -1
     assert lib.chamfer_server_destroy(None) == -1

@@ -1,6 +1,8 @@
-"""Serving: requests through the continuous-batching server give the same
-result as the same call made alone, whatever else is in flight; admission
-respects the arena."""
+"""Serving: requests through the continuous-batching server (same-stage work
+of a whole batch in persistent launches replayed from captured graphs) give
+the same result as the same call made alone, whatever else is in the batch
+or in flight; admission respects the arena and keeps the oldest request
+first."""
 
 import numpy as np
 import pytest
@@ -49,7 +51,7 @@ def test_server_same_alone_and_in_mix(ch):
     arena = 3 * biggest  # only a few requests fit at once: admission binds
     results = {}
     max_in_flight = 0
-    with ch.ChamferServer(arena, slots=8) as srv:
+    with ch.ChamferServer(arena, lanes=4) as srv:
         ids = [srv.submit(r["A"], r["B"], r["metric"], r["eps"], 0, r["seed"],
                           precision=r["precision"]) for r in reqs]
         while len(results) < len(ids):
@@ -73,22 +75,136 @@ def test_server_same_alone_and_in_mix(ch):
 
 def test_server_rejects_oversized(ch):
     r = make_requests(1)[0]
-    with ch.ChamferServer(footprint(ch, r) // 4, slots=2) as srv:
+    with ch.ChamferServer(footprint(ch, r) // 4, lanes=2) as srv:
         with pytest.raises(ch.ChamferError):
             srv.submit(r["A"], r["B"], r["metric"], r["eps"], 0, r["seed"])
 
 
-def test_server_drains_burst_with_one_slot(ch):
-    reqs = make_requests(10, seed=5, n_max=5000)
-    with ch.ChamferServer(1 << 30, slots=1) as srv:
+def test_server_drains_burst_with_one_lane(ch):
+    """One lane: batches run one at a time, and every batch holds the oldest
+    request still queued when it was formed (everything fits the arena)."""
+    reqs = make_requests(24, seed=5, n_max=5000)
+    with ch.ChamferServer(1 << 30, lanes=1) as srv:
         ids = [srv.submit(r["A"], r["B"], r["metric"], r["eps"], 0, r["seed"]) for r in reqs]
         got = {}
         while len(got) < len(ids):
             srv.progress()
-            assert srv.stats()["in_flight"] <= 1
+            assert srv.stats()["lanes_busy"] <= 1
             for res in srv.results():
                 got[res["id"]] = res
+        st = srv.stats()
     assert sorted(got) == sorted(ids)
-    # admitted in order (one slot, everything fits)
-    admits = [got[i]["admit_s"] for i in ids]
-    assert admits == sorted(admits)
+    assert st["batches"] < len(ids)          # requests of one class shared a batch
+    pending = set(ids)
+    for t in sorted({got[i]["admit_s"] for i in ids}):
+        batch = {i for i in ids if got[i]["admit_s"] == t}
+        assert min(batch) == min(pending)
+        pending -= batch
+    assert not pending
+
+
+def _estimate_alone(ch, r):
+    out = ch.chamfer_estimate(r["A"].cuda(), r["B"].cuda(), r["metric"], r["eps"], r.get("T", 0),
+                              r["seed"], precision=r.get("precision", 0))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_server_one_class_one_graph(ch):
+    """Forty small requests of one class: a handful of batches, one graph per
+    lane used, each result identical to the call made alone."""
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(40):
+        n_a, n_b = (int(x) for x in rng.integers(100, 3000, size=2))
+        A = torch.from_numpy(rng.standard_normal((n_a, 3)).astype(np.float32)).pin_memory()
+        B = torch.from_numpy(rng.standard_normal((n_b, 3)).astype(np.float32)).pin_memory()
+        reqs.append(dict(A=A, B=B, metric=2, eps=0.2, seed=500 + i))
+    with ch.ChamferServer(1 << 30, lanes=2) as srv:
+        ids = [srv.submit(r["A"], r["B"], r["metric"], r["eps"], 0, r["seed"]) for r in reqs]
+        got = {}
+        while len(got) < len(ids):
+            srv.progress()
+            for res in srv.results():
+                got[res["id"]] = res
+        st = srv.stats()
+    assert st["batched"] == len(reqs)
+    assert st["batches"] <= 4
+    assert st["graphs"] <= 2
+    for rid, r in zip(ids, reqs):
+        alone = _estimate_alone(ch, r)
+        assert got[rid]["status"] == 0
+        assert got[rid]["eta"] == float(alone["eta"].item())
+        assert got[rid]["W"] == int(alone["W"].item())
+        assert got[rid]["s"] == int(alone["s"].item())
+        assert got[rid]["D"] == float(alone["D"].item())
+
+
+def test_server_edge_requests(ch):
+    """Degenerate and ragged requests batched together with ordinary ones:
+    empty A (finished at submit, eta 0), single points, a partial last tile,
+    explicit T, FP8, and a non-finite coordinate (status ENONFINITE, the
+    other members unaffected)."""
+    rng = np.random.default_rng(12)
+
+    def pts(n, d, scale=1.0):
+        return torch.from_numpy((rng.standard_normal((n, d)) * scale).astype(np.float32)).pin_memory()
+
+    bad = pts(300, 16)
+    bad[17, 5] = float("nan")
+    reqs = [dict(A=pts(0, 16), B=pts(50, 16), metric=2, eps=0.3, seed=1),
+            dict(A=pts(1, 16), B=pts(1, 16), metric=2, eps=0.3, seed=2),
+            dict(A=pts(65, 16), B=pts(129, 16), metric=2, eps=0.3, seed=3),
+            dict(A=pts(1, 3), B=pts(2, 3), metric=1, eps=0.5, seed=4),
+            dict(A=pts(777, 3), B=pts(1, 3), metric=1, eps=0.5, seed=5, T=33),
+            dict(A=bad, B=pts(400, 16), metric=2, eps=0.3, seed=6),
+            dict(A=pts(2000, 16), B=pts(3000, 16), metric=2, eps=0.3, seed=7),
+            dict(A=pts(1500, 128, 3.0), B=pts(2500, 128, 3.0), metric=2, eps=0.2, seed=8,
+                 precision=2),
+            dict(A=pts(1500, 128, 3.0), B=pts(2500, 128, 3.0), metric=2, eps=0.2, seed=9,
+                 precision=2)]
+    with ch.ChamferServer(1 << 30, lanes=2) as srv:
+        ids = [srv.submit(r["A"], r["B"], r["metric"], r["eps"], r.get("T", 0), r["seed"],
+                          precision=r.get("precision", 0)) for r in reqs]
+        got = {}
+        while len(got) < len(ids):
+            srv.progress()
+            for res in srv.results():
+                got[res["id"]] = res
+    for rid, r in zip(ids, reqs):
+        res = got[rid]
+        if r["A"].shape[0] == 0:
+            assert res["status"] == 0 and res["eta"] == 0.0
+            continue
+        alone = _estimate_alone(ch, r)
+        if r is reqs[5]:
+            assert res["status"] == -4 and int(alone["status"].item()) == -4
+            continue
+        assert res["status"] == 0, rid
+        assert res["eta"] == float(alone["eta"].item()), rid
+        assert res["W"] == int(alone["W"].item())
+
+
+def test_server_warm(ch):
+    """warm() instantiates a class graph on every lane once; a request of
+    that class then adds no graph; bad classes are rejected."""
+    with ch.ChamferServer(1 << 28, lanes=3) as srv:
+        srv.warm(3, 2)
+        srv.warm(3, 2)
+        assert srv.stats()["graphs"] == 3
+        srv.warm(128, 2, precision=1)
+        assert srv.stats()["graphs"] == 6
+        for bad in ((0, 2), (4096, 2), (3, 5)):
+            with pytest.raises(ch.ChamferError):
+                srv.warm(*bad)
+        rng = np.random.default_rng(13)
+        A = torch.from_numpy(rng.standard_normal((500, 3)).astype(np.float32)).pin_memory()
+        B = torch.from_numpy(rng.standard_normal((700, 3)).astype(np.float32)).pin_memory()
+        rid = srv.submit(A, B, 2, 0.2, 0, 77)
+        got = []
+        while not got:
+            srv.progress()
+            got = srv.results()
+        assert srv.stats()["graphs"] == 6
+    alone = _estimate_alone(ch, dict(A=A, B=B, metric=2, eps=0.2, seed=77))
+    assert got[0]["id"] == rid and got[0]["eta"] == float(alone["eta"].item())
