@@ -123,9 +123,12 @@ def measured_traffic(workload, kernel_ms):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    if not rec.get("sources"):
+        return None
+    for src, sha in rec["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
     return rec["traffic_bytes"]
 
 
@@ -248,6 +251,7 @@ def serve_run(srv, reqs, pool, precision, saturate=False):
     i = 0
     in_flight_sum = 0
     polls = 0
+    arena_max = 0
     while done < n:
         now = time.monotonic() - t0
         while i < n and (saturate or reqs[i].arrival_s <= now):
@@ -268,6 +272,7 @@ def serve_run(srv, reqs, pool, precision, saturate=False):
             done += 1
         st = srv.stats()
         in_flight_sum += st["in_flight"]
+        arena_max = max(arena_max, st["arena_used"])
         polls += 1
     wall = time.monotonic() - t0
     st = srv.stats()
@@ -280,7 +285,7 @@ def serve_run(srv, reqs, pool, precision, saturate=False):
                 mean_in_flight=in_flight_sum / max(polls, 1),
                 batches=batches, mean_batch=(st["batched"] - st0["batched"]) / max(batches, 1),
                 admission_stalls=st["stalls"] - st0["stalls"],
-                arena_peak_gib=st["arena_peak"] / 2**30, failed=int(np.isnan(etas).sum())), etas
+                arena_max_gib=arena_max / 2**30, failed=int(np.isnan(etas).sum())), etas
 
 
 SERVE_CLASSES = ((3, 1), (3, 2), (128, 1), (128, 2))
@@ -308,7 +313,7 @@ def serve_bench(args, ch, torch, workloads):
             res["graphs"] = srv.stats()["graphs"]
         res["saturated"] = {k: sat[k] for k in ("req_per_s", "p50_ms", "p99_ms", "wall_s",
                                                 "batches", "mean_batch", "admission_stalls",
-                                                "arena_peak_gib")}
+                                                "arena_max_gib")}
         out[name] = res
         print(f"[bench] serve {name}: p50 {res['p50_ms']:.2f} ms, p99 {res['p99_ms']:.2f} ms, "
               f"{res['req_per_s']:.0f} req/s, mean batch {res['mean_batch']:.2f}; saturated "
