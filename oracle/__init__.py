@@ -77,6 +77,7 @@ def lib():
     L.or_threads.restype = _INT
     L.or_philox4x64.argtypes = [_U64, _U64, _U64]
     L.or_grid_tables.argtypes = [ctypes.c_uint64, _INT, _INT, _F32, _U64]
+    L.or_grid_tables_rep.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _INT, _INT, _F32, _U64]
     L.or_embedding.argtypes = [ctypes.c_uint64, _INT, _INT, _F32]
     L.or_default_scales.argtypes = [_I64, _I64, ctypes.c_double]
     L.or_default_scales.restype = _INT
@@ -88,6 +89,8 @@ def lib():
                                _F32, _U64, _U64]
     L.or_crude_nn.argtypes = [_U64, _I64, _U64, _I64, _INT, _F32, _F32, _INT, _INT,
                               _I32, _I32, _F32]
+    L.or_crude_window.argtypes = [_U64, _I64, _U64, _I64, _INT, _INT, _F32, _F32, _INT, _INT,
+                                  _I32, _I32, _F32]
     L.or_dist32.argtypes = [_F32, _F32, _INT, _INT]
     L.or_dist32.restype = ctypes.c_float
     L.or_nn_f64.argtypes = [_F32, _I64, _VP, _F32, _I64, _INT, _INT, _F64, _I32]
@@ -120,13 +123,17 @@ def philox4x64(counter, key) -> np.ndarray:
     return out
 
 
-def grid_tables(seed: int, L: int, kh: int):
+def grid_tables(seed: int, L: int, kh: int, rep: int = 0):
     """Shifts z'[L, kh] in cell units (U[0,1) on a 2^-24 lattice) and odd
     64-bit key multipliers M[L, kh], one independent pair per scale
-    (appendix lemma on the grid hash at every scale)."""
+    (appendix lemma on the grid hash at every scale); rep numbers the
+    independent LSH structures of the repeated variant."""
     z = np.zeros((L, kh), np.float32)
     m = np.zeros((L, kh), np.uint64)
-    lib().or_grid_tables(seed, L, kh, z, m)
+    if rep == 0:
+        lib().or_grid_tables(seed, L, kh, z, m)
+    else:
+        lib().or_grid_tables_rep(seed, rep, L, kh, z, m)
     return z, m
 
 
@@ -179,10 +186,19 @@ def dist32(a, b, metric) -> np.float32:
     return np.float32(lib().or_dist32(a, b, a.shape[0], metric))
 
 
-def crude_nn(A, B, metric, eps, seed, n_scales=0, embed_dim=DEFAULT_EMBED_DIM):
+def crude_nn(A, B, metric, eps, seed, n_scales=0, embed_dim=DEFAULT_EMBED_DIM, window=1,
+             reps=1):
     """CrudeNN figure.  Returns a dict with the per-point first colliding
     scale (L when none), the candidate b (lowest index in the bucket) and
-    D_a = dist32(a, b), plus the intermediate keys and calibration."""
+    D_a = dist32(a, b), plus the intermediate keys and calibration.
+
+    window W > 1 or reps k > 1: the variant of the large-scale experiments.
+    Each of k independent LSH structures (grid stream rep = 0 .. k-1; the
+    l2 embedding is the same for all) retrieves the first W distinct points
+    of B from a's buckets, finest scale first; the candidate is the closest
+    of the k W retrieved points (dist32, ties to the lower b) and the scale
+    the finest first-collision scale over the structures.  The keys and
+    tables returned are those of structure 0."""
     A, B = _f32(A), _f32(B)
     n_a, d = A.shape
     n_b = B.shape[0]
@@ -190,15 +206,28 @@ def crude_nn(A, B, metric, eps, seed, n_scales=0, embed_dim=DEFAULT_EMBED_DIM):
     lo, hi, S, e_top = calibrate(A, B)
     Zs = embedding(seed, d, embed_dim) if metric == L2 else None
     kh = d if metric == L1 else embed_dim
-    zfrac, mult = grid_tables(seed, L, kh)
-    kA = hash_keys(A, metric, lo, Zs, L, e_top, zfrac, mult)
-    kB = hash_keys(B, metric, lo, Zs, L, e_top, zfrac, mult)
-    scale = np.zeros(n_a, np.int32)
-    nn = np.zeros(n_a, np.int32)
-    D = np.zeros(n_a, np.float32)
-    lib().or_crude_nn(kA, n_a, kB, n_b, L, A, B, d, metric, scale, nn, D)
-    return dict(scale=scale, nn=nn, D=D, keys_a=kA, keys_b=kB, lo=lo, hi=hi, S=S,
-                e_top=e_top, L=L, embed=Zs, zfrac=zfrac, mult=mult)
+    out = None
+    for r in range(reps):
+        zfrac, mult = grid_tables(seed, L, kh, r)
+        kA = hash_keys(A, metric, lo, Zs, L, e_top, zfrac, mult)
+        kB = hash_keys(B, metric, lo, Zs, L, e_top, zfrac, mult)
+        scale = np.zeros(n_a, np.int32)
+        nn = np.zeros(n_a, np.int32)
+        D = np.zeros(n_a, np.float32)
+        if window == 1:
+            lib().or_crude_nn(kA, n_a, kB, n_b, L, A, B, d, metric, scale, nn, D)
+        else:
+            lib().or_crude_window(kA, n_a, kB, n_b, L, window, A, B, d, metric, scale, nn, D)
+        if out is None:
+            out = dict(scale=scale, nn=nn, D=D, keys_a=kA, keys_b=kB, lo=lo, hi=hi, S=S,
+                       e_top=e_top, L=L, embed=Zs, zfrac=zfrac, mult=mult)
+            continue
+        # the closest retrieved point over all structures, ties to the lower b
+        better = (D < out["D"]) | ((D == out["D"]) & (nn < out["nn"]))
+        out["D"] = np.where(better, D, out["D"])
+        out["nn"] = np.where(better, nn, out["nn"])
+        out["scale"] = np.minimum(out["scale"], scale)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -261,7 +290,7 @@ def sample(seed, P, W, T):
 
 
 def chamfer_estimate(A, B, metric, eps, T, seed, n_scales=0,
-                     embed_dim=DEFAULT_EMBED_DIM, crude=None):
+                     embed_dim=DEFAULT_EMBED_DIM, crude=None, window=1, reps=1):
     """Chamfer-Estimate figure with the fixed-point distribution above.
 
     eta = (1/T) sum_l (W / w_{x_l}) * min_b d(x_l, b), the per-sample minima in
@@ -275,7 +304,7 @@ def chamfer_estimate(A, B, metric, eps, T, seed, n_scales=0,
         return dict(eta=0.0, T=T, idx=np.zeros(0, np.int32), m=np.zeros(0), W=0, s=0,
                     D_norm=0.0, crude=None)
     if crude is None:
-        crude = crude_nn(A, B, metric, eps, seed, n_scales, embed_dim)
+        crude = crude_nn(A, B, metric, eps, seed, n_scales, embed_dim, window, reps)
     s, w, P, W, zero = weights(crude["D"])
     if zero:
         return dict(eta=0.0, T=T, idx=np.zeros(T, np.int32), m=np.zeros(T), W=0, s=0,

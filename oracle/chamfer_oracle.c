@@ -74,6 +74,14 @@ void or_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+static void draw_rep(uint64_t seed, uint64_t c0, uint64_t c1, uint32_t purpose, uint64_t rep,
+                     uint64_t out[4])
+{
+    uint64_t ctr[4] = {c0, c1, (uint64_t)purpose, rep};
+    uint64_t key[2] = {seed, 0};
+    or_philox4x64(ctr, key, out);
+}
+
 static void draw(uint64_t seed, uint64_t c0, uint64_t c1, uint32_t purpose, uint64_t out[4])
 {
     uint64_t ctr[4] = {c0, c1, (uint64_t)purpose, 0};
@@ -88,8 +96,21 @@ static void draw(uint64_t seed, uint64_t c0, uint64_t c1, uint32_t purpose, uint
 /* For scale i and hashed coordinate k the oracle draws                    */
 /*   z'_ik = (word0 >> 40) * 2^-24            (24-bit lattice in [0, 1))     */
 /*   M_ik  = word1 | 1                         (odd 64-bit multiplier)       */
-/* from the counter (k, i, GRID).  zfrac and mult are [L][kh].              */
+/* from the counter (k, i, GRID, rep): rep numbers the independent LSH      */
+/* structures of the repeated variant (0 for the single structure).         */
+/* zfrac and mult are [L][kh].                                               */
 /* ------------------------------------------------------------------------ */
+void or_grid_tables_rep(uint64_t seed, uint64_t rep, int L, int kh, float *zfrac, uint64_t *mult)
+{
+    for (int i = 0; i < L; ++i)
+        for (int k = 0; k < kh; ++k) {
+            uint64_t w[4];
+            draw_rep(seed, (uint64_t)k, (uint64_t)i, PURPOSE_GRID, rep, w);
+            zfrac[(size_t)i * kh + k] = ldexpf((float)(w[0] >> 40), -24);
+            mult[(size_t)i * kh + k] = w[1] | 1ull;
+        }
+}
+
 void or_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult)
 {
     for (int i = 0; i < L; ++i)
@@ -311,6 +332,65 @@ void or_crude_nn(const uint64_t *keysA, int64_t nA, const uint64_t *keysB, int64
         if (scale_out[a] < 0) { scale_out[a] = L; nn_out[a] = 0; }
         D_out[a] = or_dist32(A + (size_t)a * d, B + (size_t)nn_out[a] * d, d, metric);
     }
+    free(tab);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Window form of the crude join (the large-scale variant of the            */
+/* experiments, with window W): walk a's buckets finest scale first and     */
+/* retrieve the first W distinct points of B, taking a bucket's points in   */
+/* increasing index order; the candidate is the retrieved b with the        */
+/* smallest dist32 (ties to the lower b) and D_a that distance.  If no      */
+/* scale collides, the window is b = 0 .. min(W, n_B) - 1 and the scale is  */
+/* reported as L; otherwise the scale is the first one that collides.       */
+/* ------------------------------------------------------------------------ */
+void or_crude_window(const uint64_t *keysA, int64_t nA, const uint64_t *keysB, int64_t nB,
+                     int L, int W, const float *A, const float *B, int d, int metric,
+                     int32_t *scale_out, int32_t *nn_out, float *D_out)
+{
+    kv_t *tab = (kv_t *)malloc(sizeof(kv_t) * (size_t)(nB > 0 ? nB : 1));
+    int64_t *got = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nA > 0 ? nA : 1) * (size_t)W);
+    int *ngot = (int *)calloc((size_t)(nA > 0 ? nA : 1), sizeof(int));
+    for (int64_t a = 0; a < nA; ++a) scale_out[a] = L;
+    for (int i = 0; i < L; ++i) {
+        for (int64_t b = 0; b < nB; ++b) { tab[b].key = keysB[(size_t)i * nB + b]; tab[b].idx = b; }
+        qsort(tab, (size_t)nB, sizeof(kv_t), kv_cmp);
+#pragma omp parallel for schedule(static)
+        for (int64_t a = 0; a < nA; ++a) {
+            if (ngot[a] >= W) continue;
+            uint64_t k = keysA[(size_t)i * nA + a];
+            int64_t lo = 0, hi = nB; /* first entry with key >= k */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (tab[mid].key < k) lo = mid + 1; else hi = mid;
+            }
+            int64_t *mine = got + (size_t)a * W;
+            for (int64_t e = lo; e < nB && tab[e].key == k && ngot[a] < W; ++e) {
+                int seen = 0;
+                for (int j = 0; j < ngot[a]; ++j) seen |= mine[j] == tab[e].idx;
+                if (!seen) {
+                    if (ngot[a] == 0) scale_out[a] = i;
+                    mine[ngot[a]++] = tab[e].idx;
+                }
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < nA; ++a) {
+        int64_t *mine = got + (size_t)a * W;
+        if (ngot[a] == 0)
+            for (int64_t b = 0; b < W && b < nB; ++b) mine[ngot[a]++] = b;
+        float best = 0.0f;
+        int64_t arg = -1;
+        for (int j = 0; j < ngot[a]; ++j) {
+            float v = or_dist32(A + (size_t)a * d, B + (size_t)mine[j] * d, d, metric);
+            if (arg < 0 || v < best || (v == best && mine[j] < arg)) { best = v; arg = mine[j]; }
+        }
+        nn_out[a] = (int32_t)arg;
+        D_out[a] = best;
+    }
+    free(ngot);
+    free(got);
     free(tab);
 }
 

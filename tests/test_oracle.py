@@ -282,6 +282,110 @@ def test_crude_nn_single_b_and_self(orc):
         assert np.all(r["D"] == 0.0)
 
 
+def test_grid_stream_repetitions(orc):
+    """The shifts and multipliers of LSH structure r come from the counter
+    (k, i, GRID, r): checked against numpy's Philox; r = 0 is the single
+    structure of the base algorithm, other r are independent."""
+    seed, L, kh = 77, 6, 5
+    base = orc.grid_tables(seed, L, kh)
+    for r in (0, 1, 5):
+        z, m = orc.grid_tables(seed, L, kh, r)
+        for i in range(L):
+            for k in range(kh):
+                # numpy adds one to the 256-bit counter before each block
+                ctr = [k, i, 1, r]
+                for j in range(4):
+                    if ctr[j]:
+                        ctr[j] -= 1
+                        break
+                    ctr[j] = 2**64 - 1
+                bg = np.random.Philox(key=np.array([seed, 0], np.uint64),
+                                      counter=np.array(ctr, np.uint64))
+                w = bg.random_raw(4)
+                assert z[i, k] == np.float32(math.ldexp(int(w[0]) >> 40, -24))
+                assert m[i, k] == (int(w[1]) | 1)
+        if r == 0:
+            assert np.array_equal(z, base[0]) and np.array_equal(m, base[1])
+        else:
+            assert not np.array_equal(z, base[0])
+
+
+def _window_brute_force(orc, A, B, metric, seed, L, W, reps):
+    """The k x W retrieval written out with Python dicts over each
+    structure's keys: first W distinct b finest scale first, ascending b
+    within a bucket; the closest retrieved b (ties to the lower b)."""
+    lo, hi, S, e_top = orc.calibrate(A, B)
+    Zs = orc.embedding(seed, A.shape[1]) if metric == 2 else None
+    kh = A.shape[1] if metric == 1 else Zs.shape[0]
+    best = [None] * A.shape[0]
+    first = [L] * A.shape[0]
+    for r in range(reps):
+        z, m = orc.grid_tables(seed, L, kh, r)
+        kA = orc.hash_keys(A, metric, lo, Zs, L, e_top, z, m)
+        kB = orc.hash_keys(B, metric, lo, Zs, L, e_top, z, m)
+        buckets = []
+        for i in range(L):
+            d = {}
+            for b in range(B.shape[0]):
+                d.setdefault(int(kB[i, b]), []).append(b)
+            buckets.append(d)
+        for a in range(A.shape[0]):
+            got = []
+            for i in range(L):
+                for b in buckets[i].get(int(kA[i, a]), []):
+                    if len(got) < W and b not in got:
+                        if not got:
+                            first[a] = min(first[a], i)
+                        got.append(b)
+            if not got:
+                got = list(range(min(W, B.shape[0])))
+            for b in got:
+                cand = (float(orc.dist32(A[a], B[b], metric)), b)
+                if best[a] is None or cand < best[a]:
+                    best[a] = cand
+    return best, first
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("W,reps", [(1, 1), (3, 1), (1, 3), (5, 2)])
+def test_crude_window_brute_force(orc, metric, W, reps):
+    """Large-scale variant of the experiments (k LSH structures, window W)
+    against the dictionary form above, on inputs small enough to have many
+    multi-point buckets and some points with no collision."""
+    rng = np.random.default_rng(40 + metric + 3 * W + reps)
+    A = rng.uniform(-4, 4, size=(60, 4)).astype(np.float32)
+    B = rng.uniform(-4, 4, size=(45, 4)).astype(np.float32)
+    L = 9
+    r = orc.crude_nn(A, B, metric, 0.3, seed=31, n_scales=L, window=W, reps=reps)
+    best, first = _window_brute_force(orc, A, B, metric, 31, L, W, reps)
+    for a in range(A.shape[0]):
+        assert (float(r["D"][a]), int(r["nn"][a])) == best[a], a
+        assert r["scale"][a] == first[a]
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_crude_window_monotone(orc, metric):
+    """Retrieval sets grow with W (same order) and with k (more structures),
+    so D_a can only decrease, and stays >= the exact nearest-neighbour
+    distance (oversampling lemma)."""
+    A, B = workloads.clusters_l2(seed=14, n=500, d=8, k=12)
+    m32, _ = orc.nn_f32(A, B, metric)
+    prev = None
+    for W in (1, 2, 4, 8):
+        r = orc.crude_nn(A, B, metric, 0.2, seed=3, window=W)
+        assert np.all(r["D"] >= m32)
+        if prev is not None:
+            assert np.all(r["D"] <= prev)
+        prev = r["D"]
+    prev = None
+    for k in (1, 2, 4):
+        r = orc.crude_nn(A, B, metric, 0.2, seed=3, window=2, reps=k)
+        assert np.all(r["D"] >= m32)
+        if prev is not None:
+            assert np.all(r["D"] <= prev)
+        prev = r["D"]
+
+
 def test_grid_levels_vs_quality(orc):
     """More grid levels cannot make D_a worse on average here (experiments
     section: a few levels already give D_a within ~2x)."""
