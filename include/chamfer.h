@@ -61,6 +61,9 @@ typedef struct chamfer_opts {
     int32_t n_scales;   /* L grid scales; 0 => ceil(log2(max(n_A,n_B)/eps))   */
     int32_t embed_dim;  /* l2 only: embedding dimension k_e; 0 => 32          */
     int32_t precision;  /* enum chamfer_precision; 0 => CHAMFER_FP32          */
+    int32_t window;     /* W points retrieved per point of A by CrudeNN, 1..32;
+                           0 => 1 (the first colliding point)                  */
+    int32_t reps;       /* k independent LSH structures, 1..64; 0 => 1       */
     int32_t reserved;   /* must be 0                                          */
 } chamfer_opts;
 
@@ -202,7 +205,8 @@ int chamfer_nn_min(const float *X, const int32_t *rows, int64_t n_x, const float
  * requests (members of one batch share admit_s).  A request's host arrays A,
  * B (row-major float32; pinned memory makes the copy-in asynchronous) must
  * stay valid until its result is drained.  Results are bit-identical to a
- * direct chamfer_estimate call with the same arguments.  Requires d <= 2048.
+ * direct chamfer_estimate call with the same arguments.  Requires d <= 2048
+ * and the single-structure CrudeNN (opts.window and opts.reps 0 or 1).
  * A server is not thread-safe: call it from one host thread.
  * Errors: EINVAL for bad arguments (as chamfer_estimate, or d > 2048),
  * EWORKSPACE if a request can never fit the arena, EHIP for runtime

@@ -37,7 +37,8 @@ class ChamferError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("n_scales", ctypes.c_int32), ("embed_dim", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("reps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _AUX_ARRAYS = ("sample_idx", "sample_min", "sample_nn", "D", "W", "s", "status",
@@ -102,8 +103,8 @@ def _check(rc: int, where: str):
         raise ChamferError(rc, where)
 
 
-def _opts(n_scales=0, embed_dim=0, precision=0) -> Opts:
-    return Opts(n_scales, embed_dim, precision, 0)
+def _opts(n_scales=0, embed_dim=0, precision=0, window=0, reps=0) -> Opts:
+    return Opts(n_scales, embed_dim, precision, window, reps, 0)
 
 
 # ----------------------------------------------------------- torch glue ---
@@ -153,8 +154,8 @@ def release_workspaces():
 # ------------------------------------------------------------- host API ---
 
 def chamfer_workspace_bytes(n_a, n_b, d, metric, eps=0.5, T=0, n_scales=0, embed_dim=0,
-                            precision=0) -> int:
-    o = _opts(n_scales, embed_dim, precision)
+                            precision=0, window=0, reps=0) -> int:
+    o = _opts(n_scales, embed_dim, precision, window, reps)
     return int(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o)))
 
 
@@ -225,13 +226,13 @@ def chamfer_nn_min(X, B, metric=L2, rows=None, *, precision=0):
     return mn, arg
 
 
-def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):
+def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0, window=0, reps=0):
     """CrudeNN: D_a (float32), candidate b, first colliding scale."""
     torch = _torch()
     A, B = _points(A, "A"), _points(B, "B")
     n_a, d = A.shape
     dev = A.device
-    o = _opts(n_scales, embed_dim)
+    o = _opts(n_scales, embed_dim, window=window, reps=reps)
     nbytes = lib().chamfer_workspace_bytes(n_a, B.shape[0], d, metric, eps, 0, ctypes.byref(o))
     if nbytes == 0:
         raise ChamferError(-1, "crude_nn")
@@ -246,6 +247,7 @@ def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):
 
 
 def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0, precision=0,
+                     window=0, reps=0,
                      with_aux=True, stage_events=None):
     """(1 +- eps) estimate of CH(A, B).  Returns a dict of device tensors:
     eta [1] double, and with_aux: sample_idx/min/nn [T], D, W, s, status,
@@ -256,7 +258,7 @@ def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
     n_a, d = A.shape
     n_b = B.shape[0]
     dev = A.device
-    o = _opts(n_scales, embed_dim, precision)
+    o = _opts(n_scales, embed_dim, precision, window, reps)
     if T == 0 and 0.0 < eps < 1.0:
         T = chamfer_default_samples(max(n_a, 1), eps)
     nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o))

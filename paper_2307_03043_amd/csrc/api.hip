@@ -102,6 +102,8 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     chamfer_opts o{};
     if (opts) o = *opts;
     if (o.n_scales < 0 || o.n_scales > kMaxScales || o.reserved != 0) return CHAMFER_EINVAL;
+    if (o.window < 0 || o.window > kMaxWindow || o.reps < 0 || o.reps > kMaxReps)
+        return CHAMFER_EINVAL;
     if (o.precision < CHAMFER_FP32 || o.precision > CHAMFER_FP8) return CHAMFER_EINVAL;
     const int ke = o.embed_dim ? o.embed_dim : 32;
     if (!valid_ke(ke)) return CHAMFER_EINVAL;
@@ -111,6 +113,8 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.d = d;
     pl.metric = metric;
     pl.precision = o.precision;
+    pl.window = o.window ? o.window : 1;
+    pl.reps = o.reps ? o.reps : 1;
     pl.L = o.n_scales ? o.n_scales : default_scales(nA, nB, e);
     pl.ke = ke;
     pl.kh = metric == CHAMFER_L1 ? d : ke;
@@ -133,7 +137,7 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_zfrac = take(h * pl.L * pl.kh * sizeof(float));
     pl.off_mult = take(h * pl.L * pl.kh * sizeof(uint64_t));
     pl.off_embed = take(metric == CHAMFER_L2 ? h * d * ke * sizeof(float) : 0);
-    pl.off_tables = take(h * pl.L * ((size_t)1 << lc) * sizeof(Bucket));
+    pl.off_tables = take(h * table_bytes(pl.L, lc, pl.window));
     pl.off_D = take(h * nA * sizeof(float));
     pl.off_nn = take(h * nA * sizeof(int32_t));
     pl.off_scale = take(h * nA * sizeof(int32_t));
@@ -187,7 +191,7 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
                               hipMemcpyHostToDevice, st));
     }
     CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, at<float>(ws, pl.off_zfrac),
-                              at<uint64_t>(ws, pl.off_mult), st));
+                              at<uint64_t>(ws, pl.off_mult), 0, st));
     CH_TRY(launch_minmax(A, pl.nA, pl.d, lohi, p, st));
     CH_TRY(launch_minmax(B, pl.nB, pl.d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, pl.d, p, st));
@@ -201,7 +205,10 @@ hipError_t mark(void **ev, int i, hipStream_t st) {
 }
 
 // CrudeNN into D/nn/scale.  nb2 (l2 only, may be null): |b|^2 per row of B,
-// computed while B is bucketed, for the nearest-neighbour pass.
+// computed while B is bucketed, for the nearest-neighbour pass.  With k LSH
+// structures (reps) the tables are rebuilt for each structure r (grid stream
+// word r) and each probe keeps the better of its candidate and the stored
+// one; with a window W the tables hold W points per bucket.
 int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
                int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,
                float *nb2 = nullptr) {
@@ -210,17 +217,24 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
     if (rc) return rc;
     DevParams *p = at<DevParams>(ws, pl.off_params);
     Bucket *tables = at<Bucket>(ws, pl.off_tables);
-    CH_TRY(launch_table_fill(tables, (size_t)pl.L << pl.log2cap, st));
-    CH_TRY(mark(ev, 1, st));
     const uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
     const float *emb = at<float>(ws, pl.off_embed);
-    const float *zf = at<float>(ws, pl.off_zfrac);
-    const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
-    CH_TRY(launch_hash(0, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
-                       tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr, nb2, p, st));
-    CH_TRY(mark(ev, 2, st));
-    CH_TRY(launch_hash(1, A, pl.nA, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf, mt,
-                       tables, pl.log2cap, nullptr, D, nn, scale, nullptr, p, st));
+    float *zf = at<float>(ws, pl.off_zfrac);
+    uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
+    const int W = pl.window;
+    for (int r = 0; r < pl.reps; ++r) {
+        if (r > 0) CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, zf, mt, r, st));
+        CH_TRY(launch_tables_empty(tables, pl.L, pl.log2cap, W, st));
+        if (r == 0) CH_TRY(mark(ev, 1, st));
+        CH_TRY(launch_hash(W == 1 ? 0 : 3, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi,
+                           emb, zf, mt, tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr,
+                           r == 0 ? nb2 : nullptr, p, W, 0, st));
+        if (r == 0) CH_TRY(mark(ev, 2, st));
+        const int flags = (r > 0 ? kProbeMerge : 0) | (r == pl.reps - 1 ? kProbeLast : 0);
+        CH_TRY(launch_hash(W == 1 ? 1 : 4, A, pl.nA, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi,
+                           emb, zf, mt, tables, pl.log2cap, nullptr, D, nn, scale, nullptr, p, W,
+                           flags, st));
+    }
     CH_TRY(mark(ev, 3, st));
     return CHAMFER_OK;
 }
@@ -268,6 +282,7 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
     if (rc) return rc;
     if (nA < 1 || d > 2048 || A == nullptr || B == nullptr || eta == nullptr || job == nullptr)
         return CHAMFER_EINVAL;
+    if (pl.window != 1 || pl.reps != 1) return CHAMFER_EINVAL;  // single structure, W = 1
     if (metric == CHAMFER_L2 && (embed_dev == nullptr || embed_host == nullptr))
         return CHAMFER_EINVAL;
     if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
@@ -532,10 +547,12 @@ int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, 
     const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
     if (keys_A_out)
         CH_TRY(launch_hash(2, A, n_A, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
-                           pl.log2cap, keys_A_out, nullptr, nullptr, nullptr, nullptr, p, st));
+                           pl.log2cap, keys_A_out, nullptr, nullptr, nullptr, nullptr, p, 1, 0,
+                           st));
     if (keys_B_out)
         CH_TRY(launch_hash(2, B, n_B, B, n_B, d, metric, pl.L, pl.ke, lohi, emb, zf, mt, nullptr,
-                           pl.log2cap, keys_B_out, nullptr, nullptr, nullptr, nullptr, p, st));
+                           pl.log2cap, keys_B_out, nullptr, nullptr, nullptr, nullptr, p, 1, 0,
+                           st));
     if (e_top_out) {
         // e_top lives in the device parameter block.
         CH_TRY(hipMemcpyAsync(e_top_out, &p->e_top, sizeof(int32_t), hipMemcpyDeviceToDevice,

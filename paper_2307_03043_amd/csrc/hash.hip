@@ -54,25 +54,27 @@ hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t s
 // Shifts z'_ik (cell units, 24-bit lattice in [0,1)) and odd multipliers
 // M_ik from Philox4x64-10, counter (k, i, GRID, 0), key (seed, 0).
 __device__ __forceinline__ void grid_tables(uint64_t seed, int L, int kh, float *zfrac,
-                                            uint64_t *mult, Blk b) {
+                                            uint64_t *mult, int rep, Blk b) {
     const int t = (int)(b.id * blockDim.x + threadIdx.x);
     if (t >= L * kh) return;
     const int i = t / kh, k = t - i * kh;
-    uint64_t c[4] = {(uint64_t)k, (uint64_t)i, (uint64_t)kPurposeGrid, 0};
+    uint64_t c[4] = {(uint64_t)k, (uint64_t)i, (uint64_t)kPurposeGrid, (uint64_t)rep};
     philox4x64_10(c, seed, 0);
     zfrac[t] = ldexpf((float)(uint32_t)(c[0] >> 40), -24);
     mult[t] = c[1] | 1ull;
 }
 
-__global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult) {
-    grid_tables(seed, L, kh, zfrac, mult, grid_blk());
+__global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
+                              int rep) {
+    grid_tables(seed, L, kh, zfrac, mult, rep, grid_blk());
 }
 
 int64_t grid_table_blocks(int L, int kh) { return ((int64_t)L * kh + 255) / 256; }
 
 hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
-                              hipStream_t st) {
-    k_grid_tables<<<(unsigned)grid_table_blocks(L, kh), 256, 0, st>>>(seed, L, kh, zfrac, mult);
+                              int rep, hipStream_t st) {
+    k_grid_tables<<<(unsigned)grid_table_blocks(L, kh), 256, 0, st>>>(seed, L, kh, zfrac, mult,
+                                                                      rep);
     return hipGetLastError();
 }
 
@@ -382,6 +384,54 @@ __device__ __forceinline__ int table_probe(const CH_RO Bucket *tab, int log2cap,
     }
 }
 
+// Window tables (multi-probe CrudeNN): a bucket holds its key and the W
+// smallest b inserted under it, ascending, INT_MAX for empty positions.
+// W smallest suffice: a probe that has seen s < W points at finer scales
+// needs W - s unseen points of the bucket, and at most s of its W smallest
+// are seen, so the W - s smallest unseen ones are among them.
+// The insert runs b through the W positions as a chain of atomicMin: each
+// position keeps the smaller of its value and the incoming one and passes
+// the larger on, so position j ends with the (j+1)-th smallest b inserted,
+// whatever the interleaving.  A position already below b is skipped (values
+// only decrease), and an empty position ends the chain.
+__device__ void wide_insert(unsigned long long *keys, int *mem, int log2cap,
+                            unsigned long long key, int b, int W) {
+    const uint64_t mask = (1ull << log2cap) - 1;
+    uint64_t slot = home_slot(key, log2cap);
+    for (;;) {
+        unsigned long long cur =
+            __hip_atomic_load(&keys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kEmptyKey) {
+            const unsigned long long prev = atomicCAS(&keys[slot], kEmptyKey, key);
+            if (prev == kEmptyKey || prev == key) break;
+            cur = prev;
+        }
+        if (cur == key) break;
+        slot = (slot + 1) & mask;
+    }
+    int *m = mem + slot * (uint64_t)W;
+    int x = b;
+    for (int j = 0; j < W; ++j) {
+        if (__hip_atomic_load(&m[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < x) continue;
+        const int old = atomicMin(&m[j], x);
+        if (old == INT_MAX) return;  // x took an empty position
+        x = max(old, x);             // the larger one moves on
+    }
+}
+
+// Bucket index of key in a window table, or -1.
+__device__ __forceinline__ int64_t wide_find(const CH_RO unsigned long long *keys, int log2cap,
+                                             unsigned long long key) {
+    const uint64_t mask = (1ull << log2cap) - 1;
+    uint64_t slot = home_slot(key, log2cap);
+    for (;;) {
+        const unsigned long long k = keys[slot];
+        if (k == key) return (int64_t)slot;
+        if (k == kEmptyKey) return -1;
+        slot = (slot + 1) & mask;
+    }
+}
+
 // Canonical float32 distance (square root of the accumulator for l2).
 template <int METRIC>
 __device__ __forceinline__ float dist32(const float *__restrict__ a, const float *__restrict__ b,
@@ -398,6 +448,13 @@ constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
 // MODE 0: insert the tile's points (B) into the L tables.
 // MODE 1: probe (A): first scale with a hit, candidate, D_a; max D_a.
 // MODE 2: write keys[L][n].
+// MODE 3: insert into window tables (W smallest b per bucket).
+// MODE 4: probe window tables: the first W distinct b over the scales, finest
+//         first (wavefront 0 walks the scales of its lane's point; the
+//         retrieved b are kept in LDS), candidate = the closest of them.
+// With kProbeMerge a probe keeps the better of its candidate and the one
+// already stored for the point (an earlier LSH structure), by (D_a, b); the
+// max of D_a is reduced only with kProbeLast.
 // KE: embedding dimension for l2 (0 for l1).  YG: l1 coordinates from HBM.
 // Lane p of every wavefront works on point p of the tile; wavefront w takes
 // scales w, w + 4, w + 8, ...  For the probe each wavefront stops at its own
@@ -409,7 +466,7 @@ __device__ __forceinline__ void hash_tile(
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, float *nb2_out, DevParams *p, Blk blk) {
+    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags, Blk blk) {
     extern __shared__ float smem[];
     __shared__ float los[kEmbedChunk];
     __shared__ int hit_scale[kTile];
@@ -425,7 +482,7 @@ __device__ __forceinline__ void hash_tile(
     const bool active = lane < np;
 
     if (p->status != CHAMFER_OK) {
-        if (MODE == 1 && wave == 0 && active) {
+        if ((MODE == 1 || MODE == 4) && wave == 0 && active) {
             D_out[pt] = __builtin_nanf("");
             nn_out[pt] = -1;
             if (scale_out) scale_out[pt] = -1;
@@ -455,7 +512,7 @@ __device__ __forceinline__ void hash_tile(
 #pragma unroll
         for (int j = 0; j < JW; ++j) y[j] = 0.0f;
         float n2 = 0.0f;
-        const bool want_n2 = MODE == 0 && nb2_out != nullptr && wave == 0;
+        const bool want_n2 = (MODE == 0 || MODE == 3) && nb2_out != nullptr && wave == 0;
         for (int k0 = 0; k0 < d; k0 += kEmbedChunk) {
             const int kc = min(kEmbedChunk, d - k0);
             __syncthreads();
@@ -530,6 +587,96 @@ __device__ __forceinline__ void hash_tile(
             for (int i = wave; i < L; i += kWaves) keys_out[(size_t)i * n + pt] = key_at(i);
         return;
     }
+    // keep the better of (D, c, s) and the stored result of an earlier
+    // structure; then store, and reduce max D on the last structure
+    auto finish = [&](float D, int c, int s) {
+        if (active) {
+            if (flags & kProbeMerge) {
+                const float Dp = D_out[pt];
+                const int cp = nn_out[pt];
+                if (Dp < D || (Dp == D && cp < c)) {
+                    D = Dp;
+                    c = cp;
+                }
+                if (scale_out) s = min(s, scale_out[pt]);
+            }
+            D_out[pt] = D;
+            nn_out[pt] = c;
+            if (scale_out) scale_out[pt] = s;
+        }
+        if (flags & kProbeLast) {
+            // wavefront max of D (D >= 0, so its bits order as floats)
+            uint32_t m = active ? __float_as_uint(D) : 0u;
+            for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+            if (lane == 0) atomicMax(&p->max_d_bits, m);
+        }
+    };
+    if (MODE == 3) {
+        unsigned long long *wkeys = reinterpret_cast<unsigned long long *>(tables);
+        int *wmem = reinterpret_cast<int *>(wkeys + ((size_t)L << log2cap));
+        // lanes sharing a key: only the W lowest (smallest b) can be among
+        // the bucket's W smallest; the rest skip, as in MODE 0
+        constexpr int kLeaders = 4;
+        for (int i = wave; i < L; i += kWaves) {
+            const unsigned long long key = active ? key_at(i) : kEmptyKey;
+            unsigned long long rest = __ballot(active);
+            bool mine = false;
+            for (int it = 0; it < kLeaders && rest != 0; ++it) {
+                const int leader = __ffsll((long long)rest) - 1;
+                const unsigned long long lk = __shfl(key, leader);
+                const unsigned long long same = __ballot(active && key == lk);
+                if ((same >> lane) & 1ull) mine = __popcll(same & ((1ull << lane) - 1)) < W;
+                rest &= ~same;
+            }
+            mine |= ((rest >> lane) & 1ull) != 0;
+            if (mine)
+                wide_insert(wkeys + ((size_t)i << log2cap), wmem + ((size_t)i << log2cap) * W,
+                            log2cap, key, (int)pt, W);
+        }
+        return;
+    }
+    if (MODE == 4) {
+        if (wave != 0) return;  // no barrier follows
+        const auto *wk = reinterpret_cast<const unsigned long long *>(tables);
+        const auto *wkeys = ro(wk);
+        const auto *wmem = ro(reinterpret_cast<const int *>(wk + ((size_t)L << log2cap)));
+        const int lds_floats = METRIC == CHAMFER_L1 ? (YG ? 0 : kTile * khp)
+                                                    : kTile * (khp + kEmbedChunk + 1);
+        int *got = reinterpret_cast<int *>(smem + lds_floats) + lane * W;
+        int ng = 0, first = L;
+        float D = 0.0f;
+        int c = 0;
+        if (active) {
+            for (int i = 0; i < L && ng < W; ++i) {
+                const int64_t s = wide_find(wkeys + ((size_t)i << log2cap), log2cap, key_at(i));
+                if (s < 0) continue;
+                const auto *m = wmem + (((size_t)i << log2cap) + (size_t)s) * W;
+                for (int j = 0; j < W && ng < W; ++j) {
+                    const int b = m[j];
+                    if (b == INT_MAX) break;
+                    bool seen = false;
+                    for (int t = 0; t < ng; ++t) seen |= got[t] == b;
+                    if (!seen) {
+                        if (ng == 0) first = i;
+                        got[ng++] = b;
+                    }
+                }
+            }
+            if (ng == 0)  // no collision at any scale: the window is b = 0 .. W - 1
+                for (int b = 0; b < W && b < nB; ++b) got[ng++] = b;
+            c = -1;
+            for (int t = 0; t < ng; ++t) {
+                const int b = got[t];
+                const float v = dist32<METRIC>(xrow, Bpts + (size_t)b * d, d);
+                if (c < 0 || v < D || (v == D && b < c)) {
+                    D = v;
+                    c = b;
+                }
+            }
+        }
+        finish(D, c, first);
+        return;
+    }
     // MODE 1: probe.
     int found = L, cand = 0;
     if (active) {
@@ -552,8 +699,8 @@ __device__ __forceinline__ void hash_tile(
     __syncthreads();
     if (wave != 0) return;
     float D = 0.0f;
+    int best_s = L, best_c = 0;
     if (active) {
-        int best_s = L, best_c = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w)
             if (wave_scale[w][lane] < best_s) {
@@ -561,14 +708,8 @@ __device__ __forceinline__ void hash_tile(
                 best_c = hit_cand[w][lane];
             }
         D = dist32<METRIC>(xrow, Bpts + (size_t)best_c * d, d);
-        D_out[pt] = D;
-        nn_out[pt] = best_c;
-        if (scale_out) scale_out[pt] = best_s;
     }
-    // wavefront max of D (D >= 0, so its bits order as floats)
-    uint32_t m = __float_as_uint(D);
-    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if (lane == 0) atomicMax(&p->max_d_bits, m);
+    finish(D, best_c, best_s);
 }
 
 template <int METRIC, int MODE, int KE, bool YG>
@@ -577,9 +718,10 @@ __global__ __launch_bounds__(kThreads) void k_hash(
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, float *nb2_out, DevParams *p) {
+    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags) {
     hash_tile<METRIC, MODE, KE, YG>(X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap,
-                                    keys_out, D_out, nn_out, scale_out, nb2_out, p, grid_blk());
+                                    keys_out, D_out, nn_out, scale_out, nb2_out, p, nB, W, flags,
+                                    grid_blk());
 }
 
 int64_t hash_blocks(int64_t n) { return (n + kTile - 1) / kTile; }
@@ -592,28 +734,43 @@ static size_t hash_lds(int d) {
 }
 
 template <int METRIC, int KE, bool YG>
-static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts, int d,
-                                int L, const uint32_t *lohi, const float *embed_t,
-                                const float *zfrac, const uint64_t *mult, Bucket *tables,
-                                int log2cap, uint64_t *keys_out, float *D_out, int32_t *nn_out,
-                                int32_t *scale_out, float *nb2_out, DevParams *p,
-                                hipStream_t st) {
-    const size_t lds = hash_lds<METRIC, KE, YG>(d);
+static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts,
+                                int64_t nB, int d, int L, const uint32_t *lohi,
+                                const float *embed_t, const float *zfrac, const uint64_t *mult,
+                                Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
+                                int32_t *nn_out, int32_t *scale_out, float *nb2_out,
+                                DevParams *p, int W, int flags, hipStream_t st) {
+    size_t lds = hash_lds<METRIC, KE, YG>(d);
+    if (mode == 4) lds += (size_t)kTile * W * sizeof(int);  // retrieved b per lane
     const unsigned blocks = (unsigned)hash_blocks(n);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
-    if (mode == 0)
-        k_hash<METRIC, 0, KE, YG><<<blocks, kThreads, lds, st>>>(
-            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
-            scale_out, nb2_out, p);
-    else if (mode == 1)
-        k_hash<METRIC, 1, KE, YG><<<blocks, kThreads, lds, st>>>(
-            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
-            scale_out, nb2_out, p);
-    else
-        k_hash<METRIC, 2, KE, YG><<<blocks, kThreads, lds, st>>>(
-            X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out,
-            scale_out, nb2_out, p);
+#define CH_KARGS X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out, \
+                 scale_out, nb2_out, p, nB, W, flags
+    switch (mode) {
+        case 0: k_hash<METRIC, 0, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 1: k_hash<METRIC, 1, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 2: k_hash<METRIC, 2, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 3: k_hash<METRIC, 3, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 4: k_hash<METRIC, 4, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef CH_KARGS
     return hipGetLastError();
+}
+
+size_t table_bytes(int L, int log2cap, int W) {
+    const size_t buckets = (size_t)L << log2cap;
+    return W <= 1 ? buckets * sizeof(Bucket) : buckets * (sizeof(uint64_t) + (size_t)W * 4);
+}
+
+hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStream_t st) {
+    const size_t buckets = (size_t)L << log2cap;
+    if (W <= 1) return launch_table_fill(tables, buckets, st);
+    auto *keys = reinterpret_cast<unsigned long long *>(tables);
+    hipError_t e = launch_fill_u64(keys, (int64_t)buckets, ~0ull, st);
+    if (e != hipSuccess) return e;
+    // members: INT_MAX in both halves of each 64-bit word (W * buckets is even)
+    return launch_fill_u64(keys + buckets, (int64_t)(buckets * W / 2), 0x7fffffff7fffffffull, st);
 }
 
 // kMaxLdsL1Dim: largest l1 dimension whose tile (64 x (d|1) floats) plus the
@@ -624,13 +781,15 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
                        const float *embed_t, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
-                       hipStream_t st) {
-    (void)nB;
+                       int W, int flags, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-#define CH_ARGS mode, X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, keys_out, \
-                D_out, nn_out, scale_out, nb2_out, p, st
+    if (W < 1 || W > kMaxWindow) return hipErrorInvalidValue;
+#define CH_ARGS mode, X, n, Bpts, nB, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, keys_out, \
+                D_out, nn_out, scale_out, nb2_out, p, W, flags, st
     if (metric == CHAMFER_L1) {
-        if (d <= kMaxLdsL1Dim) return launch_hash_t<CHAMFER_L1, 0, false>(CH_ARGS);
+        // the window probe also keeps W ints per lane in LDS
+        const int room = mode == 4 ? kMaxLdsL1Dim - W : kMaxLdsL1Dim;
+        if (d <= room) return launch_hash_t<CHAMFER_L1, 0, false>(CH_ARGS);
         return launch_hash_t<CHAMFER_L1, 0, true>(CH_ARGS);
     }
     switch (ke) {
@@ -659,7 +818,7 @@ __global__ __launch_bounds__(256) void kb_setup(const Batch *__restrict__ bt) {
         }
         int64_t r = b.id - J.nb_init;
         if (r < J.nb_grid) {
-            grid_tables(J.seed, J.L, J.kh, J.zfrac, J.mult, Blk{r, J.nb_grid});
+            grid_tables(J.seed, J.L, J.kh, J.zfrac, J.mult, 0, Blk{r, J.nb_grid});
             return;
         }
         r -= J.nb_grid;
@@ -691,11 +850,11 @@ __global__ __launch_bounds__(kThreads) void kb_hash(const Batch *__restrict__ bt
         if (MODE == 0)
             hash_tile<METRIC, 0, KE, YG>(J.B, J.nB, J.B, J.d, J.L, J.lohi, J.embed, J.zfrac,
                                          J.mult, J.tables, J.log2cap, nullptr, nullptr, nullptr,
-                                         nullptr, J.nb2, J.p, b);
+                                         nullptr, J.nb2, J.p, J.nB, 1, 0, b);
         else
             hash_tile<METRIC, 1, KE, YG>(J.A, J.nA, J.B, J.d, J.L, J.lohi, J.embed, J.zfrac,
                                          J.mult, J.tables, J.log2cap, nullptr, J.D, J.nn,
-                                         nullptr, nullptr, J.p, b);
+                                         nullptr, nullptr, J.p, J.nB, 1, kProbeLast, b);
     });
 }
 

@@ -15,6 +15,11 @@ constexpr uint32_t kPurposeEmbed = 2;   // Gaussian embedding matrix
 constexpr uint32_t kPurposeSample = 3;  // importance-sampling draws
 constexpr uint64_t kEmptyKey = ~0ull;   // bucket keys are < 2^63
 constexpr int kMaxScales = 64;
+constexpr int kMaxWindow = 32;          // W of the multi-probe CrudeNN
+constexpr int kMaxReps = 64;            // k of the multi-probe CrudeNN
+// flags of the probe launches of the multi-probe CrudeNN
+constexpr int kProbeMerge = 1;  // keep the better of this and the previous structure's result
+constexpr int kProbeLast = 2;   // last structure: also reduce max D_a
 
 // Device-resident parameters of one call; written by the kernels, read by
 // later kernels of the same call (no host round trip).
@@ -81,7 +86,7 @@ __device__ __forceinline__ int ceil_log2_pos(double x) {
 struct Plan {
     // problem
     int64_t nA, nB, T;
-    int32_t d, metric, L, ke, kh, q, precision;
+    int32_t d, metric, L, ke, kh, q, precision, window, reps;
     uint64_t seed;
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
@@ -274,20 +279,27 @@ __device__ __forceinline__ void batch_loop(const Batch *__restrict__ bt, int sta
 // All launchers enqueue on `st` and return hipGetLastError().
 
 hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t st);
+// rep: index of the independent LSH structure (0 for the single one)
 hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
-                              hipStream_t st);
+                              int rep, hipStream_t st);
 hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
                          hipStream_t st);
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st);
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st);
 // mode 0: insert B into the tables (l2: also |b|^2 into nb2_out and
-// p->b2max_bits when nb2_out is set); 1: probe A (CrudeNN); 2: write keys
+// p->b2max_bits when nb2_out is set); 1: probe A (CrudeNN); 2: write keys;
+// 3 / 4: insert / probe with a window of W points per bucket (the tables
+// are then keys [L][cap] followed by members [L][cap][W]).  flags: kProbe*.
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
                        const float *embed_t, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
-                       hipStream_t st);
+                       int W, int flags, hipStream_t st);
+// Bytes of the tables of L scales of 2^log2cap buckets with window W.
+size_t table_bytes(int L, int log2cap, int W);
+// Empty tables (window W).
+hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStream_t st);
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
                           DevParams *p, hipStream_t st);
 hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,

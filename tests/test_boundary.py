@@ -100,10 +100,9 @@ def test_argument_errors_are_host_side():
     assert _raw_estimate(lib, T=-5) == -1
     assert _raw_estimate(lib, ws_bytes=0) == -2
     assert _raw_estimate(lib, ws_bytes=64) == -2
-    bad = ch.Opts(0, 12, 0, 0)
-    assert _raw_estimate(lib, opts=ctypes.byref(bad)) == -1
-    bad = ch.Opts(0, 0, 7, 0)
-    assert _raw_estimate(lib, opts=ctypes.byref(bad)) == -1
+    for bad in (ch.Opts(0, 12, 0, 0, 0, 0), ch.Opts(0, 0, 7, 0, 0, 0), ch.Opts(0, 0, 0, 33, 0, 0),
+                ch.Opts(0, 0, 0, -1, 0, 0), ch.Opts(0, 0, 0, 0, 65, 0), ch.Opts(0, 0, 0, 0, 0, 1)):
+        assert _raw_estimate(lib, opts=ctypes.byref(bad)) == -1
     dummy = ctypes.c_void_p(16)
     assert lib.chamfer_exact(dummy, dummy, 5, 0, 3, 2, dummy, None, None, None, dummy, 1 << 20,
                              None) == -1

@@ -116,6 +116,77 @@ def test_crude_nn_self_and_single(ch, orc):
     assert np.all(host(nn) == 0)
 
 
+# --------------------------------------------------- multi-probe CrudeNN ---
+
+MULTI = [(4, 1), (1, 3), (8, 4), (32, 2)]  # (window W, structures k)
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", [(1000, 777, 3), (2049, 3001, 16), (300, 2500, 128),
+                                   (130, 211, 37), (65, 1, 32), (5, 3, 4)])
+@pytest.mark.parametrize("W,reps", MULTI)
+def test_crude_multiprobe_bit_exact(ch, orc, metric, shape, W, reps):
+    """k x W CrudeNN (window tables, repeated structures) against the oracle:
+    first colliding scale, candidate and D_a bits."""
+    n_a, n_b, d = shape
+    banner(f"crude_nn multiprobe metric={metric} shape={shape} W={W} k={reps}")
+    A, B = clouds(n_a, n_b, d, seed=n_a + d + 5)
+    D, nn, sc = ch.crude_nn(dev(A), dev(B), metric, 0.1, 17, window=W, reps=reps)
+    ref = orc.crude_nn(A, B, metric, 0.1, 17, window=W, reps=reps)
+    assert np.array_equal(host(sc), ref["scale"])
+    assert np.array_equal(host(nn), ref["nn"])
+    assert np.array_equal(host(D).view(np.uint32), ref["D"].view(np.uint32))
+
+
+@pytest.mark.parametrize("d,W", [(230, 16), (250, 4), (224, 16)])
+def test_crude_multiprobe_wide_l1(ch, orc, d, W):
+    """l1 rows too wide to stage in LDS next to the window (coordinates read
+    from HBM instead), and the widest that still fits."""
+    banner(f"crude_nn multiprobe l1 d={d} W={W}")
+    A, B = clouds(400, 600, d, seed=d)
+    D, nn, sc = ch.crude_nn(dev(A), dev(B), 1, 0.2, 3, window=W, reps=2)
+    ref = orc.crude_nn(A, B, 1, 0.2, 3, window=W, reps=2)
+    assert np.array_equal(host(sc), ref["scale"])
+    assert np.array_equal(host(nn), ref["nn"])
+    assert np.array_equal(host(D).view(np.uint32), ref["D"].view(np.uint32))
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", [(2049, 3001, 16), (300, 2500, 128)])
+def test_estimate_multiprobe(ch, orc, metric, shape):
+    """The estimator on top of the k x W crude distances: weights, draws,
+    sample minima and eta as the oracle."""
+    n_a, n_b, d = shape
+    banner(f"estimate multiprobe metric={metric} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=11 * d)
+    out = ch.chamfer_estimate(dev(A), dev(B), metric, 0.2, 300, 8, window=8, reps=4)
+    ref = orc.chamfer_estimate(A, B, metric, 0.2, 300, 8, window=8, reps=4)
+    c = ref["crude"]
+    assert np.array_equal(host(out["crude_D"]).view(np.uint32), c["D"].view(np.uint32))
+    assert np.array_equal(host(out["crude_nn"]), c["nn"])
+    assert np.array_equal(host(out["crude_scale"]), c["scale"])
+    assert int(host(out["W"])[0]) == ref["W"] and int(host(out["s"])[0]) == ref["s"]
+    assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+    m32, a32 = orc.nn_f32(A, B, metric, rows=ref["idx"])
+    assert np.array_equal(host(out["sample_nn"]), a32)
+    assert np.array_equal(host(out["sample_min"]).view(np.uint32), m32.view(np.uint32))
+    assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=REL)
+
+
+def test_multiprobe_lowers_crude_distances(ch):
+    """More structures and a wider window retrieve supersets: D_a can only
+    go down (the window W = 1, k = 1 run is the base algorithm)."""
+    A, B = clouds(3000, 3000, 16, seed=99)
+    base, _, _ = ch.crude_nn(dev(A), dev(B), 2, 0.1, 5)
+    one, _, _ = ch.crude_nn(dev(A), dev(B), 2, 0.1, 5, window=1, reps=1)
+    wide, _, _ = ch.crude_nn(dev(A), dev(B), 2, 0.1, 5, window=8, reps=1)
+    many, _, _ = ch.crude_nn(dev(A), dev(B), 2, 0.1, 5, window=8, reps=8)
+    b, o, w, m = host(base), host(one), host(wide), host(many)
+    assert np.array_equal(b.view(np.uint32), o.view(np.uint32))
+    assert np.all(w <= b) and np.all(m <= w)
+    assert m.sum() < b.sum()
+
+
 # -------------------------------------------------------- nearest rows ---
 
 @pytest.mark.parametrize("metric", [1, 2])
