@@ -331,6 +331,54 @@ def serve_bench(args, ch, torch, workloads):
     return {"serving": out}
 
 
+# (k structures, window W) of the multi-probe CrudeNN report; (1, 1) is the
+# base algorithm.
+KW_CONFIGS = ((1, 1), (1, 4), (1, 16), (4, 1), (4, 4), (8, 8), (16, 4))
+KW_SEEDS = 20
+KW_T = (50, 200, 2000)
+
+
+def kw_report(args, ch, torch, At, Bt, metric, eps, T, L, desc):
+    """Multi-probe CrudeNN: for each (k, W), the estimate's time (CrudeNN
+    stages and total), lambda_hat = D / CH, and the relative error of eta
+    over KW_SEEDS hash/sampling seeds at several T (the sample-complexity
+    comparison of the large-scale experiments).  CH is the GPU brute force
+    (canonical float32 minima, float64 sum)."""
+    ex, _, _ = ch.chamfer_exact(At, Bt, metric, rows_out=False)
+    CH = float(ex.item())
+    out = {"workload": desc, "CH": CH, "seeds": KW_SEEDS, "configs": []}
+    ev = HipEvents(ch.STAGE_EVENTS)
+    for k, W in KW_CONFIGS:
+        def run(seed, t):
+            return ch.chamfer_estimate(At, Bt, metric, eps, t, seed, n_scales=L, window=W, reps=k,
+                                       stage_events=ev.arr)
+        run(1, T)
+        torch.cuda.synchronize()
+        crude, total = [], []
+        for _ in range(5):
+            o = run(1, T)
+            torch.cuda.synchronize()
+            crude.append(ev.ms(0, 3))
+            total.append(ev.ms(0, ch.STAGE_EVENTS - 1))
+        lam = float(o["D"].item()) / CH
+        errs = {}
+        for t in KW_T:
+            e = []
+            for s in range(KW_SEEDS):
+                o = run(100 + s, t)
+                e.append(abs(float(o["eta"].item()) - CH) / CH)
+            errs[str(t)] = {"mean_rel_err": float(np.mean(e)), "rms_rel_err":
+                            float(np.sqrt(np.mean(np.square(e)))), "max_rel_err": float(np.max(e))}
+        row = {"k": k, "W": W, "crude_ms": float(np.median(crude)),
+               "estimate_ms": float(np.median(total)), "lambda_hat": lam, "rel_err": errs}
+        out["configs"].append(row)
+        print(f"[bench] k={k} W={W}: crude {row['crude_ms']:.3f} ms, estimate "
+              f"{row['estimate_ms']:.3f} ms, lambda_hat {lam:.3f}, rms err T={T}: "
+              f"{errs[str(KW_T[-1])]['rms_rel_err']:.4f}", file=sys.stderr, flush=True)
+    ev.close()
+    return {"kw_report": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,6 +392,9 @@ def main():
     ap.add_argument("--precision-report", action="store_true",
                     help="time exact CH and the estimator in FP32, BF16 and FP8 and report "
                          "their errors (l2 workloads)")
+    ap.add_argument("--kw-report", action="store_true",
+                    help="multi-probe CrudeNN: time, lambda_hat and the error of eta over "
+                         "seeds for several (k structures, window W)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson stream of mixed requests through the "
                          "continuous-batching server, FP32 and BF16-refined")
@@ -392,6 +443,9 @@ def main():
     if args.precision_report:
         print(json.dumps(precision_report(args, ch, torch, A, B, At, Bt, metric, eps, T, L,
                                           desc)))
+        return
+    if args.kw_report:
+        print(json.dumps(kw_report(args, ch, torch, At, Bt, metric, eps, T, L, desc)))
         return
 
     def step():
