@@ -289,13 +289,23 @@ def sample(seed, P, W, T):
     return idx
 
 
+SAMPLING_IMPORTANCE = 0
+SAMPLING_UNIFORM = 1
+
+
 def chamfer_estimate(A, B, metric, eps, T, seed, n_scales=0,
-                     embed_dim=DEFAULT_EMBED_DIM, crude=None, window=1, reps=1):
+                     embed_dim=DEFAULT_EMBED_DIM, crude=None, window=1, reps=1,
+                     sampling=SAMPLING_IMPORTANCE):
     """Chamfer-Estimate figure with the fixed-point distribution above.
 
     eta = (1/T) sum_l (W / w_{x_l}) * min_b d(x_l, b), the per-sample minima in
     double precision and the sum exactly rounded.  eta = 0 when every D_a is 0
-    (then every min_b d(a, b) is 0 as well) and when A is empty."""
+    (then every min_b d(a, b) is 0 as well) and when A is empty.
+
+    sampling=SAMPLING_UNIFORM is the uniform-sampling baseline of the
+    uniform-vs-importance paragraph: the same steps with every D_a = 1, so
+    every point has the same fixed-point weight w, the draw is uniform over A
+    and (W / w) = n_A, i.e. eta = (n_A / T) sum_l min_b d(x_l, b)."""
     A, B = _f32(A), _f32(B)
     n_a = A.shape[0]
     if T <= 0:
@@ -303,6 +313,8 @@ def chamfer_estimate(A, B, metric, eps, T, seed, n_scales=0,
     if n_a == 0:
         return dict(eta=0.0, T=T, idx=np.zeros(0, np.int32), m=np.zeros(0), W=0, s=0,
                     D_norm=0.0, crude=None)
+    if crude is None and sampling == SAMPLING_UNIFORM:
+        crude = dict(D=np.ones(n_a, np.float32))
     if crude is None:
         crude = crude_nn(A, B, metric, eps, seed, n_scales, embed_dim, window, reps)
     s, w, P, W, zero = weights(crude["D"])
@@ -315,3 +327,19 @@ def chamfer_estimate(A, B, metric, eps, T, seed, n_scales=0,
     eta = math.fsum(terms) / T
     return dict(eta=eta, T=T, idx=idx, m=m, nn=arg, W=W, s=s, w=w, P=P,
                 D_norm=math.ldexp(float(W), -s), crude=crude)
+
+
+def chamfer_symmetric_exact(A, B, metric):
+    """CH(A, B) + CH(B, A) (the symmetric form of the small-scale
+    experiments); returns (sum, CH(A, B), CH(B, A))."""
+    ab = chamfer_exact(A, B, metric)[0]
+    ba = chamfer_exact(B, A, metric)[0]
+    return ab + ba, ab, ba
+
+
+def chamfer_symmetric_estimate(A, B, metric, eps, T, seed, **kw):
+    """eta(A, B) + eta(B, A), both directions with the same seed and
+    options; returns (sum, eta(A, B), eta(B, A))."""
+    ab = chamfer_estimate(A, B, metric, eps, T, seed, **kw)["eta"]
+    ba = chamfer_estimate(B, A, metric, eps, T, seed, **kw)["eta"]
+    return ab + ba, ab, ba

@@ -546,3 +546,74 @@ def test_outlier_scenario(orc, d):
         u_est = A.shape[0] * m64[uni].mean()
         if A.shape[0] - 1 not in uni:
             assert abs(u_est - ch) > 0.5 * share * ch
+
+
+# ------------------------------------------- uniform sampling, symmetric ---
+
+def test_uniform_sampling_draws_and_weights(orc):
+    """Uniform-sampling baseline: every point gets the same weight, so the
+    draws are uniform over A (chi-square) and W / w = n_A exactly."""
+    A, B = workloads.small_l2(seed=5, n=200, d=3)
+    r = orc.chamfer_estimate(A, B, 1, 0.2, 40000, 9, sampling=orc.SAMPLING_UNIFORM)
+    assert np.all(r["w"] == r["w"][0]) and r["W"] == 200 * int(r["w"][0])
+    assert float(r["W"]) / float(r["w"][0]) == 200.0
+    counts = np.bincount(r["idx"], minlength=200)
+    assert stats.chisquare(counts).pvalue > 1e-4
+
+
+def test_uniform_sampling_closed_form(orc):
+    """Every point at the same distance from B: the uniform estimate equals
+    CH for any draws (l1: the cube's vertices around the origin)."""
+    A = np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], np.float32)
+    B = np.zeros((1, 3), np.float32)
+    for seed in range(5):
+        r = orc.chamfer_estimate(A, B, 1, 0.5, 7, seed, sampling=orc.SAMPLING_UNIFORM)
+        assert r["eta"] == 24.0
+
+
+def test_uniform_sampling_unbiased(orc):
+    """E[eta] = CH over the draws, with the variance of the plain uniform
+    estimator, n_A^2 Var(m) / T."""
+    A, B = workloads.small_l2(seed=23, n=300, d=4)
+    T = 25
+    ch, m64, _ = orc.chamfer_exact(A, B, 1)
+    etas = np.array([orc.chamfer_estimate(A, B, 1, 0.2, T, s, sampling=orc.SAMPLING_UNIFORM)["eta"]
+                     for s in range(1500)])
+    var = 300.0 ** 2 * m64.var() / T
+    assert abs(etas.mean() - ch) <= 4.5 * math.sqrt(var / len(etas))
+    ratio = etas.var(ddof=1) / var
+    lo, hi = stats.chi2.ppf([1e-5, 1 - 1e-5], len(etas) - 1) / (len(etas) - 1)
+    assert lo <= ratio <= hi
+
+
+def test_uniform_misses_outlier(orc):
+    """Outlier scenario: with 100 samples uniform sampling rarely draws the
+    outlier and is then far off, where importance sampling is within eps."""
+    A, B = workloads.outlier_cloud(seed=100, n=2000, d=100)
+    ch, m64, _ = orc.chamfer_exact(A, B, 1)
+    far = 0
+    for seed in range(20):
+        u = orc.chamfer_estimate(A, B, 1, 0.1, 100, seed, sampling=orc.SAMPLING_UNIFORM)
+        i = orc.chamfer_estimate(A, B, 1, 0.1, 100, seed)
+        assert abs(i["eta"] - ch) <= 0.1 * ch
+        far += abs(u["eta"] - ch) > 0.2 * ch
+    assert far >= 15
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_symmetric_exact(orc, metric):
+    """CH(A, B) + CH(B, A) against scipy's tree both ways; symmetric in its
+    arguments, zero for A = B."""
+    rng = np.random.default_rng(30 + metric)
+    A = rng.standard_normal((400, 5)).astype(np.float32)
+    B = rng.standard_normal((250, 5)).astype(np.float32)
+    p = 1 if metric == 1 else 2
+    ref = (cKDTree(B.astype(np.float64)).query(A.astype(np.float64), p=p)[0].sum()
+           + cKDTree(A.astype(np.float64)).query(B.astype(np.float64), p=p)[0].sum())
+    tot, ab, ba = orc.chamfer_symmetric_exact(A, B, metric)
+    assert tot == pytest.approx(ref, rel=1e-12)
+    assert orc.chamfer_symmetric_exact(B, A, metric)[0] == pytest.approx(tot, rel=1e-15)
+    assert orc.chamfer_symmetric_exact(A, A, metric)[0] == 0.0
+    e_tot, e_ab, e_ba = orc.chamfer_symmetric_estimate(A, B, metric, 0.2, 2000, 4)
+    assert e_tot == e_ab + e_ba
+    assert e_tot == pytest.approx(tot, rel=0.05)
