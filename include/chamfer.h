@@ -56,6 +56,16 @@ enum chamfer_precision {
     CHAMFER_FP8 = 2    /* l2 distance tiles on fp8-e4m3 MFMA + float32 re-rank*/
 };
 
+/* How chamfer_estimate draws its T points of A (the uniform-vs-importance
+ * paragraph of the algorithm overview). */
+enum chamfer_sampling {
+    CHAMFER_IMPORTANCE = 0,  /* proportional to the CrudeNN distances D_a      */
+    CHAMFER_UNIFORM = 1      /* uniform over A (the baseline): the same steps
+                                with every D_a = 1, so eta = (n_A/T) sum of
+                                the sampled nearest-neighbour distances; no
+                                CrudeNN and no tables                          */
+};
+
 /* Tunables; pass NULL for all defaults.  Zero fields take their default. */
 typedef struct chamfer_opts {
     int32_t n_scales;   /* L grid scales; 0 => ceil(log2(max(n_A,n_B)/eps))   */
@@ -64,6 +74,7 @@ typedef struct chamfer_opts {
     int32_t window;     /* W points retrieved per point of A by CrudeNN, 1..32;
                            0 => 1 (the first colliding point)                  */
     int32_t reps;       /* k independent LSH structures, 1..64; 0 => 1       */
+    int32_t sampling;   /* enum chamfer_sampling; 0 => importance             */
     int32_t reserved;   /* must be 0                                          */
 } chamfer_opts;
 
@@ -76,9 +87,10 @@ typedef struct chamfer_aux {
     uint64_t *W;           /* [1] fixed-point total of the weights              */
     int32_t *s;            /* [1] fixed-point exponent (w_a = ceil(D_a 2^s))    */
     int32_t *status;       /* [1] CHAMFER_OK or CHAMFER_ENONFINITE              */
-    float *crude_D;        /* [n_A] D_a from CrudeNN                            */
-    int32_t *crude_nn;     /* [n_A] the b with D_a = d(a, b)                    */
-    int32_t *crude_scale;  /* [n_A] first colliding scale (L if none)           */
+    float *crude_D;        /* [n_A] D_a from CrudeNN (1 with uniform sampling)  */
+    int32_t *crude_nn;     /* [n_A] the b with D_a = d(a, b) (-1 if uniform)    */
+    int32_t *crude_scale;  /* [n_A] first colliding scale, L if none (-1 if
+                              uniform)                                          */
     /* Host array of CHAMFER_STAGE_EVENTS hipEvent_t (as void*), or NULL.  When
      * set, event i is recorded on the stream at stage boundary i: 0 start,
      * 1 calibration and tables done, 2 B bucketed, 3 CrudeNN done (D_a),
@@ -257,6 +269,25 @@ int chamfer_server_progress(chamfer_server *srv); /* returns requests finished *
 int chamfer_server_results(chamfer_server *srv, chamfer_result *out, int32_t max);
 int chamfer_server_stats(const chamfer_server *srv, chamfer_server_stat *out);
 int chamfer_server_destroy(chamfer_server *srv);
+
+/*
+ * Symmetric forms, CH(A, B) + CH(B, A) (the small-scale experiments).
+ * out[0] = the sum, out[1] = the A->B value, out[2] = the B->A value
+ * (device doubles).  The estimate runs chamfer_estimate in both directions
+ * with the same eps, T (0 => each direction's default), seed and opts; the
+ * exact form runs chamfer_exact both ways.  Both need n_A, n_B >= 1 and one
+ * workspace of at least the larger of chamfer_workspace_bytes(n_A, n_B, ...)
+ * and chamfer_workspace_bytes(n_B, n_A, ...) (eps = 0 for the exact form);
+ * the two directions run one after the other on `stream`.  Errors as the
+ * one-directional calls; a NaN in either direction makes the sum NaN.
+ */
+int chamfer_estimate_symmetric(const float *A, const float *B, int64_t n_A, int64_t n_B,
+                               int32_t d, int32_t metric, double eps, int64_t T, uint64_t seed,
+                               double *eta_out, const chamfer_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream);
+int chamfer_exact_symmetric(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                            int32_t metric, double *ch_out, const chamfer_opts *opts, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /* Host helpers (no device work). */
 int64_t chamfer_default_samples(int64_t n_A, double eps);            /* T default */

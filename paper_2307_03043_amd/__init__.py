@@ -38,7 +38,8 @@ class ChamferError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("n_scales", ctypes.c_int32), ("embed_dim", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("reps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reps", ctypes.c_int32), ("sampling", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _AUX_ARRAYS = ("sample_idx", "sample_min", "sample_nn", "D", "W", "s", "status",
@@ -67,6 +68,10 @@ _SIGS = {
                                          _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_nn_min": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _I32, _I32, _VP, _VP, _VP,
                                       _VP, ctypes.c_size_t, _VP]),
+    "chamfer_estimate_symmetric": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _I64,
+                                                  _U64, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "chamfer_exact_symmetric": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _VP, _VP, _VP,
+                                               ctypes.c_size_t, _VP]),
     "chamfer_default_samples": (ctypes.c_int64, [_I64, _F64]),
     "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
@@ -103,8 +108,11 @@ def _check(rc: int, where: str):
         raise ChamferError(rc, where)
 
 
-def _opts(n_scales=0, embed_dim=0, precision=0, window=0, reps=0) -> Opts:
-    return Opts(n_scales, embed_dim, precision, window, reps, 0)
+IMPORTANCE, UNIFORM = 0, 1  # enum chamfer_sampling
+
+
+def _opts(n_scales=0, embed_dim=0, precision=0, window=0, reps=0, sampling=0) -> Opts:
+    return Opts(n_scales, embed_dim, precision, window, reps, sampling, 0)
 
 
 # ----------------------------------------------------------- torch glue ---
@@ -154,8 +162,8 @@ def release_workspaces():
 # ------------------------------------------------------------- host API ---
 
 def chamfer_workspace_bytes(n_a, n_b, d, metric, eps=0.5, T=0, n_scales=0, embed_dim=0,
-                            precision=0, window=0, reps=0) -> int:
-    o = _opts(n_scales, embed_dim, precision, window, reps)
+                            precision=0, window=0, reps=0, sampling=0) -> int:
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
     return int(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o)))
 
 
@@ -247,7 +255,7 @@ def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0, window=0, reps
 
 
 def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0, precision=0,
-                     window=0, reps=0,
+                     window=0, reps=0, sampling=0,
                      with_aux=True, stage_events=None):
     """(1 +- eps) estimate of CH(A, B).  Returns a dict of device tensors:
     eta [1] double, and with_aux: sample_idx/min/nn [T], D, W, s, status,
@@ -258,7 +266,7 @@ def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
     n_a, d = A.shape
     n_b = B.shape[0]
     dev = A.device
-    o = _opts(n_scales, embed_dim, precision, window, reps)
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
     if T == 0 and 0.0 < eps < 1.0:
         T = chamfer_default_samples(max(n_a, 1), eps)
     nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o))
@@ -287,6 +295,47 @@ def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
     _check(lib().chamfer_estimate(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, T, seed,
                                   _ptr(out["eta"]), ctypes.byref(aux), ctypes.byref(o),
                                   _ptr(ws), ws.numel(), _stream(dev)), "chamfer_estimate")
+    return out
+
+
+def chamfer_estimate_symmetric(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
+                               precision=0, window=0, reps=0, sampling=0):
+    """eta(A, B) + eta(B, A): a float64 device tensor [sum, A->B, B->A]."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = A.device
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
+    nbytes = max(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o)),
+                 lib().chamfer_workspace_bytes(n_b, n_a, d, metric, eps, T, ctypes.byref(o)))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_estimate_symmetric")
+    ws = _workspace(nbytes, dev)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    _check(lib().chamfer_estimate_symmetric(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, T, seed,
+                                            _ptr(out), ctypes.byref(o), _ptr(ws), ws.numel(),
+                                            _stream(dev)), "chamfer_estimate_symmetric")
+    return out
+
+
+def chamfer_exact_symmetric(A, B, metric, *, precision=0):
+    """CH(A, B) + CH(B, A): a float64 device tensor [sum, A->B, B->A]."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = A.device
+    o = _opts(precision=precision)
+    nbytes = max(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, 0.0, 0, ctypes.byref(o)),
+                 lib().chamfer_workspace_bytes(n_b, n_a, d, metric, 0.0, 0, ctypes.byref(o)))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_exact_symmetric")
+    ws = _workspace(nbytes, dev)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    _check(lib().chamfer_exact_symmetric(_ptr(A), _ptr(B), n_a, n_b, d, metric, _ptr(out),
+                                         ctypes.byref(o), _ptr(ws), ws.numel(), _stream(dev)),
+           "chamfer_exact_symmetric")
     return out
 
 

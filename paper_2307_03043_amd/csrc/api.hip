@@ -87,13 +87,14 @@ int64_t default_samples(int64_t nA, double eps) {
     return T < 1 ? 1 : T;
 }
 
-// Validate and lay out the workspace.  hashing: the entry point runs
-// CrudeNN (needs eps and the table regions); otherwise only the regions of
-// the nearest-neighbour pass are laid out, so its total never exceeds the
-// hashing total for the same sizes.
+// Validate and lay out the workspace.  estimating: the entry point draws T
+// points (needs eps, the weight, prefix and draw regions) and, with
+// importance sampling, runs CrudeNN (the table regions); otherwise only the
+// regions of the nearest-neighbour pass are laid out, so its total never
+// exceeds the estimating total for the same sizes.
 int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, double eps,
-              int64_t T, const chamfer_opts *opts, bool hashing) {
-    const bool need_eps = hashing;
+              int64_t T, const chamfer_opts *opts, bool estimating) {
+    const bool need_eps = estimating;
     std::memset(&pl, 0, sizeof(pl));
     if (d < 1 || (metric != CHAMFER_L1 && metric != CHAMFER_L2)) return CHAMFER_EINVAL;
     if (nA < 0 || nB < 1 || nA > INT32_MAX || nB > INT32_MAX || T < 0 || T > INT32_MAX)
@@ -104,6 +105,8 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     if (o.n_scales < 0 || o.n_scales > kMaxScales || o.reserved != 0) return CHAMFER_EINVAL;
     if (o.window < 0 || o.window > kMaxWindow || o.reps < 0 || o.reps > kMaxReps)
         return CHAMFER_EINVAL;
+    if (o.sampling != CHAMFER_IMPORTANCE && o.sampling != CHAMFER_UNIFORM) return CHAMFER_EINVAL;
+    const bool hashing = estimating && o.sampling == CHAMFER_IMPORTANCE;
     if (o.precision < CHAMFER_FP32 || o.precision > CHAMFER_FP8) return CHAMFER_EINVAL;
     const int ke = o.embed_dim ? o.embed_dim : 32;
     if (!valid_ke(ke)) return CHAMFER_EINVAL;
@@ -115,6 +118,7 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.precision = o.precision;
     pl.window = o.window ? o.window : 1;
     pl.reps = o.reps ? o.reps : 1;
+    pl.sampling = o.sampling;
     pl.L = o.n_scales ? o.n_scales : default_scales(nA, nB, e);
     pl.ke = ke;
     pl.kh = metric == CHAMFER_L1 ? d : ke;
@@ -130,20 +134,20 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
         off += align_up(bytes);
         return at;
     };
-    const int64_t nrow = (hashing && pl.T > nA) ? pl.T : nA;
-    const size_t h = hashing ? 1 : 0;
+    const int64_t nrow = (estimating && pl.T > nA) ? pl.T : nA;
+    const size_t h = hashing ? 1 : 0, e_ = estimating ? 1 : 0;
     pl.off_params = take(sizeof(DevParams));
     pl.off_lohi = take(2 * (size_t)d * sizeof(uint32_t));
     pl.off_zfrac = take(h * pl.L * pl.kh * sizeof(float));
     pl.off_mult = take(h * pl.L * pl.kh * sizeof(uint64_t));
     pl.off_embed = take(metric == CHAMFER_L2 ? h * d * ke * sizeof(float) : 0);
     pl.off_tables = take(h * table_bytes(pl.L, lc, pl.window));
-    pl.off_D = take(h * nA * sizeof(float));
+    pl.off_D = take(e_ * nA * sizeof(float));
     pl.off_nn = take(h * nA * sizeof(int32_t));
     pl.off_scale = take(h * nA * sizeof(int32_t));
-    pl.off_blocksums = take(h * ((nA + kScanBlock - 1) / kScanBlock + 1) * 8);
-    pl.off_P = take(h * nA * sizeof(uint64_t));
-    pl.off_idx = take(h * pl.T * sizeof(int32_t));
+    pl.off_blocksums = take(e_ * ((nA + kScanBlock - 1) / kScanBlock + 1) * 8);
+    pl.off_P = take(e_ * nA * sizeof(uint64_t));
+    pl.off_idx = take(e_ * pl.T * sizeof(int32_t));
     pl.off_best = take((size_t)nrow * sizeof(uint64_t));
     pl.off_partial = take((size_t)(nn_finalize_blocks(nrow) + 1) * sizeof(double));
     pl.off_nb2 = take(mfma_supported(d, metric) ? (size_t)nB * sizeof(float) : 0);
@@ -260,6 +264,11 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
     return CHAMFER_OK;
 }
 
+// out[0] = out[1] + out[2] (the two directions of a symmetric call).
+__global__ void k_sum_pair(double *out) {
+    if (threadIdx.x == 0) out[0] = out[1] + out[2];
+}
+
 __global__ void k_store_zero(double *out, int32_t *status) {
     if (threadIdx.x == 0) {
         if (out) *out = 0.0;
@@ -282,7 +291,8 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
     if (rc) return rc;
     if (nA < 1 || d > 2048 || A == nullptr || B == nullptr || eta == nullptr || job == nullptr)
         return CHAMFER_EINVAL;
-    if (pl.window != 1 || pl.reps != 1) return CHAMFER_EINVAL;  // single structure, W = 1
+    // single structure, W = 1, importance sampling
+    if (pl.window != 1 || pl.reps != 1 || pl.sampling != CHAMFER_IMPORTANCE) return CHAMFER_EINVAL;
     if (metric == CHAMFER_L2 && (embed_dev == nullptr || embed_host == nullptr))
         return CHAMFER_EINVAL;
     if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
@@ -412,9 +422,9 @@ extern "C" {
 size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,
                                int64_t T, const chamfer_opts *opts) {
     Plan pl;
-    // Without a valid eps only the non-hashing entry points can run.
-    const bool hashing = eps > 0.0 && eps < 1.0;
-    if (make_plan(pl, n_A, n_B, d, metric, eps, T, opts, hashing) != CHAMFER_OK) return 0;
+    // Without a valid eps only the non-estimating entry points can run.
+    const bool estimating = eps > 0.0 && eps < 1.0;
+    if (make_plan(pl, n_A, n_B, d, metric, eps, T, opts, estimating) != CHAMFER_OK) return 0;
     return pl.total;
 }
 
@@ -485,7 +495,8 @@ int crude_nn(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d
     int rc = make_plan(pl, n_A, n_B, d, metric, eps, 0, opts, true);
     if (rc) return rc;
     if ((A == nullptr && n_A > 0) || B == nullptr ||
-        (n_A > 0 && (D_out == nullptr || nn_out == nullptr)))
+        (n_A > 0 && (D_out == nullptr || nn_out == nullptr)) ||
+        pl.sampling != CHAMFER_IMPORTANCE)
         return CHAMFER_EINVAL;
     if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
     if (n_A == 0) return CHAMFER_OK;
@@ -510,12 +521,28 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
         return hipGetLastError() == hipSuccess ? CHAMFER_OK : CHAMFER_EHIP;
     }
     float *D = ax.crude_D ? ax.crude_D : at<float>(ws, pl.off_D);
-    int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
     int32_t *scale = ax.crude_scale;
     void **ev = ax.stage_events;
     float *nb2 = mfma_supported(d, metric) ? at<float>(ws, pl.off_nb2) : nullptr;
-    if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2))) return rc;
     DevParams *p = at<DevParams>(ws, pl.off_params);
+    if (pl.sampling == CHAMFER_UNIFORM) {
+        // the baseline: no CrudeNN, every D_a = 1 (inputs still checked)
+        uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
+        CH_TRY(mark(ev, 0, st));
+        CH_TRY(launch_init_params(p, lohi, d, st));
+        CH_TRY(launch_minmax(A, n_A, d, lohi, p, st));
+        CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
+        CH_TRY(launch_calib_final(lohi, d, p, st));
+        CH_TRY(mark(ev, 1, st));
+        if (nb2 && !lowp_supported(d, metric, pl.precision))
+            CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
+        CH_TRY(mark(ev, 2, st));
+        CH_TRY(launch_unit_weights(D, ax.crude_nn, scale, n_A, p, st));
+        CH_TRY(mark(ev, 3, st));
+    } else {
+        int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
+        if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2))) return rc;
+    }
     uint64_t *P = at<uint64_t>(ws, pl.off_P);
     int32_t *idx = at<int32_t>(ws, pl.off_idx);
     auto *best = at<unsigned long long>(ws, pl.off_best);
@@ -536,7 +563,8 @@ int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, 
     Plan pl;
     int rc = make_plan(pl, n_A, n_B, d, metric, eps, 0, opts, true);
     if (rc) return rc;
-    if ((A == nullptr && n_A > 0) || B == nullptr) return CHAMFER_EINVAL;
+    if ((A == nullptr && n_A > 0) || B == nullptr || pl.sampling != CHAMFER_IMPORTANCE)
+        return CHAMFER_EINVAL;
     if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((rc = hash_prologue(pl, A, B, seed, ws, st))) return rc;
@@ -559,6 +587,43 @@ int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, 
                               st));
     }
     return CHAMFER_OK;
+}
+
+int chamfer_estimate_symmetric(const float *A, const float *B, int64_t n_A, int64_t n_B,
+                               int32_t d, int32_t metric, double eps, int64_t T, uint64_t seed,
+                               double *eta_out, const chamfer_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream) {
+    if (n_A < 1 || n_B < 1 || eta_out == nullptr) return CHAMFER_EINVAL;
+    Plan ab, ba;
+    int rc = make_plan(ab, n_A, n_B, d, metric, eps, T, opts, true);
+    if (rc || (rc = make_plan(ba, n_B, n_A, d, metric, eps, T, opts, true))) return rc;
+    if (ws == nullptr || ws_bytes < ab.total || ws_bytes < ba.total) return CHAMFER_EWORKSPACE;
+    rc = chamfer_estimate(A, B, n_A, n_B, d, metric, eps, T, seed, eta_out + 1, nullptr, opts, ws,
+                          ws_bytes, stream);
+    if (rc) return rc;
+    rc = chamfer_estimate(B, A, n_B, n_A, d, metric, eps, T, seed, eta_out + 2, nullptr, opts, ws,
+                          ws_bytes, stream);
+    if (rc) return rc;
+    k_sum_pair<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(eta_out);
+    return hipGetLastError() == hipSuccess ? CHAMFER_OK : CHAMFER_EHIP;
+}
+
+int chamfer_exact_symmetric(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                            int32_t metric, double *ch_out, const chamfer_opts *opts, void *ws,
+                            size_t ws_bytes, void *stream) {
+    if (n_A < 1 || n_B < 1 || ch_out == nullptr) return CHAMFER_EINVAL;
+    Plan ab, ba;
+    int rc = make_plan(ab, n_A, n_B, d, metric, 0.5, 0, opts, false);
+    if (rc || (rc = make_plan(ba, n_B, n_A, d, metric, 0.5, 0, opts, false))) return rc;
+    if (ws == nullptr || ws_bytes < ab.total || ws_bytes < ba.total) return CHAMFER_EWORKSPACE;
+    rc = chamfer_exact(A, B, n_A, n_B, d, metric, ch_out + 1, nullptr, nullptr, opts, ws, ws_bytes,
+                       stream);
+    if (rc) return rc;
+    rc = chamfer_exact(B, A, n_B, n_A, d, metric, ch_out + 2, nullptr, nullptr, opts, ws, ws_bytes,
+                       stream);
+    if (rc) return rc;
+    k_sum_pair<<<1, 64, 0, static_cast<hipStream_t>(stream)>>>(ch_out);
+    return hipGetLastError() == hipSuccess ? CHAMFER_OK : CHAMFER_EHIP;
 }
 
 int64_t chamfer_default_samples(int64_t n_A, double eps) {

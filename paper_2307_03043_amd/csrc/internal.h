@@ -86,7 +86,7 @@ __device__ __forceinline__ int ceil_log2_pos(double x) {
 struct Plan {
     // problem
     int64_t nA, nB, T;
-    int32_t d, metric, L, ke, kh, q, precision, window, reps;
+    int32_t d, metric, L, ke, kh, q, precision, window, reps, sampling;
     uint64_t seed;
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
@@ -338,6 +338,10 @@ hipError_t launch_nn_finalize(const unsigned long long *best, int64_t nx, int me
 hipError_t launch_sum_final(const double *partial, int64_t nparts, const DevParams *p,
                             double *out, hipStream_t st);
 hipError_t launch_copy_status(const DevParams *p, int32_t *status_out, hipStream_t st);
+// Uniform sampling: D_a = 1 for every a (nn, scale = -1 when given) and
+// max D_a = 1.
+hipError_t launch_unit_weights(float *D, int32_t *nn, int32_t *scale, int64_t nA, DevParams *p,
+                               hipStream_t st);
 int nn_finalize_blocks(int64_t nx);
 
 // ------------------------------------------------------------ geometry

@@ -253,6 +253,25 @@ hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *
     return hipGetLastError();
 }
 
+__global__ void k_unit_weights(float *D, int32_t *nn, int32_t *scale, int64_t nA, DevParams *p) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nA; a += stride) {
+        D[a] = 1.0f;
+        if (nn) nn[a] = -1;
+        if (scale) scale[a] = -1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) p->max_d_bits = __float_as_uint(1.0f);
+}
+
+hipError_t launch_unit_weights(float *D, int32_t *nn, int32_t *scale, int64_t nA, DevParams *p,
+                               hipStream_t st) {
+    int64_t blocks = (nA + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    k_unit_weights<<<(unsigned)blocks, 256, 0, st>>>(D, nn, scale, nA, p);
+    return hipGetLastError();
+}
+
 __global__ void k_copy_status(const DevParams *p, int32_t *out) {
     if (threadIdx.x == 0) *out = p->status;
 }

@@ -464,7 +464,8 @@ int chamfer_server_submit(chamfer_server *s, const chamfer_request *req, uint64_
     if (s == nullptr || req == nullptr) return CHAMFER_EINVAL;
     if ((req->n_A > 0 && req->A == nullptr) || req->B == nullptr) return CHAMFER_EINVAL;
     if (req->d > 2048) return CHAMFER_EINVAL;  // widest class the batched stages take
-    if (req->opts.window > 1 || req->opts.reps > 1) return CHAMFER_EINVAL;  // one structure, W = 1
+    if (req->opts.window > 1 || req->opts.reps > 1 || req->opts.sampling != CHAMFER_IMPORTANCE)
+        return CHAMFER_EINVAL;  // one structure, W = 1, importance sampling
     Pending pd{};
     pd.req = *req;
     pd.footprint = footprint_of(pd.req, &pd.ws_bytes);

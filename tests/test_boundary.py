@@ -100,9 +100,26 @@ def test_argument_errors_are_host_side():
     assert _raw_estimate(lib, T=-5) == -1
     assert _raw_estimate(lib, ws_bytes=0) == -2
     assert _raw_estimate(lib, ws_bytes=64) == -2
-    for bad in (ch.Opts(0, 12, 0, 0, 0, 0), ch.Opts(0, 0, 7, 0, 0, 0), ch.Opts(0, 0, 0, 33, 0, 0),
-                ch.Opts(0, 0, 0, -1, 0, 0), ch.Opts(0, 0, 0, 0, 65, 0), ch.Opts(0, 0, 0, 0, 0, 1)):
+    for bad in (ch.Opts(0, 12, 0, 0, 0, 0, 0), ch.Opts(0, 0, 7, 0, 0, 0, 0),
+                ch.Opts(0, 0, 0, 33, 0, 0, 0), ch.Opts(0, 0, 0, -1, 0, 0, 0),
+                ch.Opts(0, 0, 0, 0, 65, 0, 0), ch.Opts(0, 0, 0, 0, 0, 2, 0),
+                ch.Opts(0, 0, 0, 0, 0, 0, 1)):
         assert _raw_estimate(lib, opts=ctypes.byref(bad)) == -1
+    # CrudeNN needs its tables: uniform sampling is an estimator option only
+    uni = ch.Opts(0, 0, 0, 0, 0, 1, 0)
+    dummy = ctypes.c_void_p(16)
+    assert lib.crude_nn(dummy, dummy, 5, 5, 3, 2, 0.5, 0, dummy, dummy, None, ctypes.byref(uni),
+                        dummy, 1 << 30, None) == -1
+    # symmetric forms need both sets non-empty and a workspace for both directions
+    out = ctypes.c_void_p(64)
+    assert lib.chamfer_estimate_symmetric(dummy, dummy, 0, 5, 3, 2, 0.5, 0, 1, out, None, dummy,
+                                          1 << 30, None) == -1
+    assert lib.chamfer_exact_symmetric(dummy, dummy, 5, 0, 3, 2, out, None, dummy, 1 << 30,
+                                       None) == -1
+    small = min(lib.chamfer_workspace_bytes(10, 1000, 3, 2, 0.5, 0, None),
+                lib.chamfer_workspace_bytes(1000, 10, 3, 2, 0.5, 0, None))
+    assert lib.chamfer_estimate_symmetric(dummy, dummy, 10, 1000, 3, 2, 0.5, 0, 1, out, None,
+                                          dummy, small, None) == -2
     dummy = ctypes.c_void_p(16)
     assert lib.chamfer_exact(dummy, dummy, 5, 0, 3, 2, dummy, None, None, None, dummy, 1 << 20,
                              None) == -1

@@ -187,6 +187,63 @@ def test_multiprobe_lowers_crude_distances(ch):
     assert m.sum() < b.sum()
 
 
+# ------------------------------------------ uniform sampling, symmetric ---
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape,T", [((1000, 777, 3), 100), ((2049, 3001, 16), 512),
+                                     ((300, 2500, 128), 257), ((130, 211, 37), 64),
+                                     ((1, 1, 5), 10)])
+def test_uniform_estimate_parity(ch, orc, metric, shape, T):
+    """Uniform-sampling baseline: unit weights, draws, sampled minima and
+    eta as the oracle; no CrudeNN output."""
+    n_a, n_b, d = shape
+    banner(f"uniform estimate metric={metric} shape={shape} T={T}")
+    A, B = clouds(n_a, n_b, d, seed=5 * d + 2)
+    for seed in (0, 77):
+        out = ch.chamfer_estimate(dev(A), dev(B), metric, 0.2, T, seed, sampling=ch.UNIFORM)
+        ref = orc.chamfer_estimate(A, B, metric, 0.2, T, seed, sampling=orc.SAMPLING_UNIFORM)
+        assert int(host(out["status"])[0]) == 0
+        assert np.all(host(out["crude_D"]) == 1.0) and np.all(host(out["crude_nn"]) == -1)
+        assert int(host(out["W"])[0]) == ref["W"] and int(host(out["s"])[0]) == ref["s"]
+        assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+        m32, a32 = orc.nn_f32(A, B, metric, rows=ref["idx"])
+        assert np.array_equal(host(out["sample_nn"]), a32)
+        assert np.array_equal(host(out["sample_min"]).view(np.uint32), m32.view(np.uint32))
+        assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=REL)
+
+
+def test_uniform_estimate_lowp(ch, orc):
+    """Uniform draws with the BF16 exact pass (its own norms, no CrudeNN)."""
+    A, B = clouds(700, 2000, 128, seed=4)
+    out = ch.chamfer_estimate(dev(A), dev(B), 2, 0.2, 300, 3, sampling=ch.UNIFORM, precision=1)
+    ref = orc.chamfer_estimate(A, B, 2, 0.2, 300, 3, sampling=orc.SAMPLING_UNIFORM)
+    assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+    m32, _ = orc.nn_f32(A, B, 2, rows=ref["idx"])
+    got = host(out["sample_min"])
+    assert np.mean(got.view(np.uint32) == m32.view(np.uint32)) >= 0.99
+    assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=1e-4)
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("shape", [(1000, 777, 3), (513, 4100, 64), (300, 250, 128)])
+def test_symmetric_parity(ch, orc, metric, shape):
+    """CH(A, B) + CH(B, A), exact and estimated (both samplings), as the
+    oracle; each direction and the sum."""
+    n_a, n_b, d = shape
+    banner(f"symmetric metric={metric} shape={shape}")
+    A, B = clouds(n_a, n_b, d, seed=9 * d + 1)
+    ex = host(ch.chamfer_exact_symmetric(dev(A), dev(B), metric))
+    ref = orc.chamfer_symmetric_exact(A, B, metric)
+    np.testing.assert_allclose(ex, np.array(ref), rtol=REL, atol=0)
+    assert ex[0] == ex[1] + ex[2]
+    for sampling in (0, 1):
+        est = host(ch.chamfer_estimate_symmetric(dev(A), dev(B), metric, 0.2, 0, 12,
+                                                 sampling=sampling))
+        r = orc.chamfer_symmetric_estimate(A, B, metric, 0.2, 0, 12, sampling=sampling)
+        np.testing.assert_allclose(est, np.array(r), rtol=REL, atol=0)
+        assert est[0] == est[1] + est[2]
+
+
 # -------------------------------------------------------- nearest rows ---
 
 @pytest.mark.parametrize("metric", [1, 2])
