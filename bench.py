@@ -379,6 +379,70 @@ def kw_report(args, ch, torch, At, Bt, metric, eps, T, L, desc):
     return {"kw_report": out}
 
 
+SAMPLING_T = (10, 20, 50, 100, 200, 500, 1000, 2000)
+SAMPLING_SEEDS = 20
+
+
+def sampling_report(args, ch, torch, workloads):
+    """Importance vs uniform sampling (the comparison of the experiments):
+    RMS relative error of the estimate over SAMPLING_SEEDS seeds at each T,
+    the smallest T reaching 2% and 1% RMS error, and the time of one
+    estimate there.  Three synthetic stand-ins: the default l2 clusters
+    (A -> B), a d = 3 surface pair in l1 with the symmetric CH(A,B) +
+    CH(B,A) (the small-scale protocol), and the outlier scenario (Gaussian
+    clouds in d = 100 plus one point at 0.5 n (1, ..., 1), l1)."""
+    cases = []
+    A, B = workloads.clusters_l2(seed=args.seed, n=100_000, d=128, k=1000)
+    cases.append(("clusters l2 |A|=|B|=100000 d=128", A, B, 2, False))
+    A, B = workloads.surface_pair(np.random.default_rng(args.seed), 20_000, 20_000)
+    cases.append(("surface pair l1 |A|=|B|=20000 d=3, symmetric", A, B, 1, True))
+    A, B = workloads.outlier_cloud(seed=args.seed, n=20_000, d=100)
+    cases.append(("outlier l1 |A|=20001 |B|=20000 d=100", A, B, 1, False))
+    out = {"seeds": SAMPLING_SEEDS, "T": list(SAMPLING_T), "cases": []}
+    for name, A, B, metric, sym in cases:
+        At = torch.from_numpy(np.ascontiguousarray(A, np.float32)).cuda()
+        Bt = torch.from_numpy(np.ascontiguousarray(B, np.float32)).cuda()
+        if sym:
+            CH = float(ch.chamfer_exact_symmetric(At, Bt, metric)[0].item())
+        else:
+            CH = float(ch.chamfer_exact(At, Bt, metric, rows_out=False)[0].item())
+
+        def est(sampling, T, seed, reps):
+            if sym:
+                return ch.chamfer_estimate_symmetric(At, Bt, metric, 0.1, T, seed,
+                                                     sampling=sampling, reps=reps)[0]
+            return ch.chamfer_estimate(At, Bt, metric, 0.1, T, seed, sampling=sampling,
+                                       reps=reps, with_aux=False)["eta"]
+
+        row = {"case": name, "CH": CH}
+        for sname, sampling, reps in (("importance", 0, 1), ("importance_4x1", 0, 4),
+                                      ("uniform", 1, 1)):
+            curve, times = [], []
+            for T in SAMPLING_T:
+                errs = [abs(float(est(sampling, T, 100 + s, reps).item()) - CH) / CH
+                        for s in range(SAMPLING_SEEDS)]
+                curve.append(float(np.sqrt(np.mean(np.square(errs)))))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for s in range(5):
+                    est(sampling, T, s, reps)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) / 5 * 1e3)
+            need = {}
+            for tgt in (0.02, 0.01):
+                ok = [i for i, e in enumerate(curve) if e <= tgt]
+                need[f"{tgt:g}"] = ({"T": SAMPLING_T[ok[0]], "ms": times[ok[0]]} if ok
+                                    else None)
+            row[sname] = {"rms_rel_err": curve, "ms": times, "to_reach": need}
+        out["cases"].append(row)
+        print(f"[bench] {name}: to reach 2% / 1% rms: "
+              + "; ".join(f"{k} {row[k]['to_reach']}" for k in ("importance", "importance_4x1",
+                                                               "uniform")),
+              file=sys.stderr, flush=True)
+        del At, Bt
+    return {"sampling_report": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,6 +459,9 @@ def main():
     ap.add_argument("--kw-report", action="store_true",
                     help="multi-probe CrudeNN: time, lambda_hat and the error of eta over "
                          "seeds for several (k structures, window W)")
+    ap.add_argument("--sampling-report", action="store_true",
+                    help="importance vs uniform sampling: error vs T over seeds and the time "
+                         "to reach 2%% / 1%% on three synthetic cases")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson stream of mixed requests through the "
                          "continuous-batching server, FP32 and BF16-refined")
@@ -428,6 +495,9 @@ def main():
 
     if args.serve:
         print(json.dumps(serve_bench(args, ch, torch, workloads)))
+        return
+    if args.sampling_report:
+        print(json.dumps(sampling_report(args, ch, torch, workloads)))
         return
 
     gen, kw, metric, eps, T, L, desc = WORKLOADS[args.workload]
