@@ -299,30 +299,53 @@ hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
 // Key of hashed coordinates y (stride 1) at the scale of side 2^e:
 // cell_k = ceil(y_k 2^-e + z'_k) + 0 (the +0 turns -0 into +0, so equal
 // cells have equal bits), key = (sum_k bits(cell_k) M_k mod 2^64) >> 1.
+// The sum is mod 2^64, so it is split over four independent accumulators
+// (the same bits in any grouping) to shorten the dependent add chain.
 template <class PZ, class PM>
 __device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh, int e, PZ zf,
                                                          PM M) {
-    unsigned long long acc = 0;
-    for (int k = 0; k < kh; ++k) {
+    unsigned long long acc[4] = {0, 0, 0, 0};
+    int k = 0;
+    for (; k + 4 <= kh; k += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float q = ldexpf(y[k + u], -e) + zf[k + u];
+            const float c = ceilf(q) + 0.0f;
+            acc[u] += (unsigned long long)__float_as_uint(c) * M[k + u];
+        }
+    }
+    for (; k < kh; ++k) {
         const float q = ldexpf(y[k], -e) + zf[k];
         const float c = ceilf(q) + 0.0f;
-        acc += (unsigned long long)__float_as_uint(c) * M[k];
+        acc[0] += (unsigned long long)__float_as_uint(c) * M[k];
     }
-    return acc >> 1;
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) >> 1;
 }
 
 // Same, with y_k = x_k - lo_k read from HBM (l1 with d too large for LDS).
 template <class PX, class PL, class PZ, class PM>
 __device__ __forceinline__ unsigned long long bucket_key_global(PX x, PL lohi, int kh, int e,
                                                                 PZ zf, PM M) {
-    unsigned long long acc = 0;
-    for (int k = 0; k < kh; ++k) {
+    unsigned long long acc[4] = {0, 0, 0, 0};
+    int k = 0;
+    for (; k + 4 <= kh; k += 4) {
+        float y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = x[k + u] - ordered_to_float(lohi[k + u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float q = ldexpf(y[u], -e) + zf[k + u];
+            const float c = ceilf(q) + 0.0f;
+            acc[u] += (unsigned long long)__float_as_uint(c) * M[k + u];
+        }
+    }
+    for (; k < kh; ++k) {
         const float y = x[k] - ordered_to_float(lohi[k]);
         const float q = ldexpf(y, -e) + zf[k];
         const float c = ceilf(q) + 0.0f;
-        acc += (unsigned long long)__float_as_uint(c) * M[k];
+        acc[0] += (unsigned long long)__float_as_uint(c) * M[k];
     }
-    return acc >> 1;
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) >> 1;
 }
 
 // Home slot: the top bits of the 63-bit key (the best-mixed bits of a
@@ -445,6 +468,37 @@ constexpr int kWaves = 4;        // wavefronts per workgroup; they split the sca
 constexpr int kThreads = 64 * kWaves;
 constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
 
+// Copy rows [np][kc] of the tile (row stride d, from column k0) into LDS
+// rows of stride ldr as f(value, k): each thread issues a batch of loads
+// before it stores any of them, so a tile costs a few memory round trips
+// instead of one per element.
+template <int BATCH, class F>
+__device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t p0, int np, int d,
+                                           int k0, int kc, float *dst, int ldr, F f) {
+    const int total = np * kc;
+    const auto *Xr = ro(X);
+    for (int base = 0; base < total; base += BATCH * kThreads) {
+        float v[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int e = base + i * kThreads + (int)threadIdx.x;
+            v[i] = 0.0f;
+            if (e < total) {
+                const int r = e / kc, k = e - r * kc;
+                v[i] = Xr[(p0 + r) * d + k0 + k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; ++i) {
+            const int e = base + i * kThreads + (int)threadIdx.x;
+            if (e < total) {
+                const int r = e / kc, k = e - r * kc;
+                dst[r * ldr + k] = f(v[i], k);
+            }
+        }
+    }
+}
+
 // MODE 0: insert the tile's points (B) into the L tables.
 // MODE 1: probe (A): first scale with a hit, candidate, D_a; max D_a.
 // MODE 2: write keys[L][n].
@@ -495,11 +549,11 @@ __device__ __forceinline__ void hash_tile(
     const int e_top = p->e_top;
 
     if (METRIC == CHAMFER_L1) {
-        if (!YG)
-            for (int e = tid; e < np * d; e += kThreads) {
-                const int r = e / d, k = e - r * d;
-                ys[r * khp + k] = ro(X)[(p0 + r) * d + k] - ordered_to_float(ro(lohi)[k]);
-            }
+        if (!YG) {
+            const auto *lo = ro(lohi);
+            stage_rows<16>(X, p0, np, d, 0, d, ys, khp,
+                           [&](float v, int k) { return v - ordered_to_float(lo[k]); });
+        }
     } else {
         // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k; wavefront
         // w computes the coordinates j in [w KE/4, (w+1) KE/4) of point lane.
@@ -516,10 +570,8 @@ __device__ __forceinline__ void hash_tile(
         for (int k0 = 0; k0 < d; k0 += kEmbedChunk) {
             const int kc = min(kEmbedChunk, d - k0);
             __syncthreads();
-            for (int e = tid; e < np * kc; e += kThreads) {
-                const int r = e / kc, k = e - r * kc;
-                xs[r * (kEmbedChunk + 1) + k] = ro(X)[(p0 + r) * d + k0 + k];
-            }
+            stage_rows<16>(X, p0, np, d, k0, kc, xs, kEmbedChunk + 1,
+                           [](float v, int) { return v; });
             if (tid < kc) los[tid] = ordered_to_float(ro(lohi)[k0 + tid]);
             __syncthreads();
             if (active) {
