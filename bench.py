@@ -443,6 +443,72 @@ def sampling_report(args, ch, torch, workloads):
     return {"sampling_report": out}
 
 
+RETRIEVAL_K = (1, 5, 10, 30)
+RETRIEVAL_SETS = (("distinct surfaces", 1, 0.0), ("families of 10, 2% jitter", 10, 0.02))
+
+
+def retrieval_report(args, ch, torch, workloads):
+    """One-vs-many retrieval (the downstream experiment): collections of
+    1000 d = 3 surface clouds of 1000..4000 points and 20 queries, each a
+    resample of a member; l1, three scales, T = 50.  Two collections: every
+    member its own random surface, and families of 10 members sharing a base
+    surface with 2% parameter jitter (near neighbours).  For each k: recall@k
+    (the true nearest cloud under exact symmetric CH among the k smallest
+    estimates, i.e. top-1 accuracy after the exact re-rank) and the time of
+    one retrieval, against brute force (exact symmetric CH to every cloud,
+    one library call per cloud)."""
+    m, queries, metric, eps, T, L = 1000, 20, 1, 0.2, 50, 3
+    out = {"m": m, "n": [1000, 4000], "d": 3, "queries": queries, "metric": "l1", "eps": eps,
+           "T": T, "L": L, "sets": []}
+    for name, family, jitter in RETRIEVAL_SETS:
+        clouds, qs, src = workloads.retrieval_collection(seed=args.seed, m=m, n_min=1000,
+                                                         n_max=4000, queries=queries,
+                                                         family=family, jitter=jitter)
+        sizes = [c.shape[0] for c in clouds]
+        Bs = torch.from_numpy(np.ascontiguousarray(np.concatenate(clouds), np.float32)).cuda()
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        views = [Bs[offs[i]:offs[i + 1]] for i in range(m)]
+        Qs = [torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda() for q in qs]
+        torch.cuda.synchronize()
+        print(f"[bench] retrieval ({name}): {m} clouds, {int(offs[-1])} points, {queries} "
+              "queries", file=sys.stderr, flush=True)
+
+        truth, brute_ms = [], []
+        for q in Qs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vals = [ch.chamfer_exact_symmetric(q, v, metric) for v in views]
+            exact = torch.stack([v[0] for v in vals]).cpu().numpy()
+            brute_ms.append((time.perf_counter() - t0) * 1e3)
+            truth.append(int(np.argmin(exact)))
+        print(f"[bench] retrieval: brute force {np.median(brute_ms):.1f} ms/query",
+              file=sys.stderr, flush=True)
+
+        ch.chamfer_retrieve_packed(Qs[0], Bs, sizes, metric, eps, T, 1, 1, n_scales=L)  # warm
+        rows = []
+        for k in RETRIEVAL_K:
+            hits = 0
+            times = []
+            for qi, q in enumerate(Qs):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, top, _ = ch.chamfer_retrieve_packed(q, Bs, sizes, metric, eps, T, 1 + qi, k,
+                                                       n_scales=L)
+                times.append((time.perf_counter() - t0) * 1e3)
+                hits += top[0] == truth[qi]
+            rows.append({"k": k, "recall_at_k": hits / queries,
+                         "ms_per_query": float(np.median(times))})
+            print(f"[bench] retrieval k={k}: recall {hits}/{queries}, "
+                  f"{rows[-1]['ms_per_query']:.2f} ms/query", file=sys.stderr, flush=True)
+        out["sets"].append({"collection": name, "points": int(offs[-1]),
+                            "brute_ms_per_query": float(np.median(brute_ms)),
+                            "nearest_is_source": float(np.mean([t == int(s) for t, s in
+                                                                zip(truth, src)])),
+                            "rows": rows})
+        del Bs, views, Qs
+    return {"retrieval_report": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +528,9 @@ def main():
     ap.add_argument("--sampling-report", action="store_true",
                     help="importance vs uniform sampling: error vs T over seeds and the time "
                          "to reach 2%% / 1%% on three synthetic cases")
+    ap.add_argument("--retrieval-report", action="store_true",
+                    help="one-vs-many retrieval over 1000 clouds: recall@k and time vs "
+                         "brute force")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: Poisson stream of mixed requests through the "
                          "continuous-batching server, FP32 and BF16-refined")
@@ -498,6 +567,9 @@ def main():
         return
     if args.sampling_report:
         print(json.dumps(sampling_report(args, ch, torch, workloads)))
+        return
+    if args.retrieval_report:
+        print(json.dumps(retrieval_report(args, ch, torch, workloads)))
         return
 
     gen, kw, metric, eps, T, L, desc = WORKLOADS[args.workload]

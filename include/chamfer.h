@@ -289,6 +289,34 @@ int chamfer_exact_symmetric(const float *A, const float *B, int64_t n_A, int64_t
                             int32_t metric, double *ch_out, const chamfer_opts *opts, void *ws,
                             size_t ws_bytes, void *stream);
 
+/*
+ * One-vs-many retrieval (the downstream experiment of the experiments
+ * section: the nearest cloud to A under CH(A, B) + CH(B, A)).  Bs holds m
+ * clouds back to back (device, row-major float32); offsets (host, m + 1
+ * entries, offsets[0] = 0, strictly increasing) gives cloud i as rows
+ * offsets[i] .. offsets[i+1]-1.  For every cloud the symmetric estimate
+ * eta(A, B_i) + eta(B_i, A) is computed (both directions with eps, T, seed
+ * and opts; the jobs run 64 at a time through the batched estimator
+ * stages) into est_out (device double[m], may be NULL); the k clouds with
+ * the smallest estimates (ties to the lower index) are then re-ranked by
+ * their exact symmetric CH (always float32, whatever opts.precision):
+ * top_out (host int32[k]) gets their indices in
+ * ascending order of exact CH (ties to the lower index) and top_ch_out
+ * (host double[k]) the values.  opts.window, reps and sampling must be the
+ * defaults; d <= 2048; every cloud non-empty.  The workspace needs
+ * chamfer_retrieve_workspace_bytes (64 estimator workspaces sized for the
+ * largest cloud, plus small tables; 0 on invalid arguments).  Synchronous: returns after the stream
+ * has drained.  Errors as chamfer_estimate; a cloud with a NaN/Inf
+ * coordinate gets a NaN estimate and ranks last.
+ */
+size_t chamfer_retrieve_workspace_bytes(int64_t n_A, const int64_t *offsets, int32_t m,
+                                        int32_t d, int32_t metric, double eps, int64_t T,
+                                        const chamfer_opts *opts);
+int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t *offsets,
+                     int32_t m, int32_t d, int32_t metric, double eps, int64_t T, uint64_t seed,
+                     int32_t k, const chamfer_opts *opts, double *est_out, int32_t *top_out,
+                     double *top_ch_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Host helpers (no device work). */
 int64_t chamfer_default_samples(int64_t n_A, double eps);            /* T default */
 int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps); /* L default */

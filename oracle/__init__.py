@@ -343,3 +343,16 @@ def chamfer_symmetric_estimate(A, B, metric, eps, T, seed, **kw):
     ab = chamfer_estimate(A, B, metric, eps, T, seed, **kw)["eta"]
     ba = chamfer_estimate(B, A, metric, eps, T, seed, **kw)["eta"]
     return ab + ba, ab, ba
+
+
+def retrieve(A, clouds, metric, eps, T, seed, k, **kw):
+    """One-vs-many retrieval (the downstream experiment: the nearest cloud
+    under CH(A, B) + CH(B, A)): the symmetric estimate against every cloud,
+    the k smallest (ties to the lower index), then their exact symmetric CH
+    ranked ascending (ties to the lower index).  Returns (estimates, the k
+    cloud indices, their exact values)."""
+    est = np.array([chamfer_symmetric_estimate(A, B, metric, eps, T, seed, **kw)[0]
+                    for B in clouds])
+    cand = sorted(range(len(clouds)), key=lambda i: (est[i], i))[:k]
+    ranked = sorted((chamfer_symmetric_exact(A, clouds[i], metric)[0], i) for i in cand)
+    return est, [i for _, i in ranked], [v for v, _ in ranked]

@@ -72,6 +72,10 @@ _SIGS = {
                                                   _U64, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_exact_symmetric": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _VP, _VP, _VP,
                                                ctypes.c_size_t, _VP]),
+    "chamfer_retrieve_workspace_bytes": (ctypes.c_size_t, [_I64, _VP, _I32, _I32, _I32, _F64,
+                                                           _I64, _VP]),
+    "chamfer_retrieve": (ctypes.c_int, [_VP, _I64, _VP, _VP, _I32, _I32, _I32, _F64, _I64, _U64,
+                                        _I32, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_default_samples": (ctypes.c_int64, [_I64, _F64]),
     "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
@@ -337,6 +341,47 @@ def chamfer_exact_symmetric(A, B, metric, *, precision=0):
                                          ctypes.byref(o), _ptr(ws), ws.numel(), _stream(dev)),
            "chamfer_exact_symmetric")
     return out
+
+
+def chamfer_retrieve(A, clouds, metric, eps, T=0, seed=0, k=10, **kw):
+    """Nearest clouds to A under CH(A, B) + CH(B, A): `clouds` is a list of
+    [n_i, d] device tensors (concatenated here; chamfer_retrieve_packed
+    takes them already packed).  Returns (est [m] float64 device tensor of
+    symmetric estimates, top-k cloud indices ranked by exact symmetric CH,
+    their exact values)."""
+    torch = _torch()
+    Bs = torch.cat([_points(B, "B") for B in clouds]).contiguous()
+    return chamfer_retrieve_packed(A, Bs, [int(B.shape[0]) for B in clouds], metric, eps, T,
+                                   seed, k, **kw)
+
+
+def chamfer_retrieve_packed(A, Bs, sizes, metric, eps, T=0, seed=0, k=10, *, n_scales=0,
+                            embed_dim=0, precision=0):
+    """As chamfer_retrieve, with the m clouds back to back in one [sum n_i,
+    d] device tensor `Bs` and their sizes in `sizes`."""
+    torch = _torch()
+    A, Bs = _points(A, "A"), _points(Bs, "Bs")
+    n_a, d = A.shape
+    dev = A.device
+    offsets = np.zeros(len(sizes) + 1, np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    if offsets[-1] != Bs.shape[0] or Bs.shape[1] != d:
+        raise ValueError("chamfer_retrieve: sizes do not match Bs")
+    m = len(sizes)
+    o = _opts(n_scales, embed_dim, precision)
+    nbytes = lib().chamfer_retrieve_workspace_bytes(n_a, offsets.ctypes.data, m, d, metric, eps,
+                                                    T, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_retrieve")
+    ws = _workspace(nbytes, dev)
+    est = torch.empty(m, dtype=torch.float64, device=dev)
+    top = np.zeros(k, np.int32)
+    vals = np.zeros(k, np.float64)
+    _check(lib().chamfer_retrieve(_ptr(A), n_a, _ptr(Bs), offsets.ctypes.data, m, d, metric, eps,
+                                  T, seed, k, ctypes.byref(o), _ptr(est), top.ctypes.data,
+                                  vals.ctypes.data, _ptr(ws), ws.numel(), _stream(dev)),
+           "chamfer_retrieve")
+    return est, top.tolist(), vals.tolist()
 
 
 def chamfer_hash_keys(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0):

@@ -36,7 +36,11 @@ namespace chamfer {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kTileRows = 32;  // B rows per LDS tile: two 16-row MFMA blocks
+#ifndef CH_MFMA_MB
+#define CH_MFMA_MB 2
+#endif
+constexpr int kMB = CH_MFMA_MB;          // 16-row MFMA blocks per LDS tile
+constexpr int kTileRows = 16 * kMB;      // B rows per LDS tile
 // Launch shape, chosen by measurement on MI355X (l2, d = 128): one block of
 // 16 queries per wavefront keeps the VGPR count low enough for two
 // wavefronts per SIMD, and ~4096 workgroups give chunks of a few hundred
@@ -203,31 +207,35 @@ __device__ __forceinline__ void nnmin_l2_mfma(
         if (next < b1) fetch(next);
 
         if (wave_active) {
-            v4f acc[2][NB];
+            v4f acc[kMB][NB];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < kMB; ++m)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < KQ / 4; ++t) {
-                const float4 f0 = *reinterpret_cast<const float4 *>(&tile[j * LDR + g * KQ + 4 * t]);
-                const float4 f1 =
-                    *reinterpret_cast<const float4 *>(&tile[(16 + j) * LDR + g * KQ + 4 * t]);
-                const float a0[4] = {f0.x, f0.y, f0.z, f0.w};
-                const float a1[4] = {f1.x, f1.y, f1.z, f1.w};
+                float a[kMB][4];
+#pragma unroll
+                for (int m = 0; m < kMB; ++m) {
+                    const float4 f = *reinterpret_cast<const float4 *>(
+                        &tile[(16 * m + j) * LDR + g * KQ + 4 * t]);
+                    a[m][0] = f.x;
+                    a[m][1] = f.y;
+                    a[m][2] = f.z;
+                    a[m][3] = f.w;
+                }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], qf[nb][4 * t + s],
-                                                                         acc[0][nb], 0, 0, 0);
-                        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], qf[nb][4 * t + s],
-                                                                         acc[1][nb], 0, 0, 0);
-                    }
+                    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                        for (int m = 0; m < kMB; ++m)
+                            acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a[m][s], qf[nb][4 * t + s], acc[m][nb], 0, 0, 0);
             }
             // Lane (g, j) holds rows 16m + 4g + r of the tile for query j.
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < kMB; ++m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int lr = 16 * m + 4 * g + r;

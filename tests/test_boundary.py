@@ -129,6 +129,48 @@ def test_argument_errors_are_host_side():
                               None) == -1
 
 
+def test_retrieve_argument_errors_are_host_side():
+    """Retrieval rejects bad collections, k, options and workspaces before
+    any device work (no GPU here: a launch would fail with EHIP)."""
+    import numpy as np
+    lib = ch.lib()
+    dummy = ctypes.c_void_p(256)
+    top = np.zeros(8, np.int32)
+    vals = np.zeros(8, np.float64)
+
+    def offs(*o):
+        return np.array(o, np.int64)
+
+    def size(o, m=None, n_a=10, d=3, metric=2, opts=None):
+        return lib.chamfer_retrieve_workspace_bytes(n_a, o.ctypes.data, len(o) - 1 if m is None
+                                                    else m, d, metric, 0.2, 0,
+                                                    None if opts is None else ctypes.byref(opts))
+
+    def call(o, k=1, m=None, ws_bytes=None, n_a=10, d=3, opts=None, A=dummy):
+        m = len(o) - 1 if m is None else m
+        if ws_bytes is None:
+            ws_bytes = 1 << 40
+        return lib.chamfer_retrieve(A, n_a, dummy, o.ctypes.data, m, d, 2, 0.2, 0, 1, k, opts,
+                                    None, top.ctypes.data, vals.ctypes.data, dummy, ws_bytes, None)
+
+    good = offs(0, 5, 9, 30)
+    assert size(good) > 0
+    assert size(good, n_a=0) == 0
+    assert size(offs(0, 5, 5, 9)) == 0          # empty cloud
+    assert size(offs(1, 5, 9)) == 0             # offsets[0] != 0
+    assert size(good, m=0) == 0
+    assert size(good, d=4096) == 0
+    assert size(good, opts=ch._opts(0, 0, 0, window=4)) == 0
+    assert size(good, opts=ch._opts(0, 0, 0, sampling=ch.UNIFORM)) == 0
+    # the slots are sized for the largest cloud in either direction
+    assert size(offs(0, 5, 9, 3000)) > size(offs(0, 5, 9, 30))
+    assert call(good, k=0) == -1
+    assert call(good, k=4) == -1                # k > m
+    assert call(offs(0, 5, 5, 9)) == -1
+    assert call(good, A=None) == -1
+    assert call(good, ws_bytes=size(good) - 1) == -2
+
+
 def test_server_argument_errors_are_host_side():
     lib = ch.lib()
     h = ctypes.c_void_p()

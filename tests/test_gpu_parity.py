@@ -437,3 +437,58 @@ def test_lowp_l1_ignores_precision(ch, orc):
     _, rmin, rnn = ch.chamfer_exact(dev(A), dev(B), 1, precision=1)
     m32, a32 = orc.nn_f32(A, B, 1)
     assert np.array_equal(host(rnn), a32)
+
+
+# ------------------------------------------------------------ retrieval ---
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_retrieval_parity(ch, orc, metric):
+    """One-vs-many retrieval over 70 clouds (140 jobs: three batches, the
+    last ragged): every symmetric estimate as the oracle's and bit-identical
+    to the direct symmetric call; the top-k as the oracle's, ranked by exact
+    CH; k = m gives the brute-force ranking and puts the source cloud first."""
+    banner(f"retrieval metric={metric}")
+    cl, qs, src = workloads.retrieval_collection(seed=21 + metric, m=70, n_min=50, n_max=300,
+                                                 queries=2)
+    for q, s in zip(qs, src):
+        est, top, vals = ch.chamfer_retrieve(dev(q), [dev(B) for B in cl], metric, 0.2, 50, 7, 5,
+                                             n_scales=3)
+        r_est, r_top, r_vals = orc.retrieve(q, cl, metric, 0.2, 50, 7, 5, n_scales=3)
+        e = host(est)
+        np.testing.assert_allclose(e, r_est, rtol=REL, atol=0)
+        assert top == r_top
+        np.testing.assert_allclose(vals, r_vals, rtol=REL, atol=0)
+        for i in (0, 33, 69):
+            direct = host(ch.chamfer_estimate_symmetric(dev(q), dev(cl[i]), metric, 0.2, 50, 7,
+                                                        n_scales=3))
+            assert e[i] == direct[0]
+        _, top_all, vals_all = ch.chamfer_retrieve(dev(q), [dev(B) for B in cl], metric, 0.2, 50,
+                                                   7, len(cl), n_scales=3)
+        brute = sorted((orc.chamfer_symmetric_exact(q, B, metric)[0], i) for i, B in enumerate(cl))
+        assert top_all[0] == s
+        np.testing.assert_allclose(vals_all, [v for v, _ in brute], rtol=REL, atol=0)
+        assert sorted(top_all) == list(range(len(cl)))
+
+
+def test_retrieval_wide_and_lowp(ch, orc):
+    """d = 64 clouds (MFMA exact passes) of mixed sizes, one much larger
+    than A: estimates as the oracle's; with BF16 the estimates equal the
+    direct BF16 symmetric calls and the re-rank stays exact (float32)."""
+    banner("retrieval d=64")
+    rng = np.random.default_rng(5)
+    A = clouds(400, 1, 64, seed=77)[0]
+    cl = [clouds(1, int(n), 64, seed=78 + j)[1] for j, n in enumerate(rng.integers(20, 3000, 9))]
+    est, top, vals = ch.chamfer_retrieve(dev(A), [dev(B) for B in cl], 2, 0.2, 0, 3, 3)
+    r_est, r_top, r_vals = orc.retrieve(A, cl, 2, 0.2, 0, 3, 3)
+    np.testing.assert_allclose(host(est), r_est, rtol=REL, atol=0)
+    assert top == r_top
+    np.testing.assert_allclose(vals, r_vals, rtol=REL, atol=0)
+    est_b, top_b, vals_b = ch.chamfer_retrieve(dev(A), [dev(B) for B in cl], 2, 0.2, 0, 3, 3,
+                                               precision=1)
+    e = host(est_b)
+    for i in range(len(cl)):
+        direct = host(ch.chamfer_estimate_symmetric(dev(A), dev(cl[i]), 2, 0.2, 0, 3,
+                                                    precision=1))
+        assert e[i] == direct[0], i
+    for i, v in zip(top_b, vals_b):
+        np.testing.assert_allclose(v, orc.chamfer_symmetric_exact(A, cl[i], 2)[0], rtol=REL)

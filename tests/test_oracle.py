@@ -617,3 +617,18 @@ def test_symmetric_exact(orc, metric):
     e_tot, e_ab, e_ba = orc.chamfer_symmetric_estimate(A, B, metric, 0.2, 2000, 4)
     assert e_tot == e_ab + e_ba
     assert e_tot == pytest.approx(tot, rel=0.05)
+
+
+def test_retrieval_composition(orc):
+    """Retrieval with k = m re-ranks every cloud exactly, so it returns the
+    brute-force ranking; a resample of a member is retrieved first."""
+    clouds, queries, src = workloads.retrieval_collection(seed=3, m=12, n_min=60, n_max=120,
+                                                          queries=2)
+    for q, s in zip(queries, src):
+        est, top, vals = orc.retrieve(q, clouds, 1, 0.2, 50, 7, len(clouds), n_scales=3)
+        brute = sorted((orc.chamfer_symmetric_exact(q, B, 1)[0], i) for i, B in enumerate(clouds))
+        assert top == [i for _, i in brute] and vals == [v for v, _ in brute]
+        assert top[0] == s
+        est3, top3, _ = orc.retrieve(q, clouds, 1, 0.2, 50, 7, 3, n_scales=3)
+        assert np.array_equal(est3, est) and len(top3) == 3
+        assert top3 == sorted(top3, key=lambda i: orc.chamfer_symmetric_exact(q, clouds[i], 1)[0])

@@ -156,6 +156,60 @@ def surface_pair(rng: np.random.Generator, n_a: int, n_b: int):
     return _f32(a), _f32(b)
 
 
+def _jittered_pair(rng: np.random.Generator, base, jitter: float, n: int):
+    """Two samples of size n of the base surface (kind, parameters, rotation)
+    with every shape parameter scaled by an independent 1 + jitter N(0, 1)."""
+    kind, params, rot = base
+    p = params * (1.0 + jitter * rng.standard_normal(params.shape))
+
+    def draw(m):
+        if kind == 0:
+            th = rng.uniform(0.0, math.pi, size=m)
+            ph = rng.uniform(0.0, 2 * math.pi, size=m)
+            return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph),
+                             np.cos(th)], axis=1) * p
+        u = rng.uniform(0.0, 2 * math.pi, size=m)
+        v = rng.uniform(0.0, 2 * math.pi, size=m)
+        return np.stack([(p[0] + p[1] * np.cos(v)) * np.cos(u),
+                         (p[0] + p[1] * np.cos(v)) * np.sin(u), p[1] * np.sin(v)], axis=1)
+
+    a = draw(n) @ rot.T + 0.01 * rng.standard_normal((n, 3))
+    b = draw(n) @ rot.T + 0.01 * rng.standard_normal((n, 3))
+    return _f32(a), _f32(b)
+
+
+def retrieval_collection(seed: int = 42, m: int = 1000, n_min: int = 1000, n_max: int = 4000,
+                         queries: int = 20, family: int = 1, jitter: float = 0.0):
+    """A collection of m d=3 surface clouds (sizes uniform in [n_min, n_max])
+    and `queries` query clouds, each an independent resample (same surface,
+    same size) of a distinct member; returns (clouds, queries, source ids).
+    family = 1: every member is its own random surface (as surface_pair).
+    family > 1: members come in consecutive groups of `family` sharing one
+    base surface (ellipsoid or torus, rotation) whose parameters each member
+    scales by 1 + jitter N(0, 1): near neighbours that the estimate has to
+    tell apart."""
+    rng = np.random.default_rng(seed)
+    src = rng.choice(m, size=queries, replace=False)
+    slot = {int(s): q for q, s in enumerate(src)}
+    clouds, qs = [], [None] * queries
+    base = None
+    for i in range(m):
+        n = int(rng.integers(n_min, n_max + 1))
+        if family <= 1:
+            a, b = surface_pair(rng, n, n)
+        else:
+            if i % family == 0:
+                kind = int(rng.integers(0, 2))
+                params = (rng.uniform(0.5, 2.0, size=3) if kind == 0 else
+                          np.array([rng.uniform(1.0, 2.0), rng.uniform(0.2, 0.5)]))
+                base = (kind, params, _rotation(rng))
+            a, b = _jittered_pair(rng, base, jitter, n)
+        clouds.append(a)
+        if i in slot:
+            qs[slot[i]] = b
+    return clouds, qs, src.astype(np.int64)
+
+
 @dataclass
 class Request:
     rid: int
