@@ -99,6 +99,11 @@ def lib():
                              ctypes.POINTER(ctypes.c_uint64)]
     L.or_weights.restype = _INT
     L.or_sample.argtypes = [ctypes.c_uint64, _U64, _I64, ctypes.c_uint64, _I64, _I32]
+    L.or_sketch_direction.argtypes = [ctypes.c_uint64, _INT, _INT, _F64]
+    L.or_project.argtypes = [_F32, _I64, _INT, _F64, _F64]
+    L.or_part_tables.argtypes = [ctypes.c_uint64, _INT, _F32, _U64]
+    L.or_part_keys.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _INT, _F32, _U64, _U64]
+    L.or_pad.argtypes = [_F32, _I64, _INT, _INT, _INT, ctypes.c_uint64, ctypes.c_float, _F32]
     _lib = L
     return L
 
@@ -356,3 +361,178 @@ def retrieve(A, clouds, metric, eps, T, seed, k, **kw):
     cand = sorted(range(len(clouds)), key=lambda i: (est[i], i))[:k]
     ranked = sorted((chamfer_symmetric_exact(A, clouds[i], metric)[0], i) for i in cand)
     return est, [i for _, i in ranked], [v for v, _ in ranked]
+
+
+# --------------------------------------------------------------------------
+# Reduction to bounded aspect ratio (lemma on the reduction to poly(n/eps)
+# aspect ratio; its proof in the appendix: very crude estimate from a
+# p-stable 1-D sketch, a coarse grid partition, appended random coordinates)
+# --------------------------------------------------------------------------
+
+REDUCE_NONE = 0
+REDUCE_PARTITION = 1
+REDUCE_PAD = 2
+
+
+def ceil_log2(x: int) -> int:
+    """Smallest k >= 0 with 2^k >= x (x >= 1)."""
+    return max(0, (int(x) - 1).bit_length())
+
+
+def sketch_direction(seed: int, d: int, metric: int) -> np.ndarray:
+    """p-stable vector g: i.i.d. Cauchy entries for l1, Gaussian for l2."""
+    g = np.zeros(d, np.float64)
+    lib().or_sketch_direction(seed, d, metric, g)
+    return g
+
+
+def project(X, g) -> np.ndarray:
+    """<x, g> per row, double precision, fused multiply-adds in ascending
+    coordinate order."""
+    X = _f32(X)
+    p = np.zeros(X.shape[0], np.float64)
+    lib().or_project(X, X.shape[0], X.shape[1], np.ascontiguousarray(g, np.float64), p)
+    return p
+
+
+def nearest_1d(pa, pb) -> np.ndarray:
+    """t_a = min_b |pa - pb| by sorting pb and looking at the neighbours of
+    each pa (the 1-D nearest-neighbour search of the proof); every
+    difference is one IEEE subtraction."""
+    s = np.sort(np.asarray(pb, np.float64))
+    i = np.searchsorted(s, pa, side="left")
+    t = np.full(len(pa), np.inf)
+    has_succ = i < len(s)
+    t[has_succ] = s[i[has_succ]] - pa[has_succ]
+    has_pred = i > 0
+    pred = pa[has_pred] - s[i[has_pred] - 1]
+    t[has_pred] = np.minimum(t[has_pred], pred)
+    return t
+
+
+def reduce_bounds(n_a: int, n_b: int, eps: float, max_t: float) -> dict:
+    """Exponents and bounds from M = max_a t_a (one reading of the proof's
+    constants, all powers of two so that both implementations agree):
+
+    with n = max(n_A, n_B), a p-stable g' satisfies |g'| < t with probability
+    at most t and |g'| > t with probability below 1/t (Cauchy; the Gaussian
+    tail is lighter), so with probability at least 1 - 2/n
+      k_hi = ceil(log2 n_A) + ceil(log2 n)                   (|g'| <= 2^k_hi)
+      k_lo = ceil(log2 n_A) + ceil(log2 n_B) + ceil(log2 n)  (|g'| >= 2^-k_lo)
+    give  eta_lo = 2^(e_M - k_hi) <= CH(A, B) <= eta_hi
+                 = 2^(e_M + 1 + ceil(log2 n_A) + k_lo),  e_M = floor(log2 M).
+    c = eta_hi / eta_lo; the partition side is 2^e_part >= c n eta_hi; the
+    padding adds m = 3 ceil(log2 n) coordinates of magnitude
+    q = eps eta_lo / (2 n m) (l1 norm of the padding vector eps eta_lo / (2n)).
+    M = 0 (every a on top of a b in the projection): no partition, q = 0."""
+    n = max(n_a, n_b, 2)
+    la, lb, ln = ceil_log2(n_a), ceil_log2(n_b), ceil_log2(n)
+    k_hi = la + ln
+    k_lo = la + lb + ln
+    m = 3 * ln
+    if not max_t > 0.0:
+        return dict(degenerate=True, e_M=0, k_hi=k_hi, k_lo=k_lo, e_part=0, m=m,
+                    eta_lo=0.0, eta_hi=0.0, q=np.float32(0.0))
+    e_M = math.frexp(max_t)[1] - 1
+    e_hi = e_M + 1 + la + k_lo
+    log2c = e_hi - (e_M - k_hi)
+    e_part = log2c + ln + e_hi
+    q = np.float32(math.ldexp(eps / float(2 * n * m), e_M - k_hi))
+    return dict(degenerate=False, e_M=e_M, k_hi=k_hi, k_lo=k_lo, e_part=e_part, m=m,
+                eta_lo=math.ldexp(1.0, e_M - k_hi), eta_hi=math.ldexp(1.0, e_hi), q=q)
+
+
+def part_tables(seed: int, kh: int):
+    z = np.zeros(kh, np.float32)
+    m = np.zeros(kh, np.uint64)
+    lib().or_part_tables(seed, kh, z, m)
+    return z, m
+
+
+def part_keys(X, metric, lo, Zs, e, zfrac, mult) -> np.ndarray:
+    """Key of every point's cell of side 2^e (see or_part_keys)."""
+    X = _f32(X)
+    n, d = X.shape
+    keys = np.zeros(n, np.uint64)
+    ke = 0 if Zs is None else Zs.shape[0]
+    zp = None if Zs is None else Zs.ctypes.data
+    lib().or_part_keys(X, n, d, metric, lo, zp, ke, e, zfrac, mult, keys)
+    return keys
+
+
+def pad(X, m: int, side: int, seed: int, q) -> np.ndarray:
+    """X with m appended coordinates +-q (signs from the counter (row, side,
+    PAD))."""
+    X = _f32(X)
+    n, d = X.shape
+    out = np.zeros((n, d + m), np.float32)
+    lib().or_pad(X, n, d, m, side, seed, np.float32(q), out)
+    return out
+
+
+def aspect_reduce(A, B, metric, eps, seed, embed_dim=DEFAULT_EMBED_DIM):
+    """The reduction's steps: g, projections, t_a, their sum (the 1-D
+    Chamfer distance, a poly(n)-approximation of CH) and maximum, the bounds
+    and exponents, and the partition keys of A and B (cells of side
+    2^e_part of the grid hash on the hashed coordinates: x - lo for l1, the
+    l2 -> l1 embedding for l2)."""
+    A, B = _f32(A), _f32(B)
+    d = A.shape[1]
+    g = sketch_direction(seed, d, metric)
+    pa, pb = project(A, g), project(B, g)
+    t = nearest_1d(pa, pb)
+    max_t = float(t.max()) if len(t) else 0.0
+    out = reduce_bounds(A.shape[0], B.shape[0], eps, max_t)
+    out.update(g=g, pa=pa, pb=pb, t=t, max_t=max_t, ch1=math.fsum(t.tolist()))
+    lo, _, _, _ = calibrate(A, B)
+    Zs = embedding(seed, d, embed_dim) if metric == L2 else None
+    kh = d if metric == L1 else Zs.shape[0]
+    zf, mt = part_tables(seed, kh)
+    if out["degenerate"]:
+        out["keys_A"] = np.zeros(A.shape[0], np.uint64)
+        out["keys_B"] = np.zeros(B.shape[0], np.uint64)
+    else:
+        out["keys_A"] = part_keys(A, metric, lo, Zs, out["e_part"], zf, mt)
+        out["keys_B"] = part_keys(B, metric, lo, Zs, out["e_part"], zf, mt)
+    return out
+
+
+def parts(keys_A, keys_B):
+    """The partition as lists of row indices per part, parts in ascending
+    key order, rows ascending; None when some part of A has no point of B
+    (the event the proof bounds by 1/n: the partition is then not used)."""
+    ka = np.asarray(keys_A)
+    kb = np.asarray(keys_B)
+    out = []
+    for k in np.unique(ka):
+        ra = np.nonzero(ka == k)[0]
+        rb = np.nonzero(kb == k)[0]
+        if len(rb) == 0:
+            return None
+        out.append((ra, rb))
+    return out
+
+
+def chamfer_estimate_reduced(A, B, metric, eps, T, seed, reduction=REDUCE_PARTITION,
+                             embed_dim=DEFAULT_EMBED_DIM, **kw):
+    """The estimator applied after the reduction: partition A and B, pad
+    (reduction = REDUCE_PAD: both sets get the m coordinates +-q before the
+    estimate, rows keyed by their index in A or B), and sum the estimates
+    of the parts in ascending key order (a trivial or unusable partition is
+    one part: the plain estimate of the, possibly padded, sets)."""
+    A, B = _f32(A), _f32(B)
+    if A.shape[0] == 0:
+        return dict(eta=0.0, parts=0, info=None)
+    info = aspect_reduce(A, B, metric, eps, seed, embed_dim)
+    if reduction == REDUCE_PAD:
+        A = pad(A, info["m"], 0, seed, info["q"])
+        B = pad(B, info["m"], 1, seed, info["q"])
+    pl = parts(info["keys_A"], info["keys_B"])
+    if pl is None or len(pl) == 1:
+        r = chamfer_estimate(A, B, metric, eps, T, seed, embed_dim=embed_dim, **kw)
+        return dict(eta=r["eta"], parts=1, info=info)
+    eta = 0.0
+    for ra, rb in pl:
+        eta += chamfer_estimate(A[ra], B[rb], metric, eps, T, seed, embed_dim=embed_dim,
+                                **kw)["eta"]
+    return dict(eta=eta, parts=len(pl), info=info)

@@ -509,3 +509,98 @@ void or_sample(uint64_t seed, const uint64_t *P, int64_t nA, uint64_t W, int64_t
         idx[l] = (int32_t)lo;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Reduction to bounded aspect ratio (lemma on the reduction to poly(n/eps)  */
+/* aspect ratio and its proof in the appendix).                             */
+/*                                                                          */
+/* p-stable direction g (d doubles) from the counter (j, 0, SKETCH):       */
+/*   l1: Cauchy  g_j = tan(pi (u - 1/2)),  u = ((w0 >> 11) + 1/2) 2^-53     */
+/*   l2: Gaussian, Box-Muller as the embedding: u1 = ((w0>>11)+1) 2^-53,    */
+/*       u2 = (w1 >> 11) 2^-53, g_j = sqrt(-2 ln u1) cos(2 pi u2).          */
+/* ------------------------------------------------------------------------ */
+#define PURPOSE_SKETCH 4u
+#define PURPOSE_PART 5u
+#define PURPOSE_PAD 6u
+
+void or_sketch_direction(uint64_t seed, int d, int metric, double *g)
+{
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < d; ++j) {
+        uint64_t w[4];
+        draw(seed, (uint64_t)j, 0, PURPOSE_SKETCH, w);
+        if (metric == OR_L1) {
+            double u = ldexp((double)(w[0] >> 11) + 0.5, -53);
+            g[j] = tan(pi * (u - 0.5));
+        } else {
+            double u1 = ldexp((double)((w[0] >> 11) + 1), -53);
+            double u2 = ldexp((double)(w[1] >> 11), -53);
+            g[j] = sqrt(-2.0 * log(u1)) * cos(2.0 * pi * u2);
+        }
+    }
+}
+
+/* p_i = <x_i, g> in double: acc = fma((double) x_ij, g_j, acc), j ascending
+ * from acc = 0. */
+void or_project(const float *X, int64_t n, int d, const double *g, double *p)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) acc = fma((double)X[(size_t)i * d + j], g[j], acc);
+        p[i] = acc;
+    }
+}
+
+/* Partition grid (one scale): z'_k = (w0 >> 40) 2^-24, M_k = w1 | 1 from the
+ * counter (k, 0, PART). */
+void or_part_tables(uint64_t seed, int kh, float *zfrac, uint64_t *mult)
+{
+    for (int k = 0; k < kh; ++k) {
+        uint64_t w[4];
+        draw(seed, (uint64_t)k, 0, PURPOSE_PART, w);
+        zfrac[k] = ldexpf((float)(w[0] >> 40), -24);
+        mult[k] = w[1] | 1ull;
+    }
+}
+
+/* Partition key of every point at cell side 2^e: the hashed coordinates y
+ * as for the bucket keys (float), then in double
+ *   cell_k = ceil(ldexp((double) y_k, -e) + (double) z'_k),
+ * clamped to [-2^62, 2^62] (0 when y_k is NaN), and
+ *   key = (sum_k (uint64) (int64) cell_k * M_k mod 2^64) >> 1. */
+void or_part_keys(const float *X, int64_t n, int d, int metric, const float *lo,
+                  const float *Zs, int ke, int e, const float *zfrac, const uint64_t *mult,
+                  uint64_t *keys)
+{
+    int kh = metric == OR_L1 ? d : ke;
+    float *y = (float *)malloc(sizeof(float) * (size_t)kh);
+    const double lim = ldexp(1.0, 62);
+    for (int64_t p = 0; p < n; ++p) {
+        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
+        uint64_t acc = 0;
+        for (int k = 0; k < kh; ++k) {
+            double c = ceil(ldexp((double)y[k], -e) + (double)zfrac[k]);
+            if (c != c) c = 0.0;
+            if (c > lim) c = lim;
+            if (c < -lim) c = -lim;
+            acc += (uint64_t)(int64_t)c * mult[k];
+        }
+        keys[p] = acc >> 1;
+    }
+    free(y);
+}
+
+/* Padded copy: row i of X (n x d) followed by m coordinates +-q, the sign of
+ * coordinate j being bit (j mod 64) of word j / 64 of the block at the
+ * counter (i, side, PAD) (set bit: -q).  side is 0 for A and 1 for B. */
+void or_pad(const float *X, int64_t n, int d, int m, int side, uint64_t seed, float q,
+            float *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t w[4];
+        draw(seed, (uint64_t)i, (uint64_t)side, PURPOSE_PAD, w);
+        float *o = out + (size_t)i * (d + m);
+        for (int j = 0; j < d; ++j) o[j] = X[(size_t)i * d + j];
+        for (int j = 0; j < m; ++j) o[d + j] = ((w[j / 64] >> (j % 64)) & 1u) ? -q : q;
+    }
+}

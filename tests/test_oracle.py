@@ -632,3 +632,140 @@ def test_retrieval_composition(orc):
         est3, top3, _ = orc.retrieve(q, clouds, 1, 0.2, 50, 7, 3, n_scales=3)
         assert np.array_equal(est3, est) and len(top3) == 3
         assert top3 == sorted(top3, key=lambda i: orc.chamfer_symmetric_exact(q, clouds[i], 1)[0])
+
+
+# ------------------------------------------ reduction to bounded aspect ratio
+
+def test_sketch_direction_is_p_stable(orc):
+    """<v, g> / |v|_p has the p-stable law: |Cauchy| has median 1 (l1), a
+    standard normal has second moment 1 (l2).  A Gaussian g in l1 (median
+    0.674 |v|_2 = 0.30 |v|_1 here) or a wrong scale fails."""
+    v = np.array([1.0, -2.0, 0.5, 3.0, 1.5])
+    r1 = [abs(float(orc.sketch_direction(s, 5, 1) @ v)) / np.abs(v).sum() for s in range(4000)]
+    assert abs(np.median(r1) - 1.0) < 0.1
+    r2 = [float(orc.sketch_direction(s, 5, 2) @ v) ** 2 / float(v @ v) for s in range(4000)]
+    assert abs(np.mean(r2) - 1.0) < 0.1
+    g = orc.sketch_direction(3, 1000, 1)
+    assert abs(np.mean(np.abs(g) < 1.0) - 0.5) < 0.05          # P(|C| < 1) = 1/2
+
+
+def test_projection_and_nearest_1d(orc):
+    """Projections agree with a float64 matrix product; the sorted-search
+    t_a equals the brute-force min_b |pa - pb| bit for bit, also with ties
+    and duplicates."""
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((300, 17)).astype(np.float32)
+    g = orc.sketch_direction(5, 17, 1)
+    p = orc.project(X, g)
+    ref = X.astype(np.float64) @ g
+    assert np.all(np.abs(p - ref) <= 1e-12 * (np.abs(X).astype(np.float64) @ np.abs(g)))
+    pa = rng.integers(-20, 20, 200).astype(np.float64) * 0.25
+    pb = rng.integers(-20, 20, 50).astype(np.float64) * 0.25
+    pa = np.concatenate([pa, [-100.0, 100.0, pb[0]]])
+    brute = np.abs(pa[:, None] - pb[None, :]).min(axis=1)
+    assert np.array_equal(orc.nearest_1d(pa, pb), brute)
+    pa, pb = rng.standard_normal(500), rng.standard_normal(77)
+    assert np.array_equal(orc.nearest_1d(pa, pb), np.abs(pa[:, None] - pb[None, :]).min(axis=1))
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_reduce_bounds_bracket_ch(orc, metric):
+    """eta_lo <= CH(A, B) <= eta_hi on varied instances and seeds, the
+    partition side is at least c n eta_hi, and the sum of t_a (the 1-D
+    Chamfer distance) lies within the poly(n) band as well."""
+    rng = np.random.default_rng(metric)
+    for case in range(12):
+        n_a, n_b = (int(x) for x in rng.integers(2, 400, size=2))
+        d = int(rng.integers(1, 20))
+        A, B = workloads.uniform_cube(case, n_a, n_b, d, lo=-float(10 ** case % 7 + 1), hi=3.0)
+        ch = orc.chamfer_exact(A, B, metric)[0]
+        r = orc.aspect_reduce(A, B, metric, 0.2, 100 + case)
+        assert not r["degenerate"]
+        assert r["eta_lo"] <= ch <= r["eta_hi"], (case, r["eta_lo"], ch, r["eta_hi"])
+        assert r["eta_lo"] <= r["ch1"] * 2.0 ** r["k_lo"] and ch <= r["ch1"] * 2.0 ** r["k_lo"]
+        n = max(n_a, n_b)
+        assert 2.0 ** r["e_part"] >= (r["eta_hi"] / r["eta_lo"]) * n * r["eta_hi"]
+        assert r["m"] == 3 * orc.ceil_log2(n)
+
+
+def test_part_keys_match_exact_arithmetic(orc):
+    """Partition keys (l1) equal the cell formula evaluated in exact
+    rational arithmetic, at a side small enough for many cells."""
+    from fractions import Fraction
+    rng = np.random.default_rng(4)
+    X = (rng.standard_normal((200, 4)) * 50).astype(np.float32)
+    lo = X.min(axis=0)
+    zf, mt = orc.part_tables(9, 4)
+    for e in (-3, 0, 4, 9):
+        keys = orc.part_keys(X, 1, lo, None, e, zf, mt)
+        for p in range(0, 200, 7):
+            acc = 0
+            for k in range(4):
+                y = np.float32(X[p, k]) - np.float32(lo[k])      # float32 subtraction
+                c = math.ceil(Fraction(float(y)) / Fraction(2) ** e + Fraction(float(zf[k])))
+                acc = (acc + (c % 2 ** 64) * int(mt[k])) % 2 ** 64
+            assert int(keys[p]) == acc >> 1, (e, p)
+
+
+def test_partition_splits_far_groups(orc):
+    """Two groups 1e30 apart with neighbours 0.5 and 1e20 inside them (1e20
+    is 2^-33 of the group's magnitude: the double-precision projection still
+    resolves it): the partition separates them, every part of A has points
+    of B, and the sum of the parts' exact Chamfer distances is CH(A, B); the
+    reduced estimate is the sum of the parts' estimates (here exact: every
+    part's D_a is its true nearest distance)."""
+    A = np.array([[0, 0], [1, 0], [1e30, 0]], np.float32)
+    B = np.array([[0.5, 0], [1.5, 0], [1e30, 1e20]], np.float32)
+    ch = orc.chamfer_exact(A, B, 1)[0]
+    split = 0
+    for seed in range(8):
+        r = orc.aspect_reduce(A, B, 1, 0.2, seed)
+        pl = orc.parts(r["keys_A"], r["keys_B"])
+        assert pl is not None
+        if len(pl) == 2:
+            split += 1
+            assert sum(orc.chamfer_exact(A[ra], B[rb], 1)[0] for ra, rb in pl) == ch
+            est = orc.chamfer_estimate_reduced(A, B, 1, 0.2, 50, seed)
+            assert est["parts"] == 2
+            assert est["eta"] == pytest.approx(ch, rel=1e-12)
+    assert split >= 6
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_padding_properties(orc, metric):
+    """Padding: every appended vector has l1 norm m q, signs are fair, rows
+    with different sign vectors are at least 2q apart, and CH(A', B') lies
+    in [CH, CH + 2 m q n_A] (l1; sqrt(m) for l2), within (1 + eps) CH at
+    the reduction's q."""
+    A, B = workloads.clusters_l2(seed=5, n=500, d=8, k=5, n_b=400)
+    r = orc.aspect_reduce(A, B, metric, 0.2, 11)
+    m, q = r["m"], float(r["q"])
+    Ap, Bp = orc.pad(A, m, 0, 11, r["q"]), orc.pad(B, m, 1, 11, r["q"])
+    assert np.array_equal(Ap[:, :8], A) and np.array_equal(Bp[:, :8], B)
+    V = Ap[:, 8:].astype(np.float64)
+    assert np.all(np.abs(V) == q) and np.allclose(np.abs(V).sum(axis=1), m * q)
+    assert abs(np.mean(V < 0) - 0.5) < 0.02
+    signs = {tuple(row) for row in (V < 0)}
+    assert len(signs) == len(V)
+    ch = orc.chamfer_exact(A, B, metric)[0]
+    chp = orc.chamfer_exact(Ap, Bp, metric)[0]
+    slack = 2 * q * (m if metric == 1 else math.sqrt(m)) * A.shape[0]
+    assert ch <= chp <= ch + slack
+    assert chp <= (1 + 0.2) * ch
+    # a large q makes the bound tight enough to see
+    Ap, Bp = orc.pad(A, m, 0, 11, 1.0), orc.pad(B, m, 1, 11, 1.0)
+    assert orc.chamfer_exact(Ap, Bp, 1)[0] > ch + A.shape[0]
+
+
+def test_reduced_estimate_trivial_and_degenerate(orc):
+    """An ordinary instance has one part: the partition-only reduction is
+    the plain estimate; A inside B gives M = 0 (no partition, q = 0) and
+    eta = 0."""
+    A, B = workloads.clusters_l2(seed=6, n=700, d=16, k=7, n_b=900)
+    for metric in (1, 2):
+        red = orc.chamfer_estimate_reduced(A, B, metric, 0.2, 0, 3, orc.REDUCE_PARTITION)
+        assert red["parts"] == 1
+        assert red["eta"] == orc.chamfer_estimate(A, B, metric, 0.2, 0, 3)["eta"]
+    r = orc.aspect_reduce(B[:100], B, 1, 0.2, 3)
+    assert r["degenerate"] and r["max_t"] == 0.0 and r["q"] == 0.0
+    assert orc.chamfer_estimate_reduced(B[:100], B, 1, 0.2, 0, 3, orc.REDUCE_PAD)["eta"] == 0.0
