@@ -443,6 +443,64 @@ def sampling_report(args, ch, torch, workloads):
     return {"sampling_report": out}
 
 
+def reduction_report(args, ch, torch, workloads):
+    """The reduction to bounded aspect ratio: its bounds against the exact
+    CH, the number of parts, the time of the reduction itself (sketch,
+    sort, 1-D search, partition keys; padded copies) and of the estimate
+    plain / after the partition / on the padded sets, with the error of each
+    estimate over REDUCTION_SEEDS seeds."""
+    cases = [("clusters l2 |A|=|B|=100000 d=128", "clusters_l2", dict(n=100_000, d=128, k=1000),
+              2, 0.2),
+             ("mixed l1 |A|=|B|=1000000 d=64", "mixed_l1", dict(), 1, 0.2),
+             ("surface pair l1 |A|=|B|=200000 d=3", None, None, 1, 0.2)]
+    out = []
+    for name, gen, kw, metric, eps in cases:
+        if gen is None:
+            A, B = workloads.surface_pair(np.random.default_rng(args.seed), 200_000, 200_000)
+        else:
+            A, B = getattr(workloads, gen)(seed=args.seed, **kw)
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        exact = float(ch.chamfer_exact(At, Bt, metric, rows_out=False)[0].item())
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps * 1e3
+
+        red = ch.chamfer_aspect_reduce(At, Bt, metric, eps, 1)
+        info = red["info"]
+        ka = red["keys_A"].cpu().numpy()
+        kb = red["keys_B"].cpu().numpy()
+        parts = len(np.unique(np.concatenate([ka, kb])))
+        row = {"case": name, "CH": exact, "eta_lo": info["eta_lo"], "eta_hi": info["eta_hi"],
+               "ch1": info["ch1"], "e_part": info["e_part"], "pad_dims": info["pad_dims"],
+               "pad_value": info["pad_value"], "parts": parts,
+               "ms_reduce": timed(lambda: ch.chamfer_aspect_reduce(At, Bt, metric, eps, 1)),
+               "ms_reduce_pad": timed(lambda: ch.chamfer_aspect_reduce(At, Bt, metric, eps, 1,
+                                                                      pad=True))}
+        for label, red_mode in (("plain", 0), ("partition", 1), ("pad", 2)):
+            row[f"ms_{label}"] = timed(lambda: ch.chamfer_estimate(
+                At, Bt, metric, eps, 0, 1, reduction=red_mode, with_aux=False))
+            errs = [abs(float(ch.chamfer_estimate(At, Bt, metric, eps, 0, 100 + s,
+                                                  reduction=red_mode, with_aux=False)
+                              ["eta"].item()) - exact) / exact
+                    for s in range(REDUCTION_SEEDS)]
+            row[f"rms_err_{label}"] = float(np.sqrt(np.mean(np.square(errs))))
+        out.append(row)
+        print(f"[bench] {name}: parts {parts}, reduce {row['ms_reduce']:.3f} ms, estimate "
+              f"plain/partition/pad {row['ms_plain']:.3f}/{row['ms_partition']:.3f}/"
+              f"{row['ms_pad']:.3f} ms, rms err {row['rms_err_plain']:.4f}/"
+              f"{row['rms_err_partition']:.4f}/{row['rms_err_pad']:.4f}",
+              file=sys.stderr, flush=True)
+        del At, Bt
+    return {"reduction_report": {"seeds": REDUCTION_SEEDS, "cases": out}}
+
+
+REDUCTION_SEEDS = 10
 RETRIEVAL_K = (1, 5, 10, 30)
 RETRIEVAL_SETS = (("distinct surfaces", 1, 0.0), ("families of 10, 2% jitter", 10, 0.02))
 
@@ -528,6 +586,9 @@ def main():
     ap.add_argument("--sampling-report", action="store_true",
                     help="importance vs uniform sampling: error vs T over seeds and the time "
                          "to reach 2%% / 1%% on three synthetic cases")
+    ap.add_argument("--reduction-report", action="store_true",
+                    help="reduction to bounded aspect ratio: bounds, parts, time of the "
+                         "reduction and of the estimate with it, errors over seeds")
     ap.add_argument("--retrieval-report", action="store_true",
                     help="one-vs-many retrieval over 1000 clouds: recall@k and time vs "
                          "brute force")
@@ -567,6 +628,9 @@ def main():
         return
     if args.sampling_report:
         print(json.dumps(sampling_report(args, ch, torch, workloads)))
+        return
+    if args.reduction_report:
+        print(json.dumps(reduction_report(args, ch, torch, workloads)))
         return
     if args.retrieval_report:
         print(json.dumps(retrieval_report(args, ch, torch, workloads)))

@@ -75,8 +75,17 @@ typedef struct chamfer_opts {
                            0 => 1 (the first colliding point)                  */
     int32_t reps;       /* k independent LSH structures, 1..64; 0 => 1       */
     int32_t sampling;   /* enum chamfer_sampling; 0 => importance             */
-    int32_t reserved;   /* must be 0                                          */
+    int32_t reduction;  /* enum chamfer_reduction_mode, chamfer_estimate only;
+                           0 => none                                          */
 } chamfer_opts;
+
+/* Reduction to bounded aspect ratio before the estimate (the lemma on
+ * reducing to poly(n/eps) aspect ratio and its proof in the appendix). */
+enum chamfer_reduction_mode {
+    CHAMFER_REDUCE_NONE = 0,
+    CHAMFER_REDUCE_PARTITION = 1, /* crude bounds, coarse partition, sum of parts */
+    CHAMFER_REDUCE_PAD = 2        /* the same, on copies with appended coordinates */
+};
 
 /* Optional device outputs of chamfer_estimate; any field may be NULL. */
 typedef struct chamfer_aux {
@@ -109,6 +118,67 @@ typedef struct chamfer_aux {
  */
 size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric,
                                double eps, int64_t T, const chamfer_opts *opts);
+
+/*
+ * Reduction to bounded aspect ratio (lemma on the reduction to poly(n/eps)
+ * aspect ratio; its proof in the appendix), the steps of
+ * chamfer_aspect_reduce:
+ *  1. a p-stable direction g (l1: Cauchy, l2: Gaussian entries; Philox
+ *     purpose 4, counter (j, 0)), drawn on the host in double precision;
+ *  2. projections p_x = <x, g> in double (fused multiply-adds, coordinates
+ *     ascending);
+ *  3. t_a = min_b |p_a - p_b| (1-D nearest neighbour: B's projections
+ *     sorted, a binary search per a), M = max_a t_a and ch1 = sum_a t_a, the
+ *     1-D Chamfer distance (a poly(n)-approximation of CH);
+ *  4. with n = max(n_A, n_B), lA = ceil(log2 n_A), lB, ln likewise,
+ *     k_hi = lA + ln, k_lo = lA + lB + ln and e_M = floor(log2 M):
+ *     eta_lo = 2^(e_M - k_hi) <= CH(A, B) <= eta_hi = 2^(e_M + 1 + lA + k_lo)
+ *     with probability >= 1 - 2/n; the partition side 2^e_part with
+ *     e_part = log2(eta_hi / eta_lo) + ln + log2(eta_hi) (>= c n eta_hi);
+ *     m padding coordinates of value +-q, q = eps eta_lo / (2 n m), where m
+ *     is at least 3 ln, rounded up so that d + m is the next of 16, 32, 64,
+ *     128 (a multiple of 16 above 128);
+ *     M = 0 (every a on a b in projection) is "degenerate": no partition,
+ *     q = 0;
+ *  5. partition keys: the grid hash of side 2^e_part on the hashed
+ *     coordinates (x - lo for l1, the l2 -> l1 embedding for l2; shifts and
+ *     multipliers from Philox purpose 5, counter (k, 0)), cells computed in
+ *     double: ceil(ldexp(y, -e_part) + z'), clamped to +-2^62 (0 for NaN),
+ *     key = (sum_k cell_k M_k mod 2^64) >> 1; one_part = every key of A and
+ *     B equal;
+ *  6. padded copies (if asked): row i followed by m values +-q, the sign of
+ *     value j being bit j mod 64 of word j / 64 of the Philox block
+ *     (i, side, 6) (side 0 for A, 1 for B; a set bit gives -q).
+ *   info_out  [1] chamfer_reduction (device).
+ *   t_out     [n_A] double (device) or NULL.
+ *   keys_A_out [n_A], keys_B_out [n_B] uint64 (device) or NULL.
+ *   A_pad_out [n_A, d + m], B_pad_out [n_B, d + m] float (device) or NULL;
+ *   m = chamfer_pad_dims(n_A, n_B, d).
+ * Asynchronous on `stream`.  Workspace: chamfer_reduce_workspace_bytes.
+ * Errors: EINVAL if n_A < 1, n_B < 1, d < 1, metric not 1/2, eps not in
+ * (0, 1) or a bad embedding dimension; EWORKSPACE; EHIP.
+ */
+typedef struct chamfer_reduction {
+    double ch1;          /* sum_a t_a */
+    double max_t;        /* M = max_a t_a */
+    double eta_lo;       /* lower bound of CH(A, B) (a power of two) */
+    double eta_hi;       /* upper bound of CH(A, B) (a power of two) */
+    int32_t e_M;         /* floor(log2 M) */
+    int32_t e_part;      /* partition cells have side 2^e_part */
+    int32_t pad_dims;    /* m */
+    float pad_value;     /* q */
+    int32_t degenerate;  /* M == 0 (or not finite): no partition, q = 0 */
+    int32_t one_part;    /* every partition key of A and B is the same */
+} chamfer_reduction;
+
+int32_t chamfer_pad_dims(int64_t n_A, int64_t n_B, int32_t d);
+size_t chamfer_reduce_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric,
+                                      const chamfer_opts *opts);
+int chamfer_aspect_reduce(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                          int32_t metric, double eps, uint64_t seed, const chamfer_opts *opts,
+                          chamfer_reduction *info_out, double *t_out, uint64_t *keys_A_out,
+                          uint64_t *keys_B_out, float *A_pad_out, float *B_pad_out, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /*
  * Exact Chamfer distance by brute force (definition of CH in the
@@ -160,6 +230,14 @@ int crude_nn(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d
  * use Lemire's bounded integers on Philox4x64-10.  T = 0 selects
  * T = ceil(ceil(log2 n_A) / eps^2).  eta = 0 if n_A = 0 or every D_a = 0.
  *   eta_out [1] double (device).  aux: optional extra outputs (see above).
+ * opts.reduction = CHAMFER_REDUCE_PARTITION / _PAD runs the reduction above
+ * first (with _PAD the estimate runs on the padded copies, d + m
+ * coordinates, d + m <= 2048): if the partition is degenerate, has one
+ * part, or leaves a part of A without points of B (probability <= 1/n), the
+ * estimate is the plain one of the (padded) sets; otherwise it is the sum,
+ * in ascending key order, of the estimates of the parts (rows in ascending
+ * order, the same eps, T, seed and options).  aux must then be NULL, and
+ * the call synchronises the stream once (the host reads the partition).
  * Errors: as crude_nn, plus EINVAL if T < 0.
  */
 int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,

@@ -410,7 +410,22 @@ def nearest_1d(pa, pb) -> np.ndarray:
     return t
 
 
-def reduce_bounds(n_a: int, n_b: int, eps: float, max_t: float) -> dict:
+def pad_dims(n_a: int, n_b: int, d: int) -> int:
+    """Padding coordinates: O(log n) of them, at least 3 ceil(log2 n), with
+    d + m rounded up to the next of 16, 32, 64, 128 (a multiple of 16 above
+    128)."""
+    dp = d + 3 * ceil_log2(max(n_a, n_b, 2))
+    if dp <= 128:
+        w = 16
+        while w < dp:
+            w *= 2
+        dp = w
+    else:
+        dp = -(-dp // 16) * 16
+    return dp - d
+
+
+def reduce_bounds(n_a: int, n_b: int, eps: float, max_t: float, d: int) -> dict:
     """Exponents and bounds from M = max_a t_a (one reading of the proof's
     constants, all powers of two so that both implementations agree):
 
@@ -422,14 +437,14 @@ def reduce_bounds(n_a: int, n_b: int, eps: float, max_t: float) -> dict:
     give  eta_lo = 2^(e_M - k_hi) <= CH(A, B) <= eta_hi
                  = 2^(e_M + 1 + ceil(log2 n_A) + k_lo),  e_M = floor(log2 M).
     c = eta_hi / eta_lo; the partition side is 2^e_part >= c n eta_hi; the
-    padding adds m = 3 ceil(log2 n) coordinates of magnitude
+    padding adds m = pad_dims(n_A, n_B, d) coordinates of magnitude
     q = eps eta_lo / (2 n m) (l1 norm of the padding vector eps eta_lo / (2n)).
     M = 0 (every a on top of a b in the projection): no partition, q = 0."""
     n = max(n_a, n_b, 2)
     la, lb, ln = ceil_log2(n_a), ceil_log2(n_b), ceil_log2(n)
     k_hi = la + ln
     k_lo = la + lb + ln
-    m = 3 * ln
+    m = pad_dims(n_a, n_b, d)
     if not max_t > 0.0:
         return dict(degenerate=True, e_M=0, k_hi=k_hi, k_lo=k_lo, e_part=0, m=m,
                     eta_lo=0.0, eta_hi=0.0, q=np.float32(0.0))
@@ -482,7 +497,7 @@ def aspect_reduce(A, B, metric, eps, seed, embed_dim=DEFAULT_EMBED_DIM):
     pa, pb = project(A, g), project(B, g)
     t = nearest_1d(pa, pb)
     max_t = float(t.max()) if len(t) else 0.0
-    out = reduce_bounds(A.shape[0], B.shape[0], eps, max_t)
+    out = reduce_bounds(A.shape[0], B.shape[0], eps, max_t, d)
     out.update(g=g, pa=pa, pb=pb, t=t, max_t=max_t, ch1=math.fsum(t.tolist()))
     lo, _, _, _ = calibrate(A, B)
     Zs = embedding(seed, d, embed_dim) if metric == L2 else None

@@ -39,7 +39,19 @@ class Opts(ctypes.Structure):
     _fields_ = [("n_scales", ctypes.c_int32), ("embed_dim", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("sampling", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reduction", ctypes.c_int32)]
+
+
+REDUCE_NONE, REDUCE_PARTITION, REDUCE_PAD = 0, 1, 2
+
+
+class Reduction(ctypes.Structure):
+    """chamfer_reduction: the reduction's bounds and exponents."""
+    _fields_ = [("ch1", ctypes.c_double), ("max_t", ctypes.c_double),
+                ("eta_lo", ctypes.c_double), ("eta_hi", ctypes.c_double),
+                ("e_M", ctypes.c_int32), ("e_part", ctypes.c_int32),
+                ("pad_dims", ctypes.c_int32), ("pad_value", ctypes.c_float),
+                ("degenerate", ctypes.c_int32), ("one_part", ctypes.c_int32)]
 
 
 _AUX_ARRAYS = ("sample_idx", "sample_min", "sample_nn", "D", "W", "s", "status",
@@ -77,6 +89,11 @@ _SIGS = {
     "chamfer_retrieve": (ctypes.c_int, [_VP, _I64, _VP, _VP, _I32, _I32, _I32, _F64, _I64, _U64,
                                         _I32, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_default_samples": (ctypes.c_int64, [_I64, _F64]),
+    "chamfer_pad_dims": (ctypes.c_int32, [_I64, _I64, _I32]),
+    "chamfer_reduce_workspace_bytes": (ctypes.c_size_t, [_I64, _I64, _I32, _I32, _VP]),
+    "chamfer_aspect_reduce": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _U64, _VP,
+                                             _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                             _VP]),
     "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
     "chamfer_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -115,8 +132,9 @@ def _check(rc: int, where: str):
 IMPORTANCE, UNIFORM = 0, 1  # enum chamfer_sampling
 
 
-def _opts(n_scales=0, embed_dim=0, precision=0, window=0, reps=0, sampling=0) -> Opts:
-    return Opts(n_scales, embed_dim, precision, window, reps, sampling, 0)
+def _opts(n_scales=0, embed_dim=0, precision=0, window=0, reps=0, sampling=0,
+          reduction=0) -> Opts:
+    return Opts(n_scales, embed_dim, precision, window, reps, sampling, reduction)
 
 
 # ----------------------------------------------------------- torch glue ---
@@ -166,8 +184,8 @@ def release_workspaces():
 # ------------------------------------------------------------- host API ---
 
 def chamfer_workspace_bytes(n_a, n_b, d, metric, eps=0.5, T=0, n_scales=0, embed_dim=0,
-                            precision=0, window=0, reps=0, sampling=0) -> int:
-    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
+                            precision=0, window=0, reps=0, sampling=0, reduction=0) -> int:
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling, reduction)
     return int(lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o)))
 
 
@@ -259,19 +277,23 @@ def crude_nn(A, B, metric, eps, seed, *, n_scales=0, embed_dim=0, window=0, reps
 
 
 def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0, precision=0,
-                     window=0, reps=0, sampling=0,
+                     window=0, reps=0, sampling=0, reduction=0,
                      with_aux=True, stage_events=None):
     """(1 +- eps) estimate of CH(A, B).  Returns a dict of device tensors:
     eta [1] double, and with_aux: sample_idx/min/nn [T], D, W, s, status,
     crude_D/nn/scale [n_A].  stage_events: optional ctypes array of
-    STAGE_EVENTS hipEvent_t handles recorded at the stage boundaries."""
+    STAGE_EVENTS hipEvent_t handles recorded at the stage boundaries.
+    reduction (REDUCE_PARTITION / REDUCE_PAD): the estimate after the
+    reduction to bounded aspect ratio (no aux outputs; synchronises once)."""
     torch = _torch()
     A, B = _points(A, "A"), _points(B, "B")
     n_a, d = A.shape
     n_b = B.shape[0]
     dev = A.device
-    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
-    if T == 0 and 0.0 < eps < 1.0:
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling, reduction)
+    if reduction:
+        with_aux = False
+    if T == 0 and 0.0 < eps < 1.0 and not reduction:
         T = chamfer_default_samples(max(n_a, 1), eps)
     nbytes = lib().chamfer_workspace_bytes(n_a, n_b, d, metric, eps, T, ctypes.byref(o))
     if nbytes == 0:
@@ -297,7 +319,8 @@ def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
     if stage_events is not None:
         aux.stage_events = ctypes.cast(stage_events, ctypes.c_void_p)
     _check(lib().chamfer_estimate(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, T, seed,
-                                  _ptr(out["eta"]), ctypes.byref(aux), ctypes.byref(o),
+                                  _ptr(out["eta"]), None if reduction else ctypes.byref(aux),
+                                  ctypes.byref(o),
                                   _ptr(ws), ws.numel(), _stream(dev)), "chamfer_estimate")
     return out
 
@@ -340,6 +363,45 @@ def chamfer_exact_symmetric(A, B, metric, *, precision=0):
     _check(lib().chamfer_exact_symmetric(_ptr(A), _ptr(B), n_a, n_b, d, metric, _ptr(out),
                                          ctypes.byref(o), _ptr(ws), ws.numel(), _stream(dev)),
            "chamfer_exact_symmetric")
+    return out
+
+
+def chamfer_pad_dims(n_a: int, n_b: int, d: int) -> int:
+    return int(lib().chamfer_pad_dims(n_a, n_b, d))
+
+
+def chamfer_aspect_reduce(A, B, metric, eps, seed=0, *, embed_dim=0, pad=False):
+    """The reduction to bounded aspect ratio (chamfer_aspect_reduce): a dict
+    with the host copy of chamfer_reduction (`info`), t [n_A] float64, the
+    partition keys of A and B (int64 views of the uint64 keys) and, with
+    pad=True, the padded copies [n, d + m]."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    if B.shape[1] != d:
+        raise ValueError("A and B differ in dimension")
+    dev = A.device
+    o = _opts(embed_dim=embed_dim)
+    nbytes = lib().chamfer_reduce_workspace_bytes(n_a, n_b, d, metric, ctypes.byref(o))
+    if nbytes == 0:
+        raise ChamferError(-1, "chamfer_aspect_reduce")
+    ws = _workspace(nbytes, dev)
+    info = torch.zeros(ctypes.sizeof(Reduction), dtype=torch.uint8, device=dev)
+    out = {"t": torch.empty(n_a, dtype=torch.float64, device=dev),
+           "keys_A": torch.empty(n_a, dtype=torch.int64, device=dev),
+           "keys_B": torch.empty(n_b, dtype=torch.int64, device=dev)}
+    m = chamfer_pad_dims(n_a, n_b, d)
+    if pad:
+        out["A_pad"] = torch.empty(n_a, d + m, dtype=torch.float32, device=dev)
+        out["B_pad"] = torch.empty(n_b, d + m, dtype=torch.float32, device=dev)
+    _check(lib().chamfer_aspect_reduce(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, seed,
+                                       ctypes.byref(o), _ptr(info), _ptr(out["t"]),
+                                       _ptr(out["keys_A"]), _ptr(out["keys_B"]),
+                                       _ptr(out.get("A_pad")), _ptr(out.get("B_pad")), _ptr(ws),
+                                       ws.numel(), _stream(dev)), "chamfer_aspect_reduce")
+    r = Reduction.from_buffer_copy(bytes(info.cpu().numpy()))
+    out["info"] = {f: getattr(r, f) for f, _ in Reduction._fields_}
     return out
 
 

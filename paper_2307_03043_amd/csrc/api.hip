@@ -27,6 +27,10 @@ int ceil_log2_dbl(double x) {
     return m == 0.5 ? e - 1 : e;
 }
 
+}  // namespace
+
+namespace chamfer {
+
 // Host Philox4x64-10 (Salmon et al., SC 2011), for the embedding matrix.
 void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
     for (int r = 0; r < 10; ++r) {
@@ -70,6 +74,10 @@ void embedding_transposed(uint64_t seed, int d, int ke, float *zt) {
         for (int k = 0; k < d; ++k) zt[(size_t)k * ke + j] = z[(size_t)j * d + k];
 }
 
+}  // namespace chamfer
+
+namespace {
+
 bool valid_ke(int ke) { return ke == 8 || ke == 16 || ke == 32 || ke == 64; }
 
 int default_scales(int64_t nA, int64_t nB, double eps) {
@@ -102,7 +110,7 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     if (need_eps && !(eps > 0.0 && eps < 1.0)) return CHAMFER_EINVAL;
     chamfer_opts o{};
     if (opts) o = *opts;
-    if (o.n_scales < 0 || o.n_scales > kMaxScales || o.reserved != 0) return CHAMFER_EINVAL;
+    if (o.n_scales < 0 || o.n_scales > kMaxScales || o.reduction != 0) return CHAMFER_EINVAL;
     if (o.window < 0 || o.window > kMaxWindow || o.reps < 0 || o.reps > kMaxReps)
         return CHAMFER_EINVAL;
     if (o.sampling != CHAMFER_IMPORTANCE && o.sampling != CHAMFER_UNIFORM) return CHAMFER_EINVAL;
@@ -421,6 +429,8 @@ extern "C" {
 
 size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,
                                int64_t T, const chamfer_opts *opts) {
+    if (opts && opts->reduction != CHAMFER_REDUCE_NONE)
+        return reduced_workspace_bytes(n_A, n_B, d, metric, eps, T, opts);
     Plan pl;
     // Without a valid eps only the non-estimating entry points can run.
     const bool estimating = eps > 0.0 && eps < 1.0;
@@ -508,6 +518,9 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
                      int32_t metric, double eps, int64_t T, uint64_t seed, double *eta_out,
                      chamfer_aux *aux, const chamfer_opts *opts, void *ws, size_t ws_bytes,
                      void *stream) {
+    if (opts && opts->reduction != CHAMFER_REDUCE_NONE)
+        return estimate_reduced(A, B, n_A, n_B, d, metric, eps, T, seed, eta_out, aux, opts, ws,
+                                ws_bytes, stream);
     Plan pl;
     int rc = make_plan(pl, n_A, n_B, d, metric, eps, T, opts, true);
     if (rc) return rc;

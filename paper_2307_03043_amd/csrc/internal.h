@@ -13,6 +13,9 @@ namespace chamfer {
 constexpr uint32_t kPurposeGrid = 1;    // shifts z' and key multipliers M
 constexpr uint32_t kPurposeEmbed = 2;   // Gaussian embedding matrix
 constexpr uint32_t kPurposeSample = 3;  // importance-sampling draws
+constexpr uint32_t kPurposeSketch = 4;  // p-stable direction of the reduction
+constexpr uint32_t kPurposePart = 5;    // shifts and multipliers of the partition grid
+constexpr uint32_t kPurposePad = 6;     // signs of the padding coordinates
 constexpr uint64_t kEmptyKey = ~0ull;   // bucket keys are < 2^63
 constexpr int kMaxScales = 64;
 constexpr int kMaxWindow = 32;          // W of the multi-probe CrudeNN
@@ -393,6 +396,19 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
                 float *embed_host, Job *job);
 // Block counts of every stage of a job.
 void job_stage_blocks(const Job &job, int64_t out[kBsCount]);
+
+// Host Philox4x64-10 (counter c, key (k0, k1); output in c) and the l2 -> l1
+// embedding matrix, transposed to [d][ke].
+void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1);
+void embedding_transposed(uint64_t seed, int d, int ke, float *zt);
+
+// chamfer_estimate / chamfer_workspace_bytes with opts->reduction set.
+size_t reduced_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,
+                               int64_t T, const chamfer_opts *opts);
+int estimate_reduced(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
+                     int32_t metric, double eps, int64_t T, uint64_t seed, double *eta_out,
+                     chamfer_aux *aux, const chamfer_opts *opts, void *ws, size_t ws_bytes,
+                     void *stream);
 // Re-split B for the exact pass of a job in a batch: the exact float32
 // passes give the exact nearest neighbour for any split, so a batch shares
 // one workgroup target among its jobs in proportion to their work instead

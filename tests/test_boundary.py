@@ -103,7 +103,7 @@ def test_argument_errors_are_host_side():
     for bad in (ch.Opts(0, 12, 0, 0, 0, 0, 0), ch.Opts(0, 0, 7, 0, 0, 0, 0),
                 ch.Opts(0, 0, 0, 33, 0, 0, 0), ch.Opts(0, 0, 0, -1, 0, 0, 0),
                 ch.Opts(0, 0, 0, 0, 65, 0, 0), ch.Opts(0, 0, 0, 0, 0, 2, 0),
-                ch.Opts(0, 0, 0, 0, 0, 0, 1)):
+                ch.Opts(0, 0, 0, 0, 0, 0, 3), ch.Opts(0, 0, 0, 0, 0, 0, -1)):
         assert _raw_estimate(lib, opts=ctypes.byref(bad)) == -1
     # CrudeNN needs its tables: uniform sampling is an estimator option only
     uni = ch.Opts(0, 0, 0, 0, 0, 1, 0)
@@ -127,6 +127,62 @@ def test_argument_errors_are_host_side():
                         1 << 20, None) == -1
     assert lib.chamfer_nn_min(dummy, None, -1, dummy, 5, 3, 2, None, None, None, dummy, 1 << 20,
                               None) == -1
+
+
+def orc_pad(n, d):
+    """The padding-width rule written out (next of 16/32/64/128, else a
+    multiple of 16, of d + 3 ceil(log2 n))."""
+    dp = d + 3 * max(1, (n - 1).bit_length())
+    nxt = [w for w in (16, 32, 64, 128) if w >= dp]
+    return (nxt[0] if nxt else -(-dp // 16) * 16) - d
+
+
+def test_reduction_argument_errors_are_host_side():
+    """The reduction: pad dimension rule, workspace sizes, and argument
+    errors before any device work; the other entry points reject it."""
+    lib = ch.lib()
+    # at least 3 ceil(log2 n), d + m on a width the exact pass specialises
+    assert lib.chamfer_pad_dims(1, 1, 1) == 15 and lib.chamfer_pad_dims(1000, 5, 3) == 61
+    assert lib.chamfer_pad_dims(1 << 20, 7, 64) == 64 and lib.chamfer_pad_dims(1 << 20, 7, 100) == 60
+    assert lib.chamfer_pad_dims(3, (1 << 20) + 1, 128) == 64 and lib.chamfer_pad_dims(5, 5, 0) == -1
+    for n in (2, 100, 10 ** 6):
+        for d in (1, 3, 16, 37, 64, 100, 128, 129, 300, 2000):
+            m = lib.chamfer_pad_dims(n, n, d)
+            assert m == orc_pad(n, d) and m >= 3 * max(1, (n - 1).bit_length())
+    assert lib.chamfer_reduce_workspace_bytes(100, 200, 3, 1, None) > 0
+    assert lib.chamfer_reduce_workspace_bytes(0, 200, 3, 1, None) == 0
+    assert lib.chamfer_reduce_workspace_bytes(100, 200, 3, 3, None) == 0
+    assert lib.chamfer_reduce_workspace_bytes(100, 200, 4096, 1, None) == 0
+    part, padded = ch._opts(reduction=1), ch._opts(reduction=2)
+    plain = lib.chamfer_workspace_bytes(1000, 2000, 16, 2, 0.2, 0, None)
+    red = lib.chamfer_workspace_bytes(1000, 2000, 16, 2, 0.2, 0, ctypes.byref(part))
+    pad = lib.chamfer_workspace_bytes(1000, 2000, 16, 2, 0.2, 0, ctypes.byref(padded))
+    assert plain < red < pad
+    # d + m must stay within 2048 for the padded estimate
+    assert lib.chamfer_workspace_bytes(1000, 1000, 2040, 1, 0.2, 0, ctypes.byref(padded)) == 0
+    assert lib.chamfer_workspace_bytes(1000, 1000, 2040, 1, 0.2, 0, ctypes.byref(part)) > 0
+    dummy = ctypes.c_void_p(256)
+    aux = ch.Aux()
+    out = ctypes.c_void_p(64)
+    # aux outputs are not available with the reduction
+    assert lib.chamfer_estimate(dummy, dummy, 10, 10, 3, 2, 0.2, 0, 1, out, ctypes.byref(aux),
+                                ctypes.byref(part), dummy, 1 << 40, None) == -1
+    assert lib.chamfer_estimate(dummy, dummy, 10, 10, 3, 2, 0.2, 0, 1, out, None,
+                                ctypes.byref(part), dummy, red // 1000, None) == -2
+    assert lib.chamfer_estimate(dummy, dummy, 10, 10, 3, 2, 1.5, 0, 1, out, None,
+                                ctypes.byref(part), dummy, 1 << 40, None) == -1
+    # chamfer_aspect_reduce
+    rb = lib.chamfer_reduce_workspace_bytes(10, 10, 3, 2, None)
+    call = lambda **k: lib.chamfer_aspect_reduce(
+        k.get("A", dummy), dummy, k.get("n_a", 10), 10, 3, 2, k.get("eps", 0.2), 1, None, None,
+        None, None, None, None, None, dummy, k.get("ws", rb - 1), None)
+    assert call(n_a=0) == -1 and call(A=None) == -1 and call(eps=0.0) == -1
+    assert call() == -2
+    # every other entry point rejects a reduction
+    assert lib.crude_nn(dummy, dummy, 5, 5, 3, 2, 0.5, 0, dummy, dummy, None, ctypes.byref(part),
+                        dummy, 1 << 30, None) == -1
+    assert lib.chamfer_exact(dummy, dummy, 5, 5, 3, 2, dummy, None, None, ctypes.byref(part),
+                             dummy, 1 << 30, None) == -1
 
 
 def test_retrieve_argument_errors_are_host_side():
