@@ -112,6 +112,25 @@ struct Blk {
 };
 __device__ __forceinline__ Blk grid_blk() { return Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}; }
 
+// Work order of the exact passes (nq query blocks x nchunk chunks of B):
+// workgroup ids are dealt to the 8 XCDs round-robin, so id runs on XCD
+// id % 8 as its (id / 8)-th workgroup.  With nchunk a multiple of 8, XCD x
+// takes the chunks cb = 8c + x in turn and, for each, all its query blocks
+// one after the other: the workgroups of one chunk run on one XCD at about
+// the same time and read the chunk through that XCD's L2 once.  Otherwise
+// the chunk varies fastest.
+__device__ __forceinline__ void chunk_major(int64_t id, int64_t nq, int nchunk, int &cb,
+                                            int64_t &qb) {
+    if ((nchunk & 7) == 0) {
+        const int64_t s = id >> 3;
+        cb = (int)((s / nq) * 8 + (id & 7));
+        qb = s % nq;
+    } else {
+        cb = (int)(id % nchunk);
+        qb = id / nchunk;
+    }
+}
+
 // ---------------------------------------------------------------- batches
 // One request of a batched estimate: its inputs, workspace regions, output
 // slots and the block counts of each of its launches (the same counts its

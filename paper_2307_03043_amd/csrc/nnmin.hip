@@ -50,8 +50,10 @@ __device__ __forceinline__ void nnmin_fixed(const float *__restrict__ X,
     if (p->status != CHAMFER_OK) return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int cb = (int)(blk.id % nchunk);  // chunk index varies fastest
-    const int64_t qg = (blk.id / nchunk) * 4 + wave;
+    int cb;
+    int64_t qb;
+    chunk_major(blk.id, ((nx + 64 * QPL - 1) / (64 * QPL) + 3) / 4, nchunk, cb, qb);
+    const int64_t qg = qb * 4 + wave;
     const int64_t q0 = qg * 64 * QPL;
     if (q0 >= nx) return;
     const int64_t b0 = (int64_t)cb * chunk;
@@ -150,8 +152,10 @@ __device__ __forceinline__ void nnmin_any(const float *__restrict__ X,
     if (p->status != CHAMFER_OK) return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int cb = (int)(blk.id % nchunk);
-    const int64_t qi = ((blk.id / nchunk) * 4 + wave) * 64 + lane;
+    int cb;
+    int64_t qb;
+    chunk_major(blk.id, ((nx + 63) / 64 + 3) / 4, nchunk, cb, qb);
+    const int64_t qi = (qb * 4 + wave) * 64 + lane;
     if (qi - lane >= nx) return;
     const int64_t b0 = (int64_t)cb * chunk;
     const int64_t b1 = min(nB, b0 + chunk);
@@ -205,9 +209,8 @@ __global__ __launch_bounds__(256) void k_nnmin_any(const float *__restrict__ X,
 }
 
 // Split B into chunks so the grid has enough workgroups to fill 256 CUs;
-// the chunk count is a multiple of 8 when > 1 so the workgroups of one
-// chunk (consecutive ids differ by nchunk) land on one XCD (ids are dealt
-// round-robin over the 8 XCDs) and share its L2.
+// the chunk count is a multiple of 8 when > 1 so that the work order
+// (chunk_major) keeps each chunk's workgroups on one XCD.
 static void split_b(int64_t qblocks, int64_t nB, int64_t target, int64_t &chunk, int &nchunk) {
     int64_t nc = (target + qblocks - 1) / qblocks;
     const int64_t maxc = (nB + 63) / 64;

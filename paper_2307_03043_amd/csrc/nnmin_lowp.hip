@@ -161,8 +161,10 @@ __device__ __forceinline__ void nnmin_l2_lowp(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int cb = (int)(blk.id % nchunk);
-    const int64_t qbase = ((blk.id / nchunk) * 4 + wave) * (16 * NB);
+    int cb;
+    int64_t qb;
+    chunk_major(blk.id, (nx + 64 * NB - 1) / (64 * NB), nchunk, cb, qb);
+    const int64_t qbase = (qb * 4 + wave) * (16 * NB);
     const int64_t b0 = (int64_t)cb * chunk;
     const int64_t b1 = min(nB, b0 + chunk);
     if (b0 >= b1) return;
