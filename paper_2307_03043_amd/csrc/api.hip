@@ -145,7 +145,7 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     const int64_t nrow = (estimating && pl.T > nA) ? pl.T : nA;
     const size_t h = hashing ? 1 : 0, e_ = estimating ? 1 : 0;
     pl.off_params = take(sizeof(DevParams));
-    pl.off_lohi = take(2 * (size_t)d * sizeof(uint32_t));
+    pl.off_lohi = take(lohi_bytes(d));
     pl.off_zfrac = take(h * pl.L * pl.kh * sizeof(float));
     pl.off_mult = take(h * pl.L * pl.kh * sizeof(uint64_t));
     pl.off_embed = take(metric == CHAMFER_L2 ? h * d * ke * sizeof(float) : 0);

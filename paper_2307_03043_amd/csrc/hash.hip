@@ -33,17 +33,15 @@ __device__ __forceinline__ void init_params(DevParams *p, uint32_t *lohi, int d,
         p->fallbacks = 0;
     }
     if (lohi != nullptr)
-        for (int64_t k = t; k < d; k += b.n * blockDim.x) {
-            lohi[k] = 0xffffffffu;  // running min (ordered encoding)
-            lohi[d + k] = 0u;       // running max
-        }
+        for (int64_t k = t; k < (int64_t)kLohiReps * 2 * d; k += b.n * blockDim.x)
+            lohi[k] = (k % (2 * d)) < d ? 0xffffffffu : 0u;  // running min / max (ordered)
 }
 
 __global__ void k_init_params(DevParams *p, uint32_t *lohi, int d) {
     init_params(p, lohi, d, grid_blk());
 }
 
-int64_t init_blocks(int d) { return (d + 255) / 256; }
+int64_t init_blocks(int d) { return ((int64_t)kLohiReps * 2 * d + 255) / 256; }
 
 hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t st) {
     const int blocks = lohi ? (int)init_blocks(d) : 1;
@@ -109,16 +107,18 @@ __device__ __forceinline__ void minmax(const float *__restrict__ X, int64_t tota
             atomicMin(&sm[k], lo);
             atomicMax(&sm[d + k], hi);
         } else {
-            atomicMin(&lohi[k], lo);
-            atomicMax(&lohi[d + k], hi);
+            uint32_t *rep = lohi + (b.id % kLohiReps) * 2 * d;
+            atomicMin(&rep[k], lo);
+            atomicMax(&rep[d + k], hi);
         }
     }
     if (bad) atomicOr(&p->nonfinite, 1u);
     if (use_lds) {
         __syncthreads();
+        uint32_t *rep = lohi + (b.id % kLohiReps) * 2 * d;
         for (int i = threadIdx.x; i < d; i += blockDim.x) {
-            if (sm[i] != 0xffffffffu) atomicMin(&lohi[i], sm[i]);
-            if (sm[d + i] != 0u) atomicMax(&lohi[d + i], sm[d + i]);
+            if (sm[i] != 0xffffffffu) atomicMin(&rep[i], sm[i]);
+            if (sm[d + i] != 0u) atomicMax(&rep[d + i], sm[d + i]);
         }
     }
 }
@@ -175,9 +175,10 @@ __device__ __forceinline__ void minmax4(const float4 *__restrict__ X4, int64_t t
     }
     if (bad) atomicOr(&p->nonfinite, 1u);
     __syncthreads();
+    uint32_t *rep = lohi + (b.id % kLohiReps) * 2 * d;
     for (int i = threadIdx.x; i < d; i += blockDim.x) {
-        if (sm[i] != 0xffffffffu) atomicMin(&lohi[i], sm[i]);
-        if (sm[d + i] != 0u) atomicMax(&lohi[d + i], sm[d + i]);
+        if (sm[i] != 0xffffffffu) atomicMin(&rep[i], sm[i]);
+        if (sm[d + i] != 0u) atomicMax(&rep[d + i], sm[d + i]);
     }
 }
 
@@ -230,7 +231,22 @@ hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevPa
     return hipGetLastError();
 }
 
-__global__ void k_calib_final_wide(const uint32_t *lohi, int d, DevParams *p) {
+// Fold the kLohiReps copies of the running min/max into the first.
+__device__ __forceinline__ void fold_lohi(uint32_t *lohi, int d) {
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        uint32_t lo = lohi[k], hi = lohi[d + k];
+        for (int r = 1; r < kLohiReps; ++r) {
+            lo = min(lo, lohi[(size_t)r * 2 * d + k]);
+            hi = max(hi, lohi[(size_t)r * 2 * d + d + k]);
+        }
+        lohi[k] = lo;
+        lohi[d + k] = hi;
+    }
+    __syncthreads();
+}
+
+__global__ void k_calib_final_wide(uint32_t *lohi, int d, DevParams *p) {
+    fold_lohi(lohi, d);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double S = 0.0;
     for (int k = 0; k < d; ++k)
@@ -243,8 +259,9 @@ __global__ void k_calib_final_wide(const uint32_t *lohi, int d, DevParams *p) {
 // S = sum_k (hi_k - lo_k) in double, k ascending; e_top = ceil(log2 S).
 // The per-coordinate spans are gathered in parallel; one thread sums them
 // in order.
-__device__ __forceinline__ void calib_final(const uint32_t *lohi, int d, DevParams *p) {
+__device__ __forceinline__ void calib_final(uint32_t *lohi, int d, DevParams *p) {
     extern __shared__ double span[];
+    fold_lohi(lohi, d);
     for (int k = threadIdx.x; k < d; k += blockDim.x)
         span[k] = (double)ordered_to_float(lohi[d + k]) - (double)ordered_to_float(lohi[k]);
     __syncthreads();
@@ -256,7 +273,7 @@ __device__ __forceinline__ void calib_final(const uint32_t *lohi, int d, DevPara
     if (p->nonfinite) p->status = CHAMFER_ENONFINITE;
 }
 
-__global__ __launch_bounds__(256) void k_calib_final(const uint32_t *lohi, int d, DevParams *p) {
+__global__ __launch_bounds__(256) void k_calib_final(uint32_t *lohi, int d, DevParams *p) {
     calib_final(lohi, d, p);
 }
 

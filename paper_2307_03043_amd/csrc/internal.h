@@ -18,6 +18,12 @@ constexpr uint32_t kPurposePart = 5;    // shifts and multipliers of the partiti
 constexpr uint32_t kPurposePad = 6;     // signs of the padding coordinates
 constexpr uint64_t kEmptyKey = ~0ull;   // bucket keys are < 2^63
 constexpr int kMaxScales = 64;
+// The per-coordinate min/max is accumulated in kLohiReps copies (workgroup
+// id mod kLohiReps picks one) so that the global atomics of many workgroups
+// do not queue on the same 2d words; the calibration folds the copies into
+// the first, [lo(d) | hi(d)], which every later kernel reads.
+constexpr int kLohiReps = 8;
+inline size_t lohi_bytes(int d) { return (size_t)kLohiReps * 2 * (size_t)d * sizeof(uint32_t); }
 constexpr int kMaxWindow = 32;          // W of the multi-probe CrudeNN
 constexpr int kMaxReps = 64;            // k of the multi-probe CrudeNN
 // flags of the probe launches of the multi-probe CrudeNN

@@ -111,7 +111,7 @@ int rplan(RPlan &rp, int64_t nA, int64_t nB, int32_t d, int32_t metric,
     rp.off_sort = take(rp.sort_bytes);
     rp.off_partial = take(kNearBlocks * sizeof(double));
     rp.off_params = take(sizeof(DevParams));
-    rp.off_lohi = take((size_t)2 * d * sizeof(uint32_t));
+    rp.off_lohi = take(lohi_bytes(d));
     rp.off_embed = take(metric == CHAMFER_L2 ? (size_t)d * ke * sizeof(float) : 0);
     rp.off_zp = take((size_t)rp.kh * sizeof(float));
     rp.off_mp = take((size_t)rp.kh * sizeof(uint64_t));
