@@ -91,3 +91,54 @@ def test_fullsize_exact_rows(ch, orc, name):
     assert np.array_equal(got_min.view(np.uint32), m32.view(np.uint32))
     np.testing.assert_allclose(got_min, m64, rtol=REL, atol=0)
     assert math.isfinite(float(chv.item()))
+
+
+def test_fullsize_retrieval(ch, orc):
+    """The retrieval report's workload (1000 d = 3 clouds of 1000..4000
+    points, l1, T = 50, three scales, families of 10 with 2% jitter): the
+    symmetric estimate of every 25th cloud as the oracle's, the top-10 the
+    ten smallest estimates ranked by exact CH (the GPU's exact symmetric CH
+    of each, the first also against the oracle's)."""
+    print("[case] fullsize retrieval", flush=True)
+    clouds, qs, src = workloads.retrieval_collection(seed=42, m=1000, n_min=1000, n_max=4000,
+                                                     queries=2, family=10, jitter=0.02)
+    sizes = [c.shape[0] for c in clouds]
+    Bs = torch.from_numpy(np.ascontiguousarray(np.concatenate(clouds))).cuda()
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    for q in qs:
+        Q = torch.from_numpy(q).cuda()
+        est, top, vals = ch.chamfer_retrieve_packed(Q, Bs, sizes, 1, 0.2, 50, 3, 10, n_scales=3)
+        e = est.cpu().numpy()
+        for i in range(0, 1000, 25):
+            ref = orc.chamfer_symmetric_estimate(q, clouds[i], 1, 0.2, 50, 3, n_scales=3)[0]
+            assert e[i] == pytest.approx(ref, rel=REL), i
+        cand = sorted(range(1000), key=lambda i: (e[i], i))[:10]
+        assert sorted(top) == sorted(cand)
+        assert vals == sorted(vals)
+        for i, v in zip(top, vals):
+            ex = float(ch.chamfer_exact_symmetric(Q, Bs[offs[i]:offs[i + 1]], 1)[0].item())
+            assert v == ex
+        ref = orc.chamfer_symmetric_exact(q, clouds[top[0]], 1)[0]
+        assert vals[0] == pytest.approx(ref, rel=REL)
+
+
+@pytest.mark.parametrize("name", ["l2_100k_d128", "l1_1m_d64"])
+def test_fullsize_reduction(ch, orc, name):
+    """The reduction at the benchmark sizes: t_a and M bit for bit, the
+    exponents exactly, the partition keys of every point bit for bit, one
+    part, and the partition-only estimate identical to the plain one."""
+    print(f"[case] fullsize reduction {name}", flush=True)
+    gen, kw, metric, eps, T, L, _ = CONFIGS[name]
+    A, B, At, Bt = data(name)
+    got = ch.chamfer_aspect_reduce(At, Bt, metric, eps, 1)
+    ref = orc.aspect_reduce(A, B, metric, eps, 1)
+    info = got["info"]
+    assert np.array_equal(got["t"].cpu().numpy(), ref["t"])
+    assert info["max_t"] == ref["max_t"] and info["e_part"] == ref["e_part"]
+    assert np.float32(info["pad_value"]) == ref["q"]
+    assert np.array_equal(got["keys_A"].cpu().numpy().view(np.uint64), ref["keys_A"])
+    assert np.array_equal(got["keys_B"].cpu().numpy().view(np.uint64), ref["keys_B"])
+    assert info["one_part"] == 1
+    plain = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L, with_aux=False)["eta"]
+    red = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L, reduction=1)["eta"]
+    assert float(plain.item()) == float(red.item())
