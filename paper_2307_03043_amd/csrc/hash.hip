@@ -371,24 +371,17 @@ __device__ __forceinline__ uint64_t home_slot(unsigned long long key, int log2ca
     return (uint64_t)(key >> (63 - log2cap));
 }
 
-#ifndef CH_INSERT_READ
-#define CH_INSERT_READ 0
-#endif
 // Insert (key -> b) keeping the lowest b per key.  Linear probing; a slot's
 // key changes only from EMPTY, by CAS, so each key owns exactly one slot.
+// The slot is read first, so a key already present costs a load (and an
+// atomicMin only when b is lower than the stored value).
 __device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, int b) {
     const uint64_t mask = (1ull << log2cap) - 1;
     uint64_t slot = home_slot(key, log2cap);
     for (;;) {
         Bucket *e = tab + slot;
-#if CH_INSERT_READ == 0
         unsigned long long cur =
             __hip_atomic_load(&e->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#elif CH_INSERT_READ == 1
-        unsigned long long cur = *(volatile unsigned long long *)&e->key;
-#else
-        unsigned long long cur = kEmptyKey;
-#endif
         if (cur == kEmptyKey) {
             const unsigned long long prev = atomicCAS(&e->key, kEmptyKey, key);
             if (prev == kEmptyKey || prev == key) {
@@ -398,11 +391,7 @@ __device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, i
             cur = prev;
         }
         if (cur == key) {
-#if CH_INSERT_READ == 0
             if (__hip_atomic_load(&e->val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > b)
-#else
-            if (*(volatile int *)&e->val > b)
-#endif
                 atomicMin(&e->val, b);
             return;
         }
