@@ -374,7 +374,7 @@ int chamfer_exact_symmetric(const float *A, const float *B, int64_t n_A, int64_t
  * entries, offsets[0] = 0, strictly increasing) gives cloud i as rows
  * offsets[i] .. offsets[i+1]-1.  For every cloud the symmetric estimate
  * eta(A, B_i) + eta(B_i, A) is computed (both directions with eps, T, seed
- * and opts; the jobs run 64 at a time through the batched estimator
+ * and opts; the jobs run up to 256 at a time through the batched estimator
  * stages) into est_out (device double[m], may be NULL); the k clouds with
  * the smallest estimates (ties to the lower index) are then re-ranked by
  * their exact symmetric CH (always float32, whatever opts.precision):
@@ -382,9 +382,10 @@ int chamfer_exact_symmetric(const float *A, const float *B, int64_t n_A, int64_t
  * ascending order of exact CH (ties to the lower index) and top_ch_out
  * (host double[k]) the values.  opts.window, reps and sampling must be the
  * defaults; d <= 2048; every cloud non-empty.  The workspace needs
- * chamfer_retrieve_workspace_bytes (64 estimator workspaces sized for the
- * largest cloud, plus small tables; 0 on invalid arguments).  Synchronous: returns after the stream
- * has drained.  Errors as chamfer_estimate; a cloud with a NaN/Inf
+ * chamfer_retrieve_workspace_bytes (one estimator workspace sized for the
+ * largest cloud per job of a batch, 256 jobs or as many as fit 4 GiB, plus
+ * small tables; 0 on invalid arguments).  Synchronous: returns after the
+ * stream has drained.  Errors as chamfer_estimate; a cloud with a NaN/Inf
  * coordinate gets a NaN estimate and ranks last.
  */
 size_t chamfer_retrieve_workspace_bytes(int64_t n_A, const int64_t *offsets, int32_t m,

@@ -301,8 +301,7 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
         return CHAMFER_EINVAL;
     // single structure, W = 1, importance sampling
     if (pl.window != 1 || pl.reps != 1 || pl.sampling != CHAMFER_IMPORTANCE) return CHAMFER_EINVAL;
-    if (metric == CHAMFER_L2 && (embed_dev == nullptr || embed_host == nullptr))
-        return CHAMFER_EINVAL;
+    if (metric == CHAMFER_L2 && embed_dev == nullptr) return CHAMFER_EINVAL;
     if ((rc = check_ws(pl, ws, ws_bytes))) return rc;
     const bool lp = lowp_supported(d, metric, pl.precision);
     Job &J = *job;
@@ -370,7 +369,8 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
     J.nn_chunk = g.chunk;
     J.nn_nchunk = g.nchunk;
     J.nb_nn = (int32_t)g.blocks;
-    if (metric == CHAMFER_L2) embedding_transposed(seed, d, pl.ke, embed_host);
+    // embed_host NULL: the caller has staged this job's embedding already
+    if (metric == CHAMFER_L2 && embed_host) embedding_transposed(seed, d, pl.ke, embed_host);
     return CHAMFER_OK;
 }
 

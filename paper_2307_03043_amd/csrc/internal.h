@@ -189,7 +189,7 @@ enum BatchStage {
     kBsCount
 };
 
-constexpr int kBatchMax = 64;
+constexpr int kBatchMax = 256;
 
 struct alignas(16) Batch {
     int32_t njobs;

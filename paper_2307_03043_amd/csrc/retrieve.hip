@@ -1,12 +1,12 @@
 // One-vs-many retrieval (the downstream experiment of the paper: the
 // nearest point cloud to A under CH(A, B) + CH(B, A) in a collection):
 //   1. est_i = eta(A, B_i) + eta(B_i, A) for every cloud: two estimator jobs
-//      per cloud, run 64 at a time through the batched stage kernels (one
+//      per cloud, run up to 256 at a time through the batched stage kernels (one
 //      launch per stage for the whole batch);
 //   2. the k smallest est_i (ties to the lower i);
 //   3. the exact CH(A, B_i) + CH(B_i, A) of those k, ranked ascending (ties
 //      to the lower i).
-// Workspace: the batch descriptor, the jobs' embeddings, the per-job eta
+// Workspace: the batch descriptor, the jobs' (shared) embedding, the per-job eta
 // and per-cloud estimates, then one estimator workspace per batch slot, each
 // sized for the largest cloud in either direction and for the exact
 // re-rank's plans (which run in full precision whatever opts.precision).
@@ -26,9 +26,14 @@ constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t batch, embed_per_job, embed, eta, est, per_job_ws, jobs, total;
+    size_t batch, embed, eta, est, per_job_ws, jobs, total;
     size_t off_embed, off_eta, off_est, off_jobs;
+    int slots;  // jobs per batch
 };
+
+// Job workspaces of one batch stay within this many bytes (large clouds get
+// fewer jobs per batch; small ones fill the whole descriptor).
+constexpr size_t kSlotBudget = size_t(4) << 30;
 
 int valid_offsets(const int64_t *offsets, int32_t m) {
     if (offsets == nullptr || m < 1 || offsets[0] != 0) return 0;
@@ -60,12 +65,13 @@ int layout(Layout &lo, int64_t n_A, const int64_t *offsets, int32_t m, int32_t d
     }
     std::memset(&lo, 0, sizeof(lo));
     lo.batch = up(sizeof(Batch));
-    lo.embed_per_job = metric == CHAMFER_L2 ? up((size_t)d * ke * sizeof(float)) : 0;
-    lo.embed = lo.embed_per_job * kBatchMax;
+    // every job has the same seed and d, hence one embedding matrix (l2)
+    lo.embed = metric == CHAMFER_L2 ? up((size_t)d * ke * sizeof(float)) : 0;
     lo.eta = up((size_t)2 * m * sizeof(double));
     lo.est = up((size_t)4 * m * sizeof(double));  // estimates, then [3] per candidate
     lo.per_job_ws = up(maxws);
-    lo.jobs = lo.per_job_ws * kBatchMax;
+    lo.slots = (int)std::max<size_t>(1, std::min<size_t>(kBatchMax, kSlotBudget / lo.per_job_ws));
+    lo.jobs = lo.per_job_ws * lo.slots;
     lo.off_embed = lo.batch;
     lo.off_eta = lo.off_embed + lo.embed;
     lo.off_est = lo.off_eta + lo.eta;
@@ -80,7 +86,7 @@ __global__ void k_pair_sums(const double *eta, int32_t m, double *est) {
     if (i < m) est[i] = eta[2 * i] + eta[2 * i + 1];
 }
 
-// Two host staging buffers for the batch descriptor and embeddings: batch
+// Two host staging buffers for the batch descriptor: batch
 // j is written into buffer j % 2 once the copy of batch j - 2 out of it has
 // completed (an event after each copy), so host preparation of one batch
 // overlaps the device work of the previous one.
@@ -138,17 +144,25 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
     const int ke = metric == CHAMFER_L2 ? (o.embed_dim ? o.embed_dim : 32) : 0;
     const int prec = lowp_supported(d, metric, o.precision) ? o.precision : CHAMFER_FP32;
 
-    // 1. estimates, 64 jobs per batch (job 2i: A -> B_i, job 2i + 1: B_i -> A)
+    // 1. estimates, kBatchMax jobs per batch (job 2i: A -> B_i, job 2i + 1:
+    // B_i -> A)
     Staging stg;
     stg.st = st;
+    std::vector<float> emb;  // read by the copy below before the stream drains
+    if (metric == CHAMFER_L2) {
+        emb.resize((size_t)d * ke);
+        embedding_transposed(seed, d, ke, emb.data());
+        CH_TRY(hipMemcpyAsync(base + lo.off_embed, emb.data(), emb.size() * sizeof(float),
+                              hipMemcpyHostToDevice, st));
+    }
     for (int b = 0; b < 2; ++b) {
-        stg.buf[b].resize(lo.off_eta);  // descriptor + embeddings
+        stg.buf[b].resize(lo.batch);  // the batch descriptor
         CH_TRY(hipEventCreateWithFlags(&stg.ev[b], hipEventDisableTiming));
     }
     const int njobs = 2 * m;
-    for (int j0 = 0; j0 < njobs; j0 += kBatchMax) {
-        const int nb = std::min(kBatchMax, njobs - j0);
-        const int hb = (j0 / kBatchMax) & 1;
+    for (int j0 = 0; j0 < njobs; j0 += lo.slots) {
+        const int nb = std::min(lo.slots, njobs - j0);
+        const int hb = (j0 / lo.slots) & 1;
         if (stg.used[hb]) CH_TRY(hipEventSynchronize(stg.ev[hb]));
         std::vector<char> &host = stg.buf[hb];
         Batch *bh = reinterpret_cast<Batch *>(host.data());
@@ -162,10 +176,7 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
             rc = job_prepare(fwd ? A : B, fwd ? B : A, fwd ? n_A : nB, fwd ? nB : n_A, d, metric,
                              eps, T, seed, opts, base + lo.off_jobs + (size_t)s * lo.per_job_ws,
                              lo.per_job_ws, eta + j, aux,
-                             reinterpret_cast<const float *>(base + lo.off_embed +
-                                                             (size_t)s * lo.embed_per_job),
-                             reinterpret_cast<float *>(host.data() + lo.off_embed +
-                                                       (size_t)s * lo.embed_per_job),
+                             reinterpret_cast<const float *>(base + lo.off_embed), nullptr,
                              &bh->job[s]);
             if (rc) return rc;
         }
@@ -182,9 +193,10 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
         }
         bh->njobs = nb;
         for (int q = 0; q < kBsCount; ++q) bh->start[q][nb] = (int32_t)acc[q];
-        // the device descriptor and embeddings are reused by every batch:
-        // stream order keeps this copy behind the previous batch's kernels
-        CH_TRY(hipMemcpyAsync(bt_dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
+        // the device descriptor is reused by every batch: stream order keeps
+        // this copy (its used part) behind the previous batch's kernels
+        CH_TRY(hipMemcpyAsync(bt_dev, host.data(), offsetof(Batch, job) + (size_t)nb * sizeof(Job),
+                              hipMemcpyHostToDevice, st));
         CH_TRY(hipEventRecord(stg.ev[hb], st));
         stg.used[hb] = true;
         if ((rc = launch_estimate_batch(bt_dev, d, metric, ke, prec, st))) return rc;
