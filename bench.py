@@ -132,6 +132,9 @@ def measured_traffic(workload, kernel_ms):
     return rec["traffic_bytes"]
 
 
+# Calls timed with stage events for the per-stage split and p50/p99 latency.
+LATENCY_CALLS = 100
+
 # Points per set for the CPU oracle's timed sample (full workload when smaller).
 CPU_SAMPLE_POINTS = 250_000
 
@@ -145,13 +148,36 @@ def cpu_baseline(args, A, B, metric, eps, T, L, seed):
     t0 = time.perf_counter()
     ref = oracle.chamfer_estimate(As, Bs, metric, eps, T, seed, n_scales=L)
     dt = time.perf_counter() - t0
+    cores = oracle.threads()
+    # the same estimate on one thread, on a tenth of the sample's rows of A
+    # and of B (the exact pass is linear in T n_B, the rest in n_A + n_B)
+    oracle.set_threads(1)
+    n1, m1 = max(1, n_a // 10), max(1, n_b // 10)
+    t0 = time.perf_counter()
+    oracle.chamfer_estimate(As[:n1], Bs[:m1], metric, eps, T, seed, n_scales=L)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     what = (f"full workload (|A|={n_a}, |B|={n_b})" if full else
             f"the first {n_a} points of A and {n_b} of B (same generator)")
-    return dict(value=(n_a + n_b) / dt, unit="points/s", cores=oracle.threads(),
-                kind="oracle", seconds=dt,
+    return dict(value=(n_a + n_b) / dt, unit="points/s", cores=cores,
+                kind="oracle", seconds=dt, host_cpu=host_cpu(), nproc=os.cpu_count(),
+                single_thread={"points_per_s": (n1 + m1) / dt1, "seconds": dt1,
+                               "sample": f"|A|={n1}, |B|={m1}, same eps, T and L"},
                 sample=f"{what}, one estimate with the same eps, T and L; double-precision "
-                       f"exact pass on {oracle.threads()} OpenMP threads, hashing "
+                       f"exact pass on {cores} OpenMP threads, hashing "
                        f"single-threaded"), (ref if full else None)
+
+
+def host_cpu():
+    """The host CPU model (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def precision_report(args, ch, torch, A, B, At, Bt, metric, eps, T, L, desc):
@@ -670,25 +696,26 @@ def main():
     print(f"[bench] timed {args.steps} steps: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
     # per-stage times and per-step latency from the library's stage events
-    ev = HipEvents(ch.STAGE_EVENTS * args.steps)
-    outs = []
-    for s in range(args.steps):
+    # per-stage times and per-call latency over at least LATENCY_CALLS calls
+    ncalls = max(args.steps, LATENCY_CALLS)
+    ev = HipEvents(ch.STAGE_EVENTS * ncalls)
+    for s in range(ncalls):
         sub = ctypes.c_void_p(ctypes.addressof(ev.arr)
                               + s * ch.STAGE_EVENTS * ctypes.sizeof(ctypes.c_void_p))
-        outs.append(ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, with_aux=True,
-                                        stage_events=sub))
+        last = ch.chamfer_estimate(At, Bt, metric, eps, T, seed, n_scales=L, with_aux=True,
+                                   stage_events=sub)
     torch.cuda.synchronize()
     names = ["calibrate+tables", "bucket_B", "probe_A+D_a", "weights+draws", "exact_pass",
              "final"]
-    stage = np.zeros((args.steps, len(names)))
-    lat = np.zeros(args.steps)
-    for s in range(args.steps):
+    stage = np.zeros((ncalls, len(names)))
+    lat = np.zeros(ncalls)
+    for s in range(ncalls):
         base = s * ch.STAGE_EVENTS
         for i in range(len(names)):
             stage[s, i] = ev.ms(base + i, base + i + 1)
         lat[s] = ev.ms(base, base + ch.STAGE_EVENTS - 1)
     ev.close()
-    aux = outs[-1]
+    aux = last
     stages_ms = {n: float(stage[:, i].mean()) for i, n in enumerate(names)}
     dom = int(np.argmax(stage.mean(axis=0)))
     lam = float(aux["D"].item())
@@ -719,7 +746,8 @@ def main():
         "config": {"workload": desc, "name": args.workload, "n_a": n_a, "n_b": n_b, "d": d,
                    "metric": "l2" if metric == 2 else "l1", "eps": eps, "T": T, "L": L,
                    "seed": args.seed},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "calls": int(ncalls)},
         "stages_ms": stages_ms,
         "dominant_stage": names[dom],
         "roofline": roofline,

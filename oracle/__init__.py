@@ -75,6 +75,7 @@ def lib():
         build()
     L = ctypes.CDLL(_SO)
     L.or_threads.restype = _INT
+    L.or_set_threads.argtypes = [_INT]
     L.or_philox4x64.argtypes = [_U64, _U64, _U64]
     L.or_grid_tables.argtypes = [ctypes.c_uint64, _INT, _INT, _F32, _U64]
     L.or_grid_tables_rep.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _INT, _INT, _F32, _U64]
@@ -111,6 +112,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads of the parallel loops (exact nearest neighbours)."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads in the parallel loops from now on."""
+    lib().or_set_threads(int(n))
 
 
 def _f32(x):

@@ -44,6 +44,16 @@ int or_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from now on (n >= 1; no-op without OpenMP). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Purposes of the counter-based random streams (third counter word). */
 #define PURPOSE_GRID 1u
 #define PURPOSE_EMBED 2u
