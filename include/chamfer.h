@@ -237,7 +237,8 @@ int crude_nn(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d
  * estimate is the plain one of the (padded) sets; otherwise it is the sum,
  * in ascending key order, of the estimates of the parts (rows in ascending
  * order, the same eps, T, seed and options).  aux must then be NULL, and
- * the call synchronises the stream once (the host reads the partition).
+ * the call synchronises the stream (the host reads the partition; with
+ * several parts it also returns only after the parts' estimates).
  * Errors: as crude_nn, plus EINVAL if T < 0.
  */
 int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,

@@ -692,6 +692,12 @@ int estimate_reduced(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     std::copy(ra.begin(), ra.end(), rows.begin());
     std::copy(rb.begin(), rb.end(), rows.begin() + n_A);
     int32_t *drows = at<int32_t>(ws, ep.off_rows);
+    // the copy reads the host row list: whatever path leaves this function
+    // after it drains the stream first
+    struct DrainOnExit {
+        hipStream_t st;
+        ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+    } drain{st};
     CH_TRY(hipMemcpyAsync(drows, rows.data(), rows.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice, st));
     float *At = at<float>(ws, ep.off_At);
@@ -710,7 +716,6 @@ int estimate_reduced(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     }
     k_sum_slots<<<1, 64, 0, st>>>(slots, (int64_t)parts.size(), eta_out);
     CH_TRY(hipGetLastError());
-    CH_TRY(hipStreamSynchronize(st));  // the host row list is read by the copy above
     return CHAMFER_OK;
 }
 
