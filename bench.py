@@ -630,8 +630,9 @@ def main():
                          "(calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported (the path would "
+              "shard A by rows with B replicated, and one GPU runs one shard's kernels).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
