@@ -492,3 +492,49 @@ def test_retrieval_wide_and_lowp(ch, orc):
         assert e[i] == direct[0], i
     for i, v in zip(top_b, vals_b):
         np.testing.assert_allclose(v, orc.chamfer_symmetric_exact(A, cl[i], 2)[0], rtol=REL)
+
+
+def test_retrieval_nonfinite_cloud_and_edges(ch, orc):
+    """A cloud with a NaN coordinate gets a NaN estimate and ranks last, the
+    others keep their estimates; k = m and a single cloud work."""
+    banner("retrieval edges")
+    cl, qs, _ = workloads.retrieval_collection(seed=31, m=9, n_min=40, n_max=90, queries=1)
+    q = qs[0]
+    bad = [c.copy() for c in cl]
+    bad[4][7, 1] = np.nan
+    est, top, vals = ch.chamfer_retrieve(dev(q), [dev(B) for B in bad], 1, 0.2, 30, 5, 9)
+    e = host(est)
+    assert math.isnan(e[4]) and top[-1] == 4 and sorted(top) == list(range(9))
+    ref, _, _ = ch.chamfer_retrieve(dev(q), [dev(B) for B in cl], 1, 0.2, 30, 5, 9)
+    r = host(ref)
+    keep = [i for i in range(9) if i != 4]
+    assert np.array_equal(e[keep], r[keep])
+    est1, top1, vals1 = ch.chamfer_retrieve(dev(q), [dev(cl[2])], 1, 0.2, 30, 5, 1)
+    assert top1 == [0]
+    assert host(est1)[0] == pytest.approx(
+        orc.chamfer_symmetric_estimate(q, cl[2], 1, 0.2, 30, 5)[0], rel=REL)
+    assert vals1[0] == pytest.approx(orc.chamfer_symmetric_exact(q, cl[2], 1)[0], rel=REL)
+
+
+def test_misaligned_inputs(ch):
+    """Point sets starting 4 bytes past a 16-byte boundary (d a multiple of
+    4) take the scalar load paths and give the same results."""
+    banner("misaligned inputs")
+    A, B = clouds(700, 900, 16, seed=41)
+    def shifted(X):
+        buf = torch.empty(X.size + 1, dtype=torch.float32, device="cuda:0")
+        buf[1:] = dev(X.reshape(-1))
+        v = buf[1:].view(X.shape)
+        assert v.data_ptr() % 16 == 4
+        return v
+    for metric in (1, 2):
+        a0 = host(ch.chamfer_estimate(dev(A), dev(B), metric, 0.2, 0, 3)["eta"])
+        a1 = host(ch.chamfer_estimate(shifted(A), shifted(B), metric, 0.2, 0, 3)["eta"])
+        assert a0[0] == a1[0]
+        e0 = host(ch.chamfer_exact(dev(A), dev(B), metric)[0])
+        e1 = host(ch.chamfer_exact(shifted(A), shifted(B), metric)[0])
+        assert e0[0] == e1[0]
+        r0 = ch.chamfer_aspect_reduce(dev(A), dev(B), metric, 0.2, 3)
+        r1 = ch.chamfer_aspect_reduce(shifted(A), shifted(B), metric, 0.2, 3)
+        assert np.array_equal(host(r0["t"]), host(r1["t"]))
+        assert np.array_equal(host(r0["keys_A"]), host(r1["keys_A"]))
