@@ -538,3 +538,25 @@ def test_misaligned_inputs(ch):
         r1 = ch.chamfer_aspect_reduce(shifted(A), shifted(B), metric, 0.2, 3)
         assert np.array_equal(host(r0["t"]), host(r1["t"]))
         assert np.array_equal(host(r0["keys_A"]), host(r1["keys_A"]))
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("d", [241, 1000, 2048])
+def test_wide_points(ch, orc, metric, d):
+    """Wide points (the l1 hash reads rows from global memory above 240
+    coordinates; l2 above 256 leaves the matrix cores): keys, CrudeNN, the
+    estimate and exact CH as the oracle's."""
+    n_a, n_b = 300, 410
+    banner(f"wide metric={metric} d={d}")
+    A, B = clouds(n_a, n_b, d, seed=d + metric)
+    D, nn, sc = ch.crude_nn(dev(A), dev(B), metric, 0.2, 4)
+    ref = orc.crude_nn(A, B, metric, 0.2, 4)
+    assert np.array_equal(host(sc), ref["scale"])
+    assert np.array_equal(host(nn), ref["nn"])
+    assert np.array_equal(host(D).view(np.uint32), np.asarray(ref["D"], np.float32).view(np.uint32))
+    out = ch.chamfer_estimate(dev(A), dev(B), metric, 0.2, 0, 4)
+    r = orc.chamfer_estimate(A, B, metric, 0.2, 0, 4)
+    assert np.array_equal(host(out["sample_idx"]), r["idx"])
+    assert float(host(out["eta"])[0]) == pytest.approx(r["eta"], rel=REL)
+    ex = float(host(ch.chamfer_exact(dev(A), dev(B), metric)[0])[0])
+    assert ex == pytest.approx(orc.chamfer_exact(A, B, metric)[0], rel=REL)
