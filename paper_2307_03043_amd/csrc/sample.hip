@@ -208,19 +208,40 @@ __device__ __forceinline__ void estimate_final(const unsigned long long *__restr
     const uint64_t W = p->W;
     const int s = p->s;
     double acc = 0.0;
-    for (int64_t l = t; l < T; l += 256) {
-        const unsigned long long b = ro(best)[l];
-        const float v = __uint_as_float((uint32_t)(b >> 32));
-        const int32_t nn = (int32_t)(uint32_t)(b & 0xffffffffu);
-        float m = metric == CHAMFER_L2 ? sqrtf(v) : v;
-        if (status != CHAMFER_OK) m = __builtin_nanf("");
-        if (status == CHAMFER_OK && W != 0) {
-            const double w = (double)weight_of(ro(D)[ro(idx)[l]], s);
-            acc += ((double)W / w) * (double)m;
+    // kG terms per thread per round: their loads (best, idx, then D[idx])
+    // are issued together, then the terms are added in index order
+    constexpr int kG = 8;
+    for (int64_t l0 = t; l0 < T; l0 += 256 * kG) {
+        unsigned long long bv[kG];
+        int32_t ix[kG];
+        float dv[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int64_t l = l0 + (int64_t)g * 256;
+            bv[g] = l < T ? ro(best)[l] : 0ull;
+            ix[g] = l < T ? ro(idx)[l] : 0;
         }
-        if (aux.sample_min) aux.sample_min[l] = (status == CHAMFER_OK && W == 0) ? 0.0f : m;
-        if (aux.sample_nn) aux.sample_nn[l] = (W == 0) ? 0 : nn;
-        if (aux.sample_idx) aux.sample_idx[l] = idx[l];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int64_t l = l0 + (int64_t)g * 256;
+            dv[g] = (l < T && status == CHAMFER_OK && W != 0) ? ro(D)[ix[g]] : 0.0f;
+        }
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int64_t l = l0 + (int64_t)g * 256;
+            if (l >= T) break;
+            const float v = __uint_as_float((uint32_t)(bv[g] >> 32));
+            const int32_t nn = (int32_t)(uint32_t)(bv[g] & 0xffffffffu);
+            float m = metric == CHAMFER_L2 ? sqrtf(v) : v;
+            if (status != CHAMFER_OK) m = __builtin_nanf("");
+            if (status == CHAMFER_OK && W != 0) {
+                const double w = (double)weight_of(dv[g], s);
+                acc += ((double)W / w) * (double)m;
+            }
+            if (aux.sample_min) aux.sample_min[l] = (status == CHAMFER_OK && W == 0) ? 0.0f : m;
+            if (aux.sample_nn) aux.sample_nn[l] = (W == 0) ? 0 : nn;
+            if (aux.sample_idx) aux.sample_idx[l] = ix[g];
+        }
     }
     red[t] = acc;
     __syncthreads();
