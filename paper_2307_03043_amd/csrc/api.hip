@@ -192,7 +192,11 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
                   hipStream_t st) {
     DevParams *p = at<DevParams>(ws, pl.off_params);
     uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
-    CH_TRY(launch_init_params(p, lohi, pl.d, st));
+    // parameter block and the structure-0 shifts and multipliers in one
+    // launch; the tables are emptied after the min/max pass (emptying them
+    // first evicts A and B from the memory-side cache at 10^6 points)
+    CH_TRY(launch_setup(p, lohi, pl.d, seed, pl.L, pl.kh, at<float>(ws, pl.off_zfrac),
+                        at<uint64_t>(ws, pl.off_mult), nullptr, 0, st));
     if (pl.metric == CHAMFER_L2) {
         // The embedding matrix is drawn on the host (it needs log and cos in
         // double precision) and uploaded transposed, [d][ke].
@@ -202,8 +206,6 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
         CH_TRY(hipMemcpyAsync(at<float>(ws, pl.off_embed), zt.data(), zt.size() * sizeof(float),
                               hipMemcpyHostToDevice, st));
     }
-    CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, at<float>(ws, pl.off_zfrac),
-                              at<uint64_t>(ws, pl.off_mult), 0, st));
     CH_TRY(launch_minmax(A, pl.nA, pl.d, lohi, p, st));
     CH_TRY(launch_minmax(B, pl.nB, pl.d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, pl.d, p, st));
@@ -225,6 +227,7 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
                int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,
                float *nb2 = nullptr) {
     CH_TRY(mark(ev, 0, st));
+    const int W = pl.window;
     int rc = hash_prologue(pl, A, B, seed, ws, st);
     if (rc) return rc;
     DevParams *p = at<DevParams>(ws, pl.off_params);
@@ -233,7 +236,6 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
     const float *emb = at<float>(ws, pl.off_embed);
     float *zf = at<float>(ws, pl.off_zfrac);
     uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
-    const int W = pl.window;
     for (int r = 0; r < pl.reps; ++r) {
         if (r > 0) CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, zf, mt, r, st));
         CH_TRY(launch_tables_empty(tables, pl.L, pl.log2cap, W, st));

@@ -306,6 +306,33 @@ int64_t table_fill_blocks(size_t count) {
     return (int64_t)blocks;
 }
 
+// Parameter block, lo/hi, shifts and multipliers of structure 0 and (tables
+// non-null) the empty W = 1 tables in one launch: the three independent
+// bodies over consecutive block ranges.
+__global__ __launch_bounds__(256) void k_setup(DevParams *p, uint32_t *lohi, int d, uint64_t seed,
+                                               int L, int kh, float *zfrac, uint64_t *mult,
+                                               Bucket *tables, size_t count, int nb_init,
+                                               int nb_grid, int nb_fill) {
+    const int64_t b = blockIdx.x;
+    if (b < nb_init) {
+        init_params(p, lohi, d, Blk{b, nb_init});
+    } else if (b < nb_init + nb_grid) {
+        grid_tables(seed, L, kh, zfrac, mult, 0, Blk{b - nb_init, nb_grid});
+    } else {
+        table_fill(tables, count, Blk{b - nb_init - nb_grid, nb_fill});
+    }
+}
+
+hipError_t launch_setup(DevParams *p, uint32_t *lohi, int d, uint64_t seed, int L, int kh,
+                        float *zfrac, uint64_t *mult, Bucket *tables, size_t count,
+                        hipStream_t st) {
+    const int nb_init = (int)init_blocks(d), nb_grid = (int)grid_table_blocks(L, kh);
+    const int nb_fill = tables ? (int)table_fill_blocks(count) : 0;
+    k_setup<<<(unsigned)(nb_init + nb_grid + nb_fill), 256, 0, st>>>(
+        p, lohi, d, seed, L, kh, zfrac, mult, tables, count, nb_init, nb_grid, nb_fill);
+    return hipGetLastError();
+}
+
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
     k_table_fill<<<(unsigned)table_fill_blocks(count), 256, 0, st>>>(tables, count);
     return hipGetLastError();

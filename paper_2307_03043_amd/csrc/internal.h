@@ -307,6 +307,11 @@ __device__ __forceinline__ void batch_loop(const Batch *__restrict__ bt, int sta
 // All launchers enqueue on `st` and return hipGetLastError().
 
 hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t st);
+// init_params, the rep-0 grid tables and (tables non-null) the empty W = 1
+// tables of `count` buckets, in one launch
+hipError_t launch_setup(DevParams *p, uint32_t *lohi, int d, uint64_t seed, int L, int kh,
+                        float *zfrac, uint64_t *mult, Bucket *tables, size_t count,
+                        hipStream_t st);
 // rep: index of the independent LSH structure (0 for the single one)
 hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
                               int rep, hipStream_t st);
