@@ -135,6 +135,9 @@ def measured_traffic(workload, kernel_ms):
 # Calls timed with stage events for the per-stage split and p50/p99 latency.
 LATENCY_CALLS = 100
 
+# Rows of A in the CPU oracle's timed brute-force sample.
+CPU_BRUTE_ROWS = 500
+
 # Points per set for the CPU oracle's timed sample (full workload when smaller).
 CPU_SAMPLE_POINTS = 250_000
 
@@ -157,9 +160,17 @@ def cpu_baseline(args, A, B, metric, eps, T, L, seed):
     oracle.chamfer_estimate(As[:n1], Bs[:m1], metric, eps, T, seed, n_scales=L)
     dt1 = time.perf_counter() - t0
     oracle.set_threads(cores)
+    # the oracle's float64 brute force on a sample of rows of A, all of B
+    rows = np.arange(0, n_a, max(1, n_a // CPU_BRUTE_ROWS), dtype=np.int32)[:CPU_BRUTE_ROWS]
+    t0 = time.perf_counter()
+    oracle.nn_f64(As, Bs, metric, rows=rows)
+    dtb = time.perf_counter() - t0
     what = (f"full workload (|A|={n_a}, |B|={n_b})" if full else
             f"the first {n_a} points of A and {n_b} of B (same generator)")
     return dict(value=(n_a + n_b) / dt, unit="points/s", cores=cores,
+                brute_force={"rows": int(len(rows)), "seconds": dtb,
+                             "full_seconds_extrapolated": dtb * n_a / max(1, len(rows)),
+                             "kind": "float64, all OpenMP threads"},
                 kind="oracle", seconds=dt, host_cpu=host_cpu(), nproc=os.cpu_count(),
                 single_thread={"points_per_s": (n1 + m1) / dt1, "seconds": dt1,
                                "sample": f"|A|={n1}, |B|={m1}, same eps, T and L"},
