@@ -17,7 +17,6 @@ runs on one GPU.
 import argparse
 import ctypes
 import json
-import math
 import os
 import sys
 import time

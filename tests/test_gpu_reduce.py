@@ -5,7 +5,6 @@ estimate after the reduction within the estimator's tolerance (one part:
 bit-identical to the plain estimate; several parts: the sum of the parts'
 estimates)."""
 
-import math
 
 import numpy as np
 import pytest
