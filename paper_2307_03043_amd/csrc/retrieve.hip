@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -101,6 +103,42 @@ struct Staging {
             if (e) (void)hipEventDestroy(e);
     }
 };
+
+// Side streams of the exact re-rank, created once per device and kept for
+// the process (default priority, non-blocking); the mutex serialises the
+// fork/join sequences of concurrent calls.
+constexpr int kRerankStreams = 3;
+struct SideStreams {
+    std::mutex mu;
+    int device = -1;
+    hipStream_t s[kRerankStreams] = {};
+    hipEvent_t fork = nullptr, join[kRerankStreams] = {};
+    bool ready() {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return false;
+        if (device == dev) return true;
+        if (device >= 0) return false;  // one device per set (see side_streams)
+        for (int j = 0; j < kRerankStreams; ++j)
+            if (hipStreamCreateWithFlags(&s[j], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&join[j], hipEventDisableTiming) != hipSuccess)
+                return false;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
+        device = dev;
+        return true;
+    }
+};
+
+// The set of the current device.
+SideStreams &side_streams() {
+    static std::mutex mu;
+    static std::map<int, SideStreams *> sets;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> hold(mu);
+    SideStreams *&set = sets[dev];
+    if (!set) set = new SideStreams();  // lives for the process
+    return *set;
+}
 
 #define CH_TRY(expr)                                    \
     do {                                                \
@@ -217,15 +255,36 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
         return h_est[x] < h_est[y] || (h_est[x] == h_est[y] && x < y);
     });
 
-    // 3. exact symmetric CH of the candidates (back to back on the stream,
-    // each into its own [3] slot, one copy back), ranked
-    for (int c = 0; c < k; ++c) {
-        const int i = order[c];
-        const float *B = Bs + (size_t)offsets[i] * d;
-        const int64_t nB = offsets[i + 1] - offsets[i];
-        if ((rc = chamfer_exact_symmetric(A, B, n_A, nB, d, metric, sym + 3 * c, &ox,
-                                          base + lo.off_jobs, lo.per_job_ws, stream)))
+    // 3. exact symmetric CH of the candidates, each into its own [3] slot:
+    // the candidates are dealt to side streams (forked from and joined back
+    // into the caller's stream), stream j using job workspace slot j, so the
+    // small kernels of several candidates run at once; one copy back
+    {
+        SideStreams &side = side_streams();
+        std::lock_guard<std::mutex> hold(side.mu);
+        const int ns = std::min(kRerankStreams, lo.slots);
+        if (!side.ready()) return CHAMFER_EHIP;
+        CH_TRY(hipEventRecord(side.fork, st));
+        for (int j = 0; j < ns; ++j) CH_TRY(hipStreamWaitEvent(side.s[j], side.fork, 0));
+        for (int c = 0; c < k && rc == CHAMFER_OK; ++c) {
+            const int i = order[c], j = c % ns;
+            const float *B = Bs + (size_t)offsets[i] * d;
+            const int64_t nB = offsets[i + 1] - offsets[i];
+            rc = chamfer_exact_symmetric(A, B, n_A, nB, d, metric, sym + 3 * c, &ox,
+                                         base + lo.off_jobs + (size_t)j * lo.per_job_ws,
+                                         lo.per_job_ws, side.s[j]);
+        }
+        for (int j = 0; j < ns; ++j) {
+            if (hipEventRecord(side.join[j], side.s[j]) != hipSuccess ||
+                hipStreamWaitEvent(st, side.join[j], 0) != hipSuccess) {
+                for (int q = 0; q < ns; ++q) (void)hipStreamSynchronize(side.s[q]);
+                return CHAMFER_EHIP;
+            }
+        }
+        if (rc) {
+            (void)hipStreamSynchronize(st);
             return rc;
+        }
     }
     std::vector<double> v((size_t)3 * k);
     CH_TRY(hipMemcpyAsync(v.data(), sym, v.size() * sizeof(double), hipMemcpyDeviceToHost, st));
