@@ -159,9 +159,9 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_best = take((size_t)nrow * sizeof(uint64_t));
     pl.off_partial = take((size_t)(nn_finalize_blocks(nrow) + 1) * sizeof(double));
     pl.off_nb2 = take(mfma_supported(d, metric) ? (size_t)nB * sizeof(float) : 0);
-    pl.off_fallback = take(0);
     // low precision: cast rows of B and of the queries, scales and norms
     const bool lp = lowp_supported(d, metric, pl.precision);
+    pl.off_bsplit = take(!lp && mfma_supported(d, metric) ? split_table_bytes(nB, d) : 0);
     const size_t rb = lp ? lowp_row_bytes(d, pl.precision) : 0;
     pl.off_bq = take(rb * (size_t)nB);
     pl.off_xq = take(rb * (size_t)nrow);
@@ -268,6 +268,12 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
         CH_TRY(launch_cast_rows(pl.precision, X, rows, nx, pl.d, xq, xsc, xn2, p, st));
         CH_TRY(launch_nnmin_lowp(pl.precision, xq, xsc, nx, X, rows, bq, bsc, bn2, B, nB, pl.d,
                                  best, p, st));
+        return CHAMFER_OK;
+    }
+    if (nb2 != nullptr && mfma_supported(pl.d, pl.metric)) {
+        uint16_t *bs = at<uint16_t>(ws, pl.off_bsplit);
+        CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
+        CH_TRY(launch_nnmin_split(X, rows, nx, B, bs, nB, pl.d, best, nb2, p, st));
         return CHAMFER_OK;
     }
     CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, nb2, p, st));

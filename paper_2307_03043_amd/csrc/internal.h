@@ -100,7 +100,7 @@ struct Plan {
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
-        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_fallback,
+        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit,
         off_bq, off_xq, off_lpf, total;
 };
 
@@ -353,6 +353,16 @@ bool mfma_supported(int d, int metric);
 hipError_t launch_nnmin_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
                              int64_t nB, int d, unsigned long long *best, const float *nb2,
                              DevParams *p, hipStream_t st);
+// The same exact l2 nearest neighbours on the BF16 matrix cores with a
+// two-term split of every coordinate: launch_split_rows fills the split table
+// of B (split_table_bytes), then launch_nnmin_split needs it, nb2 and
+// p->b2max_bits.
+size_t split_table_bytes(int64_t nB, int d);
+hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out,
+                             const DevParams *p, hipStream_t st);
+hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
+                              const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
+                              const float *nb2, DevParams *p, hipStream_t st);
 // Low-precision (BF16 / FP8-E4M3) l2 nearest neighbours with float32 re-rank.
 int lowp_dpad(int d, int precision);
 bool lowp_supported(int d, int metric, int precision);
@@ -396,6 +406,7 @@ struct NNGeom {
 // target: workgroups the split of B aims for (0: the direct-launch target)
 NNGeom valu_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
 NNGeom mfma_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
+NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
 constexpr int64_t kValuTargetWGs = 4096;
 NNGeom lowp_geom(int64_t nx, int64_t nB, int d, int precision);
 constexpr int kMaxLdsL1Dim = 240;  // widest l1 tile staged in LDS by the hash

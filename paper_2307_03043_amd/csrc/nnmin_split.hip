@@ -1,0 +1,426 @@
+// Exact l2 nearest neighbours on the BF16 matrix cores (gfx950
+// v_mfma_f32_16x16x32_bf16) with every float32 coordinate split in two
+// BF16 terms, returning the same canonical float32 result as the FP32 MFMA
+// and VALU forms: the minimum over b of (fma-chain accumulator of
+// (x_k - b_k)^2 in ascending k, b), ties to the lower b.
+//
+// Split.  v = h + m + r with h = bf16(v), m = bf16(v - h) (round to nearest
+// even; v - h is exact in float32), so |m| <= 2^-8 (1 + 2^-8) |v| and
+// |r| <= 2^-16 |v|.  B is split once per call into a row-major table of
+// [h[0..DP), m[0..DP)] per row (zero padded); each query is split in
+// registers.
+//
+// Scores.  s(b) = |b|^2 - 2 x~.b~ with x~.b~ = xh.bh + xm.bh + xh.bm (three
+// BF16 MFMAs per 32 coordinates, TERMS = 3) or that plus xm.bm (TERMS = 4).
+// BF16 products are exact in float32.  The dropped terms sum to at most
+// c_tr |x| |b| (Cauchy-Schwarz over k): (xh + xm).rb + rx.(bh + bm) + rx.rb
+// gives 2.01 * 2^-16 and xm.bm adds at most 1.02 * 2^-16.  With adders that
+// round to nearest (the model of the FP32 MFMA form), the float32
+// accumulation errs by at most u per addition times the sum of the terms'
+// magnitudes.  TERMS = 3 accumulates all 3 DP products in one register
+// (1.02 |x||b| of magnitude): c_rel = (3 DP + 8) u 1.1.  TERMS = 4 keeps the
+// leading products xh.bh (DP additions, 1.008 |x||b|) apart from the three
+// small ones (3 DP additions, 0.008 |x||b|) and adds the two before the
+// score: c_rel = (DP + 8) u 1.1.  So the computed score is within
+//   E = c_abs + c_den (|x| + |b|max) + c_rel (|b|max^2 + 2 |x| |b|max)
+//       + 2 c_tr 1.1 |x| |b|max
+// of |b|^2 - 2 x.b, c_abs and c_den absorbing flushes of subnormal operands,
+// products and sums to zero.  TERMS = 4 has the smaller E (fewer exact
+// rescans) and TERMS = 3 the fewer registers (four wavefronts per SIMD at
+// d <= 128); launches over many queries take TERMS = 4.
+//
+// Candidates, re-rank, certificate and rescan are those of the FP32 MFMA
+// form with this E: each lane keeps its best score (with its b) and its
+// second-best score per query; the four lane-group bests are re-evaluated
+// with the canonical float32 distance; a (query, chunk) pair whose
+// non-candidates cannot be proved worse than the best candidate (or the best
+// already recorded) is rescanned exactly by the whole wavefront; chunks merge
+// with a 64-bit atomicMin of (accumulator bits << 32 | b).  Overflow of any
+// norm makes E infinite, which sends every chunk to the exact rescan.
+#include <cfloat>
+#include <cmath>
+
+#include "internal.h"
+
+namespace chamfer {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kSplitTileRows = 32;  // B rows per LDS tile (two 16-row MFMA blocks)
+#ifndef CH_SPLIT_TARGET_WGS
+#define CH_SPLIT_TARGET_WGS 4096
+#endif
+#ifndef CH_SPLIT_NB
+#define CH_SPLIT_NB 1
+#endif
+constexpr int kSplitTargetWGs = CH_SPLIT_TARGET_WGS;  // workgroups a launch aims for
+constexpr int kSplitNB = CH_SPLIT_NB;                 // 16-query blocks per wavefront
+#ifndef CH_SPLIT_MANY_QUERIES
+#define CH_SPLIT_MANY_QUERIES 16384
+#endif
+// Launches with at least this many queries take the four-product form: they
+// split B into few, long chunks, where near-ties inside a chunk (and so
+// exact rescans, each reading the whole chunk) are frequent.
+constexpr int64_t kSplitManyQueries = CH_SPLIT_MANY_QUERIES;
+
+__host__ __device__ inline int split_dpad(int d) {
+    return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
+}
+
+size_t split_table_bytes(int64_t nB, int d) { return (size_t)nB * split_dpad(d) * 4; }
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// (h, m) of v as BF16 bit patterns.
+__device__ __forceinline__ void split2(float v, uint32_t &h, uint32_t &m) {
+    h = bf16_rne_bits(v);
+    m = bf16_rne_bits(v - __uint_as_float(h << 16));
+}
+
+__device__ __forceinline__ unsigned long long pack_sp(float v, int64_t b) {
+    return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(uint32_t)b;
+}
+
+__device__ __forceinline__ float unpack_sp(unsigned long long p) {
+    const uint32_t hi = (uint32_t)(p >> 32);
+    return hi == 0xffffffffu ? INFINITY : __uint_as_float(hi);
+}
+
+// Split table of B: thread t handles 4 coordinates of one row.
+__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ B, int64_t nB,
+                                                    int d, int dp, uint16_t *out,
+                                                    const DevParams *p) {
+    if (p->status != CHAMFER_OK) return;
+    const int per_row = dp / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nB * per_row) return;
+    const int64_t r = t / per_row;
+    const int k0 = (int)(t - r * per_row) * 4;
+    const auto *b = ro(B) + r * d;
+    uint32_t h[4], m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float v = k0 + i < d ? b[k0 + i] : 0.0f;
+        split2(v, h[i], m[i]);
+    }
+    uint16_t *row = out + (size_t)r * (2 * dp);
+    *reinterpret_cast<uint2 *>(row + k0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    *reinterpret_cast<uint2 *>(row + dp + k0) =
+        make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
+}
+
+hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out, const DevParams *p,
+                             hipStream_t st) {
+    if (nB <= 0) return hipSuccess;
+    const int dp = split_dpad(d);
+    const int64_t threads = nB * (dp / 4);
+    k_split_rows<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(B, nB, d, dp, out, p);
+    return hipGetLastError();
+}
+
+template <int DP, int NB, int TERMS>
+__device__ __forceinline__ void nnmin_l2_split(
+    const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
+    const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
+    DevParams *p, Blk blk) {
+    constexpr int KQ = DP / 4;                   // coordinates per 16-lane group
+    constexpr int NS = KQ / 8;                   // MFMA steps (8 coordinates per lane)
+    constexpr int RB = 4 * DP;                   // bytes per split row (h then m)
+    constexpr int LDR = RB + 16;                 // padded LDS row (bytes)
+    constexpr int NV = kSplitTileRows * RB / 16;  // 16-byte units per tile
+    constexpr int PER_T = (NV + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kSplitTileRows * LDR];
+    __shared__ float tn2[kSplitTileRows];
+
+    if (p->status != CHAMFER_OK) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    int cb;
+    int64_t qb;
+    chunk_major(blk.id, (nx + 64 * NB - 1) / (64 * NB), nchunk, cb, qb);
+    const int64_t qbase = (qb * 4 + wave) * (16 * NB);
+    const int64_t b0 = (int64_t)cb * chunk;
+    const int64_t b1 = min(nB, b0 + chunk);
+    if (b0 >= b1) return;  // uniform over the workgroup
+    const bool wave_active = qbase < nx;
+
+    // Query fragments: lane (g, j) holds coordinates [g KQ, (g+1) KQ) of
+    // query qbase + nb 16 + j, split, 8 per MFMA step; padding is zero.
+    uint4 qh[NB][NS], qm[NB][NS];
+    float qn2[NB];
+    int64_t qrow[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int64_t qi = qbase + nb * 16 + j;
+        const int64_t r = qi < nx ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
+        qrow[nb] = r;
+        const auto *xr = ro(X) + r * d;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            uint32_t h[8], m[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = g * KQ + 8 * s + e;
+                const float v = k < d ? xr[k] : 0.0f;
+                s2 = fmaf(v, v, s2);
+                split2(v, h[e], m[e]);
+            }
+            qh[nb][s] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                   h[6] | (h[7] << 16));
+            qm[nb][s] = make_uint4(m[0] | (m[1] << 16), m[2] | (m[3] << 16), m[4] | (m[5] << 16),
+                                   m[6] | (m[7] << 16));
+        }
+        s2 += __shfl_xor(s2, 16);
+        s2 += __shfl_xor(s2, 32);
+        qn2[nb] = s2;
+    }
+
+    float bestv[NB], second[NB];
+    int32_t bidx[NB];  // B has at most 2^31 - 1 rows
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        bestv[nb] = INFINITY;
+        second[nb] = INFINITY;
+        bidx[nb] = (int32_t)b0;
+    }
+
+    // Register prefetch of one tile (PER_T 16-byte units per thread) and its norms.
+    uint4 pf[PER_T];
+    float pn2 = INFINITY;
+    auto fetch = [&](int64_t t0) {
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int v = tid + i * 256;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (v < NV) {
+                const int row = v / (RB / 16);
+                const int u = v - row * (RB / 16);
+                if (t0 + row < b1)
+                    val = ld(reinterpret_cast<const CH_RO uint4 *>(
+                                 ro(Bs) + (size_t)(t0 + row) * (2 * DP)) + u);
+            }
+            pf[i] = val;
+        }
+        if (tid < kSplitTileRows) pn2 = (t0 + tid < b1) ? ro(nb2)[t0 + tid] : INFINITY;
+    };
+
+    int64_t t0 = b0;
+    fetch(t0);
+    for (;;) {
+        __syncthreads();  // the previous tile is no longer being read
+#pragma unroll
+        for (int i = 0; i < PER_T; ++i) {
+            const int v = tid + i * 256;
+            if (v < NV) {
+                const int row = v / (RB / 16);
+                const int u = v - row * (RB / 16);
+                *reinterpret_cast<uint4 *>(&tile[row * LDR + u * 16]) = pf[i];
+            }
+        }
+        if (tid < kSplitTileRows) tn2[tid] = pn2;
+        __syncthreads();
+        const int64_t next = t0 + kSplitTileRows;
+        if (next < b1) fetch(next);
+
+        if (wave_active) {
+            // TERMS = 3: every product into hi; TERMS = 4: the small ones into lo
+            constexpr int NL = TERMS == 4 ? 2 : 1;
+            v4f hi[2][NB], lo[NL][NB];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) hi[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int m = 0; m < NL; ++m)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) lo[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                v8bf ah[2], am[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const uint8_t *ap = &tile[(16 * m + j) * LDR + (g * KQ + 8 * s) * 2];
+                    ah[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap));
+                    am[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap + 2 * DP));
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const v8bf xh = __builtin_bit_cast(v8bf, qh[nb][s]);
+                    const v8bf xm = __builtin_bit_cast(v8bf, qm[nb][s]);
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+                        hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xh, hi[m][nb],
+                                                                            0, 0, 0);
+                    if constexpr (TERMS == 4) {
+#pragma unroll
+                        for (int m = 0; m < 2; ++m) {
+                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
+                                                                                lo[m][nb], 0, 0, 0);
+                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
+                                                                                lo[m][nb], 0, 0, 0);
+                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xm,
+                                                                                lo[m][nb], 0, 0, 0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < 2; ++m)
+                            hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
+                                                                                hi[m][nb], 0, 0, 0);
+#pragma unroll
+                        for (int m = 0; m < 2; ++m)
+                            hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
+                                                                                hi[m][nb], 0, 0, 0);
+                    }
+                }
+            }
+            // Lane (g, j) holds rows 16m + 4g + r of the tile for query j.
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int lr = 16 * m + 4 * g + r;
+                    const float n2 = tn2[lr];
+                    const int32_t brow = (int32_t)(t0 + lr);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        float dot = hi[m][nb][r];
+                        if constexpr (TERMS == 4) dot += lo[m][nb][r];
+                        const float sc = fmaf(dot, -2.0f, n2);
+                        const float bv = bestv[nb];
+                        second[nb] = fminf(second[nb], fmaxf(bv, sc));
+                        const bool lt = sc < bv;
+                        bestv[nb] = lt ? sc : bv;
+                        bidx[nb] = lt ? brow : bidx[nb];
+                    }
+                }
+        }
+        t0 = next;
+        if (t0 >= b1) break;
+    }
+    if (!wave_active) return;
+
+    // ---- re-rank and certificate, per block of 16 queries ----
+    constexpr double kU = 1.0 / 16777216.0;                       // 2^-24
+    constexpr double kTiny = 1.1754943508222875e-38;               // 2^-126
+    const double rho = (double)(d + 4) * kU * 1.1;
+    const double crel = (double)((TERMS == 4 ? 1 : 3) * DP + 8) * kU * 1.1;
+    const double ctr = (TERMS == 4 ? 2.01 : 3.03) / 65536.0 * 1.1;
+    const double cabs = (double)(20 * DP + 16) * kTiny * 1.1;
+    const double cden = 8.0 * sqrt((double)DP) * kTiny * 1.1;
+    const double b2m = (double)__uint_as_float(p->b2max_bits) * (1.0 + rho);
+    const double bm = sqrt(b2m);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int64_t qi = qbase + nb * 16 + j;
+        const bool valid = qi < nx;
+        // recorded best for the query, read once (group 0) and shared
+        float gacc = INFINITY;
+        if (g == 0 && valid)
+            gacc = unpack_sp(__hip_atomic_load(&best[qi], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT));
+        gacc = __shfl(gacc, j);
+        float bmin = bestv[nb];
+        bmin = fminf(bmin, __shfl_xor(bmin, 16));
+        bmin = fminf(bmin, __shfl_xor(bmin, 32));
+        float cut = second[nb];
+        cut = fminf(cut, __shfl_xor(cut, 16));
+        cut = fminf(cut, __shfl_xor(cut, 32));
+        const double xn2 = (double)qn2[nb];
+        const double xabs = sqrt(xn2 * (1.0 + rho));
+        const double E = cabs + cden * (xabs + bm) + crel * (b2m + 2.0 * xabs * bm) +
+                         2.0 * ctr * xabs * bm;
+        const double xlo = xn2 * (1.0 - rho);
+        const double lb_all = (1.0 - rho) * ((double)bmin - E + xlo);
+        const bool need = valid && !(lb_all > (double)gacc);
+        unsigned long long mine = ~0ull;
+        if (need && bestv[nb] < INFINITY)
+            mine = pack_sp(canon_acc<CHAMFER_L2>(X + qrow[nb] * d, B + (int64_t)bidx[nb] * d, d),
+                           bidx[nb]);
+        mine = min(mine, (unsigned long long)__shfl_xor(mine, 16));
+        mine = min(mine, (unsigned long long)__shfl_xor(mine, 32));
+        const double thr = fmin((double)unpack_sp(mine), (double)gacc);
+        const double lb_nc = (1.0 - rho) * ((double)cut - E + xlo);
+        const bool rescan = need && !(lb_nc > thr);
+        if (need && g == 0 && mine != ~0ull) atomicMin(&best[qi], mine);
+        unsigned long long mask = __ballot(rescan && g == 0);
+        while (mask) {
+            const int jj = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            const int64_t q2 = qbase + nb * 16 + jj;
+            const int64_t xr = rows ? (int64_t)rows[q2] : q2;
+            unsigned long long lb = ~0ull;
+            for (int64_t b = b0 + lane; b < b1; b += 64)
+                lb = min(lb, pack_sp(canon_acc<CHAMFER_L2>(X + xr * d, B + b * d, d), b));
+            for (int off = 32; off > 0; off >>= 1)
+                lb = min(lb, (unsigned long long)__shfl_xor(lb, off));
+            if (lane == 0) {
+                atomicMin(&best[q2], lb);
+                atomicAdd(&p->fallbacks, 1u);
+            }
+        }
+    }
+}
+
+template <int DP, int NB, int TERMS>
+__global__ __launch_bounds__(256) void k_nnmin_l2_split(
+    const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
+    const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
+    DevParams *p) {
+    nnmin_l2_split<DP, NB, TERMS>(X, rows, nx, B, Bs, nB, d, nb2, chunk, nchunk, best, p,
+                                  grid_blk());
+}
+
+NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target) {
+    (void)d;
+    const int64_t per_wg = 64 * kSplitNB;
+    const int64_t nq = (nx + per_wg - 1) / per_wg;
+    if (target <= 0) target = kSplitTargetWGs;
+    int64_t nc = (target + nq - 1) / nq;
+    const int64_t cmin = (nB + 8191) / 8192, cmax = (nB + 255) / 256;
+    if (nc < cmin) nc = cmin;
+    if (nc > cmax) nc = cmax;
+    if (nc < 1) nc = 1;
+    if (nc > 1) nc = (nc + 7) / 8 * 8;  // one chunk's workgroups share an XCD
+    NNGeom g;
+    g.chunk = (nB + nc - 1) / nc;
+    g.nchunk = (int)((nB + g.chunk - 1) / g.chunk);
+    g.blocks = nq * g.nchunk;
+    return g;
+}
+
+template <int DP>
+static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
+                           const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
+                           const float *nb2, DevParams *p, hipStream_t st) {
+    const NNGeom g = split_geom(nx, nB, d, 0);
+    if (nx >= kSplitManyQueries)
+        k_nnmin_l2_split<DP, kSplitNB, 4><<<(unsigned)g.blocks, 256, 0, st>>>(
+            X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
+    else
+        k_nnmin_l2_split<DP, kSplitNB, 3><<<(unsigned)g.blocks, 256, 0, st>>>(
+            X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
+                              const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
+                              const float *nb2, DevParams *p, hipStream_t st) {
+    if (nx <= 0) return hipSuccess;
+    switch (split_dpad(d)) {
+        case 32: return go_split<32>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
+        case 64: return go_split<64>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
+        case 128: return go_split<128>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
+        default: return go_split<256>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
+    }
+}
+
+}  // namespace chamfer
