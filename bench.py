@@ -30,7 +30,6 @@ METRIC_NAME = "Chamfer points/s at ε=0.1 vs GPU brute force; %HBM/MFMA peak; p5
 
 # MI355X published peaks.
 HBM_PEAK_GBS = 8000.0
-FP32_MFMA_TFLOPS = 157.3
 FP32_VECTOR_TFLOPS = 157.3   # 256 CUs x 256 FP32 flops/clk x 2.4 GHz
 BF16_MFMA_TFLOPS = 2500.0
 FP8_MFMA_TFLOPS = 5000.0
@@ -98,13 +97,19 @@ class HipEvents:
 
 def algorithmic_sample_pass(metric, T, n_b, d):
     """Work of the exact pass over the draws: T * n_B * d coordinate terms.
-    l2 (12 <= d <= 256) runs on FP32 MFMA: 2 flops (one multiply-add of
-    x.b) per term.  l1 runs on the vector ALU: 2 flops (subtract, add |t|)
-    per term, against the FP32 vector peak."""
+    l2 (12 <= d <= 256) runs on the BF16 matrix cores: 2 flops (one
+    multiply-add of x.b) per term, each computed as three BF16 products of
+    the two-term split of the coordinates (four when T >= 16384), so the
+    peak is the BF16 MFMA peak and the form's own ceiling is that peak over
+    the product count.  l1 runs on the vector ALU: 2 flops (subtract, add
+    |t|) per term, against the FP32 vector peak."""
     elems = float(T) * n_b * d
     if metric == 2 and 12 <= d <= 256:
-        return dict(bound="mfma", unit="TFLOP/s", ops=2.0 * elems, peak=FP32_MFMA_TFLOPS,
-                    note="2 flops (x.b multiply-add) per coordinate term on FP32 MFMA")
+        products = 4 if T >= 16384 else 3
+        return dict(bound="mfma", unit="TFLOP/s", ops=2.0 * elems, peak=BF16_MFMA_TFLOPS,
+                    products=products,
+                    note=f"2 flops (x.b multiply-add) per coordinate term, computed as {products} "
+                         "BF16 MFMA products of the two-term split coordinates")
     if metric == 2:
         return dict(bound="alu", unit="TFLOP/s", ops=3.0 * elems, peak=FP32_VECTOR_TFLOPS,
                     note="3 FP32 flops (subtract, fma) per coordinate term on the vector ALU")
@@ -740,6 +745,10 @@ def main():
                 "frac": achieved / work["peak"],
                 "traffic": measured_traffic(args.workload, kernel_ms), "kernel_ms": kernel_ms,
                 "algorithmic": work["note"]}
+    if "products" in work:
+        roofline["kernel"] = "k_nnmin_l2_split (exact pass over the T draws)"
+        roofline["mfma_dtype"] = "bf16"
+        roofline["frac_of_split_ceiling"] = achieved * work["products"] / work["peak"]
 
     result = {
         "metric": METRIC_NAME,

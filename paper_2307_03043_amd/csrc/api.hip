@@ -223,6 +223,8 @@ hipError_t mark(void **ev, int i, hipStream_t st) {
 // structures (reps) the tables are rebuilt for each structure r (grid stream
 // word r) and each probe keeps the better of its candidate and the stored
 // one; with a window W the tables hold W points per bucket.
+// nb2 given: the hash of B also fills |b|^2 and p->b2max_bits (inputs of the
+// l2 exact pass).
 int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
                int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,
                float *nb2 = nullptr) {
@@ -254,11 +256,12 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
 }
 
 // Exact pass over queries (rows of X, or X[rows[q]]): the low-precision
-// form when requested and supported, else the float32 form (MFMA for l2
-// when nb2 is given, vector ALU otherwise).
+// form when requested and supported, else the float32 result (split-BF16
+// matrix cores for l2 when nb2 is given, vector ALU otherwise).  split_ready:
+// the split table of B is already in the workspace.
 int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64_t nx,
             const float *B, int64_t nB, unsigned long long *best, float *nb2, DevParams *p,
-            hipStream_t st) {
+            hipStream_t st, bool split_ready = false) {
     if (lowp_supported(pl.d, pl.metric, pl.precision)) {
         uint8_t *bq = at<uint8_t>(ws, pl.off_bq);
         uint8_t *xq = at<uint8_t>(ws, pl.off_xq);
@@ -272,7 +275,7 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
     }
     if (nb2 != nullptr && mfma_supported(pl.d, pl.metric)) {
         uint16_t *bs = at<uint16_t>(ws, pl.off_bsplit);
-        CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
+        if (!split_ready) CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
         CH_TRY(launch_nnmin_split(X, rows, nx, B, bs, nB, pl.d, best, nb2, p, st));
         return CHAMFER_OK;
     }
@@ -545,6 +548,9 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     int32_t *scale = ax.crude_scale;
     void **ev = ax.stage_events;
     float *nb2 = mfma_supported(d, metric) ? at<float>(ws, pl.off_nb2) : nullptr;
+    uint16_t *bsplit = nb2 && !lowp_supported(d, metric, pl.precision)
+                           ? at<uint16_t>(ws, pl.off_bsplit)
+                           : nullptr;
     DevParams *p = at<DevParams>(ws, pl.off_params);
     if (pl.sampling == CHAMFER_UNIFORM) {
         // the baseline: no CrudeNN, every D_a = 1 (inputs still checked)
@@ -555,8 +561,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
         CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
         CH_TRY(launch_calib_final(lohi, d, p, st));
         CH_TRY(mark(ev, 1, st));
-        if (nb2 && !lowp_supported(d, metric, pl.precision))
-            CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
+        if (bsplit) CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));
         CH_TRY(mark(ev, 2, st));
         CH_TRY(launch_unit_weights(D, ax.crude_nn, scale, n_A, p, st));
         CH_TRY(mark(ev, 3, st));
@@ -569,8 +574,12 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
+    // the split table of B, written after the hash tables are done with (it
+    // would evict them from the last-level cache) and just before its reader
+    if (bsplit) CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
     CH_TRY(mark(ev, 4, st));
-    if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st))) return rc;
+    if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st, bsplit != nullptr)))
+        return rc;
     CH_TRY(mark(ev, 5, st));
     CH_TRY(launch_estimate_final(best, idx, D, pl.T, metric, p, eta_out, ax, st));
     CH_TRY(mark(ev, 6, st));

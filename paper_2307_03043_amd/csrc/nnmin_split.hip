@@ -12,16 +12,19 @@
 //
 // Scores.  s(b) = |b|^2 - 2 x~.b~ with x~.b~ = xh.bh + xm.bh + xh.bm (three
 // BF16 MFMAs per 32 coordinates, TERMS = 3) or that plus xm.bm (TERMS = 4).
-// BF16 products are exact in float32.  The dropped terms sum to at most
+// The accumulator of each (b, x) starts at -|b|^2 / 2 (exact), so it ends at
+// v = -s / 2 and the selection keeps the largest v.  BF16 products are
+// exact in float32.  The dropped terms sum to at most
 // c_tr |x| |b| (Cauchy-Schwarz over k): (xh + xm).rb + rx.(bh + bm) + rx.rb
 // gives 2.01 * 2^-16 and xm.bm adds at most 1.02 * 2^-16.  With adders that
 // round to nearest (the model of the FP32 MFMA form), the float32
 // accumulation errs by at most u per addition times the sum of the terms'
 // magnitudes.  TERMS = 3 accumulates all 3 DP products in one register
-// (1.02 |x||b| of magnitude): c_rel = (3 DP + 8) u 1.1.  TERMS = 4 keeps the
-// leading products xh.bh (DP additions, 1.008 |x||b|) apart from the three
-// small ones (3 DP additions, 0.008 |x||b|) and adds the two before the
-// score: c_rel = (DP + 8) u 1.1.  So the computed score is within
+// (|b|^2 / 2 + 1.02 |x||b| of magnitude): c_rel = (3 DP + 8) u 1.1.
+// TERMS = 4 keeps the leading products xh.bh (DP additions,
+// |b|^2 / 2 + 1.008 |x||b|) apart from the three small ones (3 DP additions,
+// 0.008 |x||b|) and adds the two at the end: c_rel = (DP + 8) u 1.1.  With
+// the rounding of |b|^2 itself ((d + 1) u |b|^2), the computed score is within
 //   E = c_abs + c_den (|x| + |b|max) + c_rel (|b|max^2 + 2 |x| |b|max)
 //       + 2 c_tr 1.1 |x| |b|max
 // of |b|^2 - 2 x.b, c_abs and c_den absorbing flushes of subnormal operands,
@@ -136,7 +139,7 @@ __device__ __forceinline__ void nnmin_l2_split(
     constexpr int NV = kSplitTileRows * RB / 16;  // 16-byte units per tile
     constexpr int PER_T = (NV + 255) / 256;
     __shared__ __attribute__((aligned(16))) uint8_t tile[kSplitTileRows * LDR];
-    __shared__ float tn2[kSplitTileRows];
+    __shared__ __attribute__((aligned(16))) float tn2[kSplitTileRows];  // -|b|^2 / 2
 
     if (p->status != CHAMFER_OK) return;
     const int tid = threadIdx.x;
@@ -183,33 +186,41 @@ __device__ __forceinline__ void nnmin_l2_split(
         qn2[nb] = s2;
     }
 
+    // Per lane and query: the largest v = x~.b~ - |b|^2 / 2 over the lane's
+    // rows (v = -s / 2, so the smallest score), its row, and the second
+    // largest v.  The MFMA accumulators start at -|b|^2 / 2 of their rows.
     float bestv[NB], second[NB];
     int32_t bidx[NB];  // B has at most 2^31 - 1 rows
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        bestv[nb] = INFINITY;
-        second[nb] = INFINITY;
+        bestv[nb] = -INFINITY;
+        second[nb] = -INFINITY;
         bidx[nb] = (int32_t)b0;
     }
 
-    // Register prefetch of one tile (PER_T 16-byte units per thread) and its norms.
+    // Register prefetch of one tile: thread tid takes the 16-byte unit
+    // u = tid % UPR of the rows tid / UPR + i RPI (i < PER_T), and threads
+    // below kSplitTileRows take -|b|^2 / 2 of one row (-inf past the chunk).
+    constexpr int UPR = RB / 16;  // 16-byte units per split row
+    constexpr int RPI = 256 / UPR;
+    static_assert(RPI * PER_T == kSplitTileRows, "one tile per 256 threads and PER_T passes");
+    const int r0 = tid / UPR, u0 = tid - (tid / UPR) * UPR;
     uint4 pf[PER_T];
-    float pn2 = INFINITY;
+    float pn2 = -INFINITY;
     auto fetch = [&](int64_t t0) {
+        const CH_RO uint4 *src =
+            reinterpret_cast<const CH_RO uint4 *>(ro(Bs) + (size_t)(t0 + r0) * (2 * DP)) + u0;
+        if (t0 + kSplitTileRows <= b1) {  // whole tile (uniform)
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const int v = tid + i * 256;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (v < NV) {
-                const int row = v / (RB / 16);
-                const int u = v - row * (RB / 16);
-                if (t0 + row < b1)
-                    val = ld(reinterpret_cast<const CH_RO uint4 *>(
-                                 ro(Bs) + (size_t)(t0 + row) * (2 * DP)) + u);
-            }
-            pf[i] = val;
+            for (int i = 0; i < PER_T; ++i) pf[i] = ld(src + (size_t)i * RPI * UPR);
+        } else {
+#pragma unroll
+            for (int i = 0; i < PER_T; ++i)
+                pf[i] = t0 + r0 + i * RPI < b1 ? ld(src + (size_t)i * RPI * UPR)
+                                               : make_uint4(0u, 0u, 0u, 0u);
         }
-        if (tid < kSplitTileRows) pn2 = (t0 + tid < b1) ? ro(nb2)[t0 + tid] : INFINITY;
+        if (tid < kSplitTileRows)
+            pn2 = (t0 + tid < b1) ? -0.5f * ro(nb2)[t0 + tid] : -INFINITY;
     };
 
     int64_t t0 = b0;
@@ -217,14 +228,8 @@ __device__ __forceinline__ void nnmin_l2_split(
     for (;;) {
         __syncthreads();  // the previous tile is no longer being read
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i) {
-            const int v = tid + i * 256;
-            if (v < NV) {
-                const int row = v / (RB / 16);
-                const int u = v - row * (RB / 16);
-                *reinterpret_cast<uint4 *>(&tile[row * LDR + u * 16]) = pf[i];
-            }
-        }
+        for (int i = 0; i < PER_T; ++i)
+            *reinterpret_cast<uint4 *>(&tile[(r0 + i * RPI) * LDR + u0 * 16]) = pf[i];
         if (tid < kSplitTileRows) tn2[tid] = pn2;
         __syncthreads();
         const int64_t next = t0 + kSplitTileRows;
@@ -235,9 +240,11 @@ __device__ __forceinline__ void nnmin_l2_split(
             constexpr int NL = TERMS == 4 ? 2 : 1;
             v4f hi[2][NB], lo[NL][NB];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < 2; ++m) {
+                const v4f h0 = *reinterpret_cast<const v4f *>(&tn2[16 * m + 4 * g]);
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) hi[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int nb = 0; nb < NB; ++nb) hi[m][nb] = h0;
+            }
 #pragma unroll
             for (int m = 0; m < NL; ++m)
 #pragma unroll
@@ -286,19 +293,16 @@ __device__ __forceinline__ void nnmin_l2_split(
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int lr = 16 * m + 4 * g + r;
-                    const float n2 = tn2[lr];
-                    const int32_t brow = (int32_t)(t0 + lr);
+                    const int32_t brow = (int32_t)(t0 + 16 * m + 4 * g + r);
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
-                        float dot = hi[m][nb][r];
-                        if constexpr (TERMS == 4) dot += lo[m][nb][r];
-                        const float sc = fmaf(dot, -2.0f, n2);
+                        float v = hi[m][nb][r];
+                        if constexpr (TERMS == 4) v += lo[m][nb][r];
                         const float bv = bestv[nb];
-                        second[nb] = fminf(second[nb], fmaxf(bv, sc));
-                        const bool lt = sc < bv;
-                        bestv[nb] = lt ? sc : bv;
-                        bidx[nb] = lt ? brow : bidx[nb];
+                        second[nb] = fmaxf(second[nb], fminf(bv, v));
+                        const bool gt = v > bv;
+                        bestv[nb] = gt ? v : bv;
+                        bidx[nb] = gt ? brow : bidx[nb];
                     }
                 }
         }
@@ -327,27 +331,29 @@ __device__ __forceinline__ void nnmin_l2_split(
             gacc = unpack_sp(__hip_atomic_load(&best[qi], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT));
         gacc = __shfl(gacc, j);
-        float bmin = bestv[nb];
-        bmin = fminf(bmin, __shfl_xor(bmin, 16));
-        bmin = fminf(bmin, __shfl_xor(bmin, 32));
-        float cut = second[nb];
-        cut = fminf(cut, __shfl_xor(cut, 16));
-        cut = fminf(cut, __shfl_xor(cut, 32));
+        // smallest score (and smallest second-best score) over the lane groups
+        float vmax = bestv[nb];
+        vmax = fmaxf(vmax, __shfl_xor(vmax, 16));
+        vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
+        float vcut = second[nb];
+        vcut = fmaxf(vcut, __shfl_xor(vcut, 16));
+        vcut = fmaxf(vcut, __shfl_xor(vcut, 32));
+        const double bmin = -2.0 * (double)vmax, cut = -2.0 * (double)vcut;
         const double xn2 = (double)qn2[nb];
         const double xabs = sqrt(xn2 * (1.0 + rho));
         const double E = cabs + cden * (xabs + bm) + crel * (b2m + 2.0 * xabs * bm) +
                          2.0 * ctr * xabs * bm;
         const double xlo = xn2 * (1.0 - rho);
-        const double lb_all = (1.0 - rho) * ((double)bmin - E + xlo);
+        const double lb_all = (1.0 - rho) * (bmin - E + xlo);
         const bool need = valid && !(lb_all > (double)gacc);
         unsigned long long mine = ~0ull;
-        if (need && bestv[nb] < INFINITY)
+        if (need && bestv[nb] > -INFINITY)
             mine = pack_sp(canon_acc<CHAMFER_L2>(X + qrow[nb] * d, B + (int64_t)bidx[nb] * d, d),
                            bidx[nb]);
         mine = min(mine, (unsigned long long)__shfl_xor(mine, 16));
         mine = min(mine, (unsigned long long)__shfl_xor(mine, 32));
         const double thr = fmin((double)unpack_sp(mine), (double)gacc);
-        const double lb_nc = (1.0 - rho) * ((double)cut - E + xlo);
+        const double lb_nc = (1.0 - rho) * (cut - E + xlo);
         const bool rescan = need && !(lb_nc > thr);
         if (need && g == 0 && mine != ~0ull) atomicMin(&best[qi], mine);
         unsigned long long mask = __ballot(rescan && g == 0);
