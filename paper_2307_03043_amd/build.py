@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libchamfer.so")
 
-SOURCES = ["api.hip", "hash.hip", "sample.hip", "nnmin.hip", "nnmin_mfma.hip", "nnmin_lowp.hip",
-           "nnmin_split.hip", "serve.hip", "retrieve.hip", "reduce.hip"]
+SOURCES = ["api.hip", "hash.hip", "sample.hip", "nnmin.hip", "nnmin_lowp.hip", "nnmin_split.hip",
+           "serve.hip", "retrieve.hip", "reduce.hip"]
 
 # -ffp-contract=off: no implicit fused multiply-adds (the canonical float32
 # operations are spelled out, fmaf where an fma is meant).  Packed FP32

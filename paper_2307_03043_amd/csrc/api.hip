@@ -279,7 +279,7 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
         CH_TRY(launch_nnmin_split(X, rows, nx, B, bs, nB, pl.d, best, nb2, p, st));
         return CHAMFER_OK;
     }
-    CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, nb2, p, st));
+    CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, p, st));
     return CHAMFER_OK;
 }
 
@@ -345,7 +345,9 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
     J.idx = at<int32_t>(ws, pl.off_idx);
     J.best = at<unsigned long long>(ws, pl.off_best);
     J.nb2 = mfma_supported(d, metric) ? at<float>(ws, pl.off_nb2) : nullptr;
-    J.bq = lp ? at<uint8_t>(ws, pl.off_bq) : nullptr;
+    // low precision: the cast rows of B; float32 l2: the split table of B
+    J.bq = lp ? at<uint8_t>(ws, pl.off_bq)
+              : mfma_supported(d, metric) ? at<uint8_t>(ws, pl.off_bsplit) : nullptr;
     J.xq = lp ? at<uint8_t>(ws, pl.off_xq) : nullptr;
     J.lpf = lp ? at<float>(ws, pl.off_lpf) : nullptr;
     J.eta = eta;
@@ -373,7 +375,9 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
         J.nb_castX = (int32_t)cast_blocks(pl.T);
         g = lowp_geom(pl.T, nB, d, pl.precision);
     } else if (mfma_supported(d, metric)) {
-        g = mfma_geom(pl.T, nB, d);
+        J.nb_castB = (int32_t)split_blocks(nB, d);
+        J.nb_castX = 0;
+        g = split_geom(pl.T, nB, d);
     } else {
         g = valu_geom(pl.T, nB, d);
     }
@@ -412,7 +416,7 @@ void job_share_nn(Job *jobs, int n) {
         Job &J = jobs[j];
         const double share = target * ((double)J.T * (double)J.nB) / total;
         const int64_t t = share < 1.0 ? 1 : (int64_t)std::ceil(share);
-        const NNGeom g = mfma ? mfma_geom(J.T, J.nB, J.d, t) : valu_geom(J.T, J.nB, J.d, t);
+        const NNGeom g = mfma ? split_geom(J.T, J.nB, J.d, t) : valu_geom(J.T, J.nB, J.d, t);
         J.nn_chunk = g.chunk;
         J.nn_nchunk = g.nchunk;
         J.nb_nn = (int32_t)g.blocks;
@@ -428,7 +432,10 @@ int launch_estimate_batch(const Batch *bt, int d, int metric, int ke, int precis
     CH_TRY(launch_batch_hash(1, bt, d, metric, ke, st));
     CH_TRY(launch_batch_weights(bt, st));
     CH_TRY(launch_batch_sample(bt, st));
-    if (lowp_supported(d, metric, precision)) CH_TRY(launch_batch_cast(bt, d, precision, st));
+    if (lowp_supported(d, metric, precision))
+        CH_TRY(launch_batch_cast(bt, d, precision, st));
+    else if (mfma_supported(d, metric))
+        CH_TRY(launch_batch_split_rows(bt, st));
     CH_TRY(launch_batch_nn(bt, d, metric, precision, st));
     CH_TRY(launch_batch_final(bt, metric, st));
     return CHAMFER_OK;

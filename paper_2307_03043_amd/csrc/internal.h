@@ -183,7 +183,7 @@ enum BatchStage {
     kBsWscan,   // scan of the block sums, W and s
     kBsPrefix,  // prefix P
     kBsSample,  // T draws
-    kBsCast,    // low-precision copies of B and of the sampled rows
+    kBsCast,    // low-precision copies of B and of the sampled rows, or B's split table
     kBsNN,      // exact nearest neighbours of the samples
     kBsFinal,   // eta and the per-request outputs
     kBsCount
@@ -342,22 +342,20 @@ hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *
                                  double *eta_out, chamfer_aux aux, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v,
                            hipStream_t st);
-// Exact nearest neighbours; nb2 (float [nB], or nullptr) selects the l2 MFMA
-// form, which needs launch_rownorm to have filled nb2 and p->b2max_bits.
+// Exact nearest neighbours on the vector ALU (l1, and l2 outside the
+// matrix-core dimensions).
 hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                        int64_t nB, int d, int metric, unsigned long long *best,
-                        const float *nb2, DevParams *p, hipStream_t st);
+                        int64_t nB, int d, int metric, unsigned long long *best, DevParams *p,
+                        hipStream_t st);
+// The l2 exact pass on the BF16 matrix cores (12 <= d <= 256) with a two-term
+// split of every coordinate: launch_rownorm (or the hash of B) fills nb2 and
+// p->b2max_bits, launch_split_rows the split table of B (split_table_bytes),
+// then launch_nnmin_split returns the canonical float32 minima.
+bool mfma_supported(int d, int metric);
 hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevParams *p,
                           hipStream_t st);
-bool mfma_supported(int d, int metric);
-hipError_t launch_nnmin_mfma(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                             int64_t nB, int d, unsigned long long *best, const float *nb2,
-                             DevParams *p, hipStream_t st);
-// The same exact l2 nearest neighbours on the BF16 matrix cores with a
-// two-term split of every coordinate: launch_split_rows fills the split table
-// of B (split_table_bytes), then launch_nnmin_split needs it, nb2 and
-// p->b2max_bits.
 size_t split_table_bytes(int64_t nB, int d);
+int64_t split_blocks(int64_t nB, int d);
 hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out,
                              const DevParams *p, hipStream_t st);
 hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
@@ -405,7 +403,6 @@ struct NNGeom {
 };
 // target: workgroups the split of B aims for (0: the direct-launch target)
 NNGeom valu_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
-NNGeom mfma_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
 NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
 constexpr int64_t kValuTargetWGs = 4096;
 NNGeom lowp_geom(int64_t nx, int64_t nB, int d, int precision);
@@ -423,7 +420,8 @@ hipError_t launch_batch_weights(const Batch *bt, hipStream_t st);
 hipError_t launch_batch_sample(const Batch *bt, hipStream_t st);
 hipError_t launch_batch_cast(const Batch *bt, int d, int precision, hipStream_t st);
 hipError_t launch_batch_nn(const Batch *bt, int d, int metric, int precision, hipStream_t st);
-hipError_t launch_batch_mfma(const Batch *bt, int d, hipStream_t st);
+hipError_t launch_batch_split_rows(const Batch *bt, hipStream_t st);
+hipError_t launch_batch_split(const Batch *bt, int d, hipStream_t st);
 hipError_t launch_batch_lowp(const Batch *bt, int d, int precision, hipStream_t st);
 hipError_t launch_batch_final(const Batch *bt, int metric, hipStream_t st);
 

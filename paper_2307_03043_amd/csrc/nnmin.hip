@@ -272,11 +272,9 @@ static hipError_t go_metric(const float *X, const int32_t *rows, int64_t nx, con
 }
 
 hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                        int64_t nB, int d, int metric, unsigned long long *best,
-                        const float *nb2, DevParams *p, hipStream_t st) {
+                        int64_t nB, int d, int metric, unsigned long long *best, DevParams *p,
+                        hipStream_t st) {
     if (nx <= 0) return hipSuccess;
-    if (nb2 != nullptr && mfma_supported(d, metric))
-        return launch_nnmin_mfma(X, rows, nx, B, nB, d, best, nb2, p, st);
     if (metric == CHAMFER_L1) return go_metric<CHAMFER_L1>(X, rows, nx, B, nB, d, best, p, st);
     return go_metric<CHAMFER_L2>(X, rows, nx, B, nB, d, best, p, st);
 }
@@ -401,7 +399,7 @@ static hipError_t batch_valu(const Batch *bt, int d, hipStream_t st) {
 
 hipError_t launch_batch_nn(const Batch *bt, int d, int metric, int precision, hipStream_t st) {
     if (lowp_supported(d, metric, precision)) return launch_batch_lowp(bt, d, precision, st);
-    if (mfma_supported(d, metric)) return launch_batch_mfma(bt, d, st);
+    if (mfma_supported(d, metric)) return launch_batch_split(bt, d, st);
     if (metric == CHAMFER_L1) return batch_valu<CHAMFER_L1>(bt, d, st);
     return batch_valu<CHAMFER_L2>(bt, d, st);
 }

@@ -94,13 +94,13 @@ __device__ __forceinline__ float unpack_sp(unsigned long long p) {
     return hi == 0xffffffffu ? INFINITY : __uint_as_float(hi);
 }
 
-// Split table of B: thread t handles 4 coordinates of one row.
-__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ B, int64_t nB,
-                                                    int d, int dp, uint16_t *out,
-                                                    const DevParams *p) {
+// Split table of B: thread t of the blk.n blocks of 256 handles 4
+// coordinates of one row.
+__device__ __forceinline__ void split_rows(const float *__restrict__ B, int64_t nB, int d, int dp,
+                                           uint16_t *out, const DevParams *p, Blk blk) {
     if (p->status != CHAMFER_OK) return;
     const int per_row = dp / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = blk.id * 256 + threadIdx.x;
     if (t >= nB * per_row) return;
     const int64_t r = t / per_row;
     const int k0 = (int)(t - r * per_row) * 4;
@@ -117,14 +117,56 @@ __global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ B,
         make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
 }
 
+__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ B, int64_t nB,
+                                                    int d, int dp, uint16_t *out,
+                                                    const DevParams *p) {
+    split_rows(B, nB, d, dp, out, p, grid_blk());
+}
+
+int64_t split_blocks(int64_t nB, int d) { return (nB * (split_dpad(d) / 4) + 255) / 256; }
+
 hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out, const DevParams *p,
                              hipStream_t st) {
     if (nB <= 0) return hipSuccess;
-    const int dp = split_dpad(d);
-    const int64_t threads = nB * (dp / 4);
-    k_split_rows<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(B, nB, d, dp, out, p);
+    k_split_rows<<<(unsigned)split_blocks(nB, d), 256, 0, st>>>(B, nB, d, split_dpad(d), out, p);
     return hipGetLastError();
 }
+
+// |b|^2 per row (float32 fma chain in ascending k) and its maximum over B
+// (p->b2max_bits); one thread per row with 16-byte loads.
+__global__ __launch_bounds__(256) void k_rownorm(const float *__restrict__ B, int64_t nB, int d,
+                                                 float *nb2, DevParams *p) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float v = 0.0f;
+    if (r < nB) {
+        const float *b = B + r * d;
+        if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0) {
+            const float4 *b4 = reinterpret_cast<const float4 *>(b);
+            for (int k = 0; k < (d >> 2); ++k) {
+                const float4 u = b4[k];
+                v = fmaf(u.x, u.x, v);
+                v = fmaf(u.y, u.y, v);
+                v = fmaf(u.z, u.z, v);
+                v = fmaf(u.w, u.w, v);
+            }
+        } else {
+            for (int k = 0; k < d; ++k) v = fmaf(b[k], b[k], v);
+        }
+        nb2[r] = v;
+    }
+    uint32_t m = __float_as_uint(v);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(&p->b2max_bits, m);
+}
+
+hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevParams *p,
+                          hipStream_t st) {
+    if (nB <= 0) return hipSuccess;
+    k_rownorm<<<(unsigned)((nB + 255) / 256), 256, 0, st>>>(B, nB, d, nb2, p);
+    return hipGetLastError();
+}
+
+bool mfma_supported(int d, int metric) { return metric == CHAMFER_L2 && d >= 12 && d <= 256; }
 
 template <int DP, int NB, int TERMS>
 __device__ __forceinline__ void nnmin_l2_split(
@@ -427,6 +469,42 @@ hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, c
         case 128: return go_split<128>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
         default: return go_split<256>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
     }
+}
+
+// ---------------------------------------------------------------- batched
+// A job's split table lives at J.bq (its cast stage fills it); served
+// batches take the three-product form.
+
+constexpr unsigned kGridSplit = 1024, kGridNNSplit = 2048;
+
+__global__ __launch_bounds__(256) void kb_split_rows(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsCast, [&](const Job &J, Blk b) {
+        split_rows(J.B, J.nB, J.d, split_dpad(J.d), reinterpret_cast<uint16_t *>(J.bq), J.p, b);
+    });
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void kb_nn_split(const Batch *__restrict__ bt) {
+    batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
+        nnmin_l2_split<DP, kSplitNB, 3>(J.A, J.idx, J.T, J.B,
+                                        reinterpret_cast<const uint16_t *>(J.bq), J.nB, J.d,
+                                        J.nb2, J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
+    });
+}
+
+hipError_t launch_batch_split_rows(const Batch *bt, hipStream_t st) {
+    kb_split_rows<<<kGridSplit, 256, 0, st>>>(bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(const Batch *bt, int d, hipStream_t st) {
+    switch (split_dpad(d)) {
+        case 32: kb_nn_split<32><<<kGridNNSplit, 256, 0, st>>>(bt); break;
+        case 64: kb_nn_split<64><<<kGridNNSplit, 256, 0, st>>>(bt); break;
+        case 128: kb_nn_split<128><<<kGridNNSplit, 256, 0, st>>>(bt); break;
+        default: kb_nn_split<256><<<kGridNNSplit, 256, 0, st>>>(bt); break;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace chamfer
