@@ -130,7 +130,10 @@ def measured_traffic(workload, kernel_ms):
     if not rec.get("sources"):
         return None
     for src, sha in rec["sources"].items():
-        with open(os.path.join(ROOT, src), "rb") as f:
+        path = os.path.join(ROOT, src)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != sha:
                 return None
     return rec["traffic_bytes"]
