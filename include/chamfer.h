@@ -51,7 +51,8 @@ enum chamfer_status {
 };
 
 enum chamfer_precision {
-    CHAMFER_FP32 = 0,  /* float32 arithmetic, exact canonical arg-mins        */
+    CHAMFER_FP32 = 0,  /* exact canonical float32 arg-mins (l2: certified    *
+                        * candidates from bf16-split MFMA tiles)             */
     CHAMFER_BF16 = 1,  /* l2 distance tiles on bf16 MFMA + float32 re-rank    */
     CHAMFER_FP8 = 2    /* l2 distance tiles on fp8-e4m3 MFMA + float32 re-rank*/
 };
