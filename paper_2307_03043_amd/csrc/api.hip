@@ -411,7 +411,7 @@ void job_share_nn(Job *jobs, int n) {
     const bool mfma = mfma_supported(J0.d, J0.metric);
     double total = 0.0;
     for (int j = 0; j < n; ++j) total += (double)jobs[j].T * (double)jobs[j].nB;
-    const double target = mfma ? 4096.0 : (double)kValuTargetWGs;
+    const double target = mfma ? (double)split_target_wgs(J0.d) : (double)kValuTargetWGs;
     for (int j = 0; j < n; ++j) {
         Job &J = jobs[j];
         const double share = target * ((double)J.T * (double)J.nB) / total;

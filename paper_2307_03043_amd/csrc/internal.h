@@ -404,6 +404,7 @@ struct NNGeom {
 // target: workgroups the split of B aims for (0: the direct-launch target)
 NNGeom valu_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
 NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target = 0);
+int64_t split_target_wgs(int d);  // the direct-launch target of split_geom
 constexpr int64_t kValuTargetWGs = 4096;
 NNGeom lowp_geom(int64_t nx, int64_t nB, int d, int precision);
 constexpr int kMaxLdsL1Dim = 240;  // widest l1 tile staged in LDS by the hash

@@ -50,15 +50,17 @@ namespace chamfer {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kSplitTileRows = 32;  // B rows per LDS tile (two 16-row MFMA blocks)
-#ifndef CH_SPLIT_TARGET_WGS
-#define CH_SPLIT_TARGET_WGS 4096
-#endif
-#ifndef CH_SPLIT_NB
-#define CH_SPLIT_NB 1
-#endif
-constexpr int kSplitTargetWGs = CH_SPLIT_TARGET_WGS;  // workgroups a launch aims for
-constexpr int kSplitNB = CH_SPLIT_NB;                 // 16-query blocks per wavefront
+constexpr int kSplitMB = 2;                    // 16-row MFMA blocks per LDS tile
+constexpr int kSplitTileRows = 16 * kSplitMB;  // B rows per LDS tile
+// Launch shape by padded dimension, chosen by a measured sweep on MI355X:
+// two 16-query blocks per wavefront (half the LDS reads per MFMA) up to
+// d_pad = 128, one at 256 (registers: three wavefronts per SIMD either way),
+// and a workgroup target that is a whole number of resident rounds
+// (2304 = 3 x 256 CUs x 3 workgroups; 1.6 vs 2.1 ms for the 10^6-point
+// exact pass of the 2000 draws at d = 128).
+__host__ __device__ constexpr int split_nb(int dp) { return dp <= 128 ? 2 : 1; }
+constexpr int64_t split_target(int dp) { return dp <= 128 ? 2304 : 4096; }
+
 #ifndef CH_SPLIT_MANY_QUERIES
 #define CH_SPLIT_MANY_QUERIES 16384
 #endif
@@ -279,10 +281,10 @@ __device__ __forceinline__ void nnmin_l2_split(
 
         if (wave_active) {
             // TERMS = 3: every product into hi; TERMS = 4: the small ones into lo
-            constexpr int NL = TERMS == 4 ? 2 : 1;
-            v4f hi[2][NB], lo[NL][NB];
+            constexpr int NL = TERMS == 4 ? kSplitMB : 1;
+            v4f hi[kSplitMB][NB], lo[NL][NB];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < kSplitMB; ++m) {
                 const v4f h0 = *reinterpret_cast<const v4f *>(&tn2[16 * m + 4 * g]);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) hi[m][nb] = h0;
@@ -293,9 +295,9 @@ __device__ __forceinline__ void nnmin_l2_split(
                 for (int nb = 0; nb < NB; ++nb) lo[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                v8bf ah[2], am[2];
+                v8bf ah[kSplitMB], am[kSplitMB];
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
+                for (int m = 0; m < kSplitMB; ++m) {
                     const uint8_t *ap = &tile[(16 * m + j) * LDR + (g * KQ + 8 * s) * 2];
                     ah[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap));
                     am[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap + 2 * DP));
@@ -305,12 +307,12 @@ __device__ __forceinline__ void nnmin_l2_split(
                     const v8bf xh = __builtin_bit_cast(v8bf, qh[nb][s]);
                     const v8bf xm = __builtin_bit_cast(v8bf, qm[nb][s]);
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
+                    for (int m = 0; m < kSplitMB; ++m)
                         hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xh, hi[m][nb],
                                                                             0, 0, 0);
                     if constexpr (TERMS == 4) {
 #pragma unroll
-                        for (int m = 0; m < 2; ++m) {
+                        for (int m = 0; m < kSplitMB; ++m) {
                             lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
                                                                                 lo[m][nb], 0, 0, 0);
                             lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
@@ -320,11 +322,11 @@ __device__ __forceinline__ void nnmin_l2_split(
                         }
                     } else {
 #pragma unroll
-                        for (int m = 0; m < 2; ++m)
+                        for (int m = 0; m < kSplitMB; ++m)
                             hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
                                                                                 hi[m][nb], 0, 0, 0);
 #pragma unroll
-                        for (int m = 0; m < 2; ++m)
+                        for (int m = 0; m < kSplitMB; ++m)
                             hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
                                                                                 hi[m][nb], 0, 0, 0);
                     }
@@ -332,7 +334,7 @@ __device__ __forceinline__ void nnmin_l2_split(
             }
             // Lane (g, j) holds rows 16m + 4g + r of the tile for query j.
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < kSplitMB; ++m)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int32_t brow = (int32_t)(t0 + 16 * m + 4 * g + r);
@@ -427,11 +429,12 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_split(
                                   grid_blk());
 }
 
+int64_t split_target_wgs(int d) { return split_target(split_dpad(d)); }
+
 NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target) {
-    (void)d;
-    const int64_t per_wg = 64 * kSplitNB;
+    const int64_t per_wg = 64 * split_nb(split_dpad(d));
     const int64_t nq = (nx + per_wg - 1) / per_wg;
-    if (target <= 0) target = kSplitTargetWGs;
+    if (target <= 0) target = split_target(split_dpad(d));
     int64_t nc = (target + nq - 1) / nq;
     const int64_t cmin = (nB + 8191) / 8192, cmax = (nB + 255) / 256;
     if (nc < cmin) nc = cmin;
@@ -451,10 +454,10 @@ static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, cons
                            const float *nb2, DevParams *p, hipStream_t st) {
     const NNGeom g = split_geom(nx, nB, d, 0);
     if (nx >= kSplitManyQueries)
-        k_nnmin_l2_split<DP, kSplitNB, 4><<<(unsigned)g.blocks, 256, 0, st>>>(
+        k_nnmin_l2_split<DP, split_nb(DP), 4><<<(unsigned)g.blocks, 256, 0, st>>>(
             X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
     else
-        k_nnmin_l2_split<DP, kSplitNB, 3><<<(unsigned)g.blocks, 256, 0, st>>>(
+        k_nnmin_l2_split<DP, split_nb(DP), 3><<<(unsigned)g.blocks, 256, 0, st>>>(
             X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
     return hipGetLastError();
 }
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(256) void kb_split_rows(const Batch *__restrict__ b
 template <int DP>
 __global__ __launch_bounds__(256) void kb_nn_split(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
-        nnmin_l2_split<DP, kSplitNB, 3>(J.A, J.idx, J.T, J.B,
+        nnmin_l2_split<DP, split_nb(DP), 3>(J.A, J.idx, J.T, J.B,
                                         reinterpret_cast<const uint16_t *>(J.bq), J.nB, J.d,
                                         J.nb2, J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
     });
