@@ -499,7 +499,7 @@ __device__ __forceinline__ float dist32(const float *__restrict__ a, const float
 constexpr int kTile = 64;        // points per workgroup
 constexpr int kWaves = 4;        // wavefronts per workgroup; they split the scales
 constexpr int kThreads = 64 * kWaves;
-constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2)
+constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2), by default
 
 // Copy rows [np][kc] of the tile (row stride d, from column k0) into LDS
 // rows of stride ldr as f(value, k): each thread issues a batch of loads
@@ -547,7 +547,8 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t 
 // scales w, w + 4, w + 8, ...  For the probe each wavefront stops at its own
 // first hit (or once another wavefront has hit at a finer scale); the first
 // colliding scale is the smallest over the four.
-template <int METRIC, int MODE, int KE, bool YG>
+// EC: coordinates of x staged per pass of the l2 embedding.
+template <int METRIC, int MODE, int KE, bool YG, int EC = kEmbedChunk>
 __device__ __forceinline__ void hash_tile(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
@@ -555,7 +556,7 @@ __device__ __forceinline__ void hash_tile(
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
     int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags, Blk blk) {
     extern __shared__ float smem[];
-    __shared__ float los[kEmbedChunk];
+    __shared__ float los[EC];
     __shared__ int hit_scale[kTile];
     __shared__ int hit_cand[kWaves][kTile];
     __shared__ int wave_scale[kWaves][kTile];
@@ -594,22 +595,22 @@ __device__ __forceinline__ void hash_tile(
         // subtraction); for B, wavefront 0 also accumulates |x|^2 per row for
         // the l2 nearest-neighbour pass.
         constexpr int JW = KE / kWaves;
-        float *xs = smem + kTile * khp;  // [kTile][kEmbedChunk + 1]
+        float *xs = smem + kTile * khp;  // [kTile][EC + 1]
         float y[JW > 0 ? JW : 1];
 #pragma unroll
         for (int j = 0; j < JW; ++j) y[j] = 0.0f;
         float n2 = 0.0f;
         const bool want_n2 = (MODE == 0 || MODE == 3) && nb2_out != nullptr && wave == 0;
-        for (int k0 = 0; k0 < d; k0 += kEmbedChunk) {
-            const int kc = min(kEmbedChunk, d - k0);
+        for (int k0 = 0; k0 < d; k0 += EC) {
+            const int kc = min(EC, d - k0);
             __syncthreads();
-            stage_rows<16>(X, p0, np, d, k0, kc, xs, kEmbedChunk + 1,
+            stage_rows<16>(X, p0, np, d, k0, kc, xs, EC + 1,
                            [](float v, int) { return v; });
             if (tid < kc) los[tid] = ordered_to_float(ro(lohi)[k0 + tid]);
             __syncthreads();
             if (active) {
                 for (int k = 0; k < kc; ++k) {
-                    const float xraw = xs[lane * (kEmbedChunk + 1) + k];
+                    const float xraw = xs[lane * (EC + 1) + k];
                     const float xv = xraw - los[k];
                     const auto *zc = ro(embed_t) + (size_t)(k0 + k) * KE + wave * JW;
 #pragma unroll
@@ -726,7 +727,7 @@ __device__ __forceinline__ void hash_tile(
         const auto *wkeys = ro(wk);
         const auto *wmem = ro(reinterpret_cast<const int *>(wk + ((size_t)L << log2cap)));
         const int lds_floats = METRIC == CHAMFER_L1 ? (YG ? 0 : kTile * khp)
-                                                    : kTile * (khp + kEmbedChunk + 1);
+                                                    : kTile * (khp + EC + 1);
         int *got = reinterpret_cast<int *>(smem + lds_floats) + lane * W;
         int ng = 0, first = L;
         float D = 0.0f;
@@ -797,26 +798,31 @@ __device__ __forceinline__ void hash_tile(
     finish(D, best_c, best_s);
 }
 
-template <int METRIC, int MODE, int KE, bool YG>
-__global__ __launch_bounds__(kThreads) void k_hash(
+// WAVES: wavefronts per SIMD the register allocation must allow.
+template <int METRIC, int MODE, int KE, bool YG, int EC, int WAVES>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_hash(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
     const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
     int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags) {
-    hash_tile<METRIC, MODE, KE, YG>(X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap,
-                                    keys_out, D_out, nn_out, scale_out, nb2_out, p, nB, W, flags,
-                                    grid_blk());
+    hash_tile<METRIC, MODE, KE, YG, EC>(X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables,
+                                        log2cap, keys_out, D_out, nn_out, scale_out, nb2_out, p,
+                                        nB, W, flags, grid_blk());
 }
 
 int64_t hash_blocks(int64_t n) { return (n + kTile - 1) / kTile; }
 
-template <int METRIC, int KE, bool YG>
+template <int METRIC, int KE, bool YG, int EC = kEmbedChunk>
 static size_t hash_lds(int d) {
     const int kh = METRIC == CHAMFER_L1 ? d : KE;
     if (METRIC == CHAMFER_L1) return YG ? 0 : (size_t)kTile * (kh | 1) * sizeof(float);
-    return (size_t)kTile * ((kh | 1) + kEmbedChunk + 1) * sizeof(float);
+    return (size_t)kTile * ((kh | 1) + EC + 1) * sizeof(float);
 }
+
+// Tables up to this size stay in the last-level cache between the insert and
+// the probe.
+constexpr size_t kHotTableBytes = (size_t)128 << 20;
 
 template <int METRIC, int KE, bool YG>
 static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts,
@@ -825,18 +831,33 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
                                 Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                                 int32_t *nn_out, int32_t *scale_out, float *nb2_out,
                                 DevParams *p, int W, int flags, hipStream_t st) {
-    size_t lds = hash_lds<METRIC, KE, YG>(d);
-    if (mode == 4) lds += (size_t)kTile * W * sizeof(int);  // retrieved b per lane
     const unsigned blocks = (unsigned)hash_blocks(n);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
 #define CH_KARGS X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out, \
                  scale_out, nb2_out, p, nB, W, flags
+    // l2 insert, and l2 probe of cache-resident tables: a 32-coordinate
+    // embedding stage holds fewer registers and LDS, so 7 workgroups fit on a
+    // CU (one resident round for 10^5 points: insert 155 -> 133 us, probe
+    // 109 -> 83 us).  A probe of larger tables is bound by their HBM lines
+    // and does better with the default (10^6 points: 1.32 vs 1.46 ms).
+    constexpr int ECS = METRIC == CHAMFER_L2 ? 32 : kEmbedChunk;
+    constexpr int WS = METRIC == CHAMFER_L2 ? 7 : 4;
+    const bool hot = table_bytes(L, log2cap, W) <= kHotTableBytes;
+    const size_t lds = hash_lds<METRIC, KE, YG>(d), lds_s = hash_lds<METRIC, KE, YG, ECS>(d);
     switch (mode) {
-        case 0: k_hash<METRIC, 0, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
-        case 1: k_hash<METRIC, 1, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
-        case 2: k_hash<METRIC, 2, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
-        case 3: k_hash<METRIC, 3, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
-        case 4: k_hash<METRIC, 4, KE, YG><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 0: k_hash<METRIC, 0, KE, YG, ECS, WS><<<blocks, kThreads, lds_s, st>>>(CH_KARGS); break;
+        case 1:
+            if (hot)
+                k_hash<METRIC, 1, KE, YG, ECS, WS><<<blocks, kThreads, lds_s, st>>>(CH_KARGS);
+            else
+                k_hash<METRIC, 1, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS);
+            break;
+        case 2: k_hash<METRIC, 2, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 3: k_hash<METRIC, 3, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 4:  // retrieved b per lane after the tile
+            k_hash<METRIC, 4, KE, YG, kEmbedChunk, 4>
+                <<<blocks, kThreads, lds + (size_t)kTile * W * sizeof(int), st>>>(CH_KARGS);
+            break;
         default: return hipErrorInvalidValue;
     }
 #undef CH_KARGS
