@@ -104,7 +104,8 @@ typedef struct chamfer_aux {
     /* Host array of CHAMFER_STAGE_EVENTS hipEvent_t (as void*), or NULL.  When
      * set, event i is recorded on the stream at stage boundary i: 0 start,
      * 1 calibration and tables done, 2 B bucketed, 3 CrudeNN done (D_a),
-     * 4 weights and draws done, 5 exact pass over the draws done, 6 end.
+     * 4 weights and draws (and, for l2, the BF16 split table of B) done,
+     * 5 exact pass over the draws done, 6 end.
      * Stage 4->5 is a single kernel (the nearest-neighbour pass). */
     void **stage_events;
 } chamfer_aux;
