@@ -1,8 +1,8 @@
 // Exact l2 nearest neighbours on the BF16 matrix cores (gfx950
 // v_mfma_f32_16x16x32_bf16) with every float32 coordinate split in two
-// BF16 terms, returning the same canonical float32 result as the FP32 MFMA
-// and VALU forms: the minimum over b of (fma-chain accumulator of
-// (x_k - b_k)^2 in ascending k, b), ties to the lower b.
+// BF16 terms, returning the same canonical float32 result as the VALU form:
+// the minimum over b of (fma-chain accumulator of (x_k - b_k)^2 in
+// ascending k, b), ties to the lower b.
 //
 // Split.  v = h + m + r with h = bf16(v), m = bf16(v - h) (round to nearest
 // even; v - h is exact in float32), so |m| <= 2^-8 (1 + 2^-8) |v| and
@@ -17,7 +17,7 @@
 // exact in float32.  The dropped terms sum to at most
 // c_tr |x| |b| (Cauchy-Schwarz over k): (xh + xm).rb + rx.(bh + bm) + rx.rb
 // gives 2.01 * 2^-16 and xm.bm adds at most 1.02 * 2^-16.  With adders that
-// round to nearest (the model of the FP32 MFMA form), the float32
+// round to nearest (the model assumed for the matrix cores), the float32
 // accumulation errs by at most u per addition times the sum of the terms'
 // magnitudes.  TERMS = 3 accumulates all 3 DP products in one register
 // (|b|^2 / 2 + 1.02 |x||b| of magnitude): c_rel = (3 DP + 8) u 1.1.
@@ -29,17 +29,17 @@
 //       + 2 c_tr 1.1 |x| |b|max
 // of |b|^2 - 2 x.b, c_abs and c_den absorbing flushes of subnormal operands,
 // products and sums to zero.  TERMS = 4 has the smaller E (fewer exact
-// rescans) and TERMS = 3 the fewer registers (four wavefronts per SIMD at
-// d <= 128); launches over many queries take TERMS = 4.
+// rescans) and TERMS = 3 the fewer registers and MFMAs; launches over many
+// queries take TERMS = 4.
 //
-// Candidates, re-rank, certificate and rescan are those of the FP32 MFMA
-// form with this E: each lane keeps its best score (with its b) and its
-// second-best score per query; the four lane-group bests are re-evaluated
-// with the canonical float32 distance; a (query, chunk) pair whose
-// non-candidates cannot be proved worse than the best candidate (or the best
-// already recorded) is rescanned exactly by the whole wavefront; chunks merge
-// with a 64-bit atomicMin of (accumulator bits << 32 | b).  Overflow of any
-// norm makes E infinite, which sends every chunk to the exact rescan.
+// Candidates and certificate: each lane keeps its best score (with its b)
+// and its second-best score per query; the four lane-group bests are
+// re-evaluated with the canonical float32 distance; a (query, chunk) pair
+// whose non-candidates cannot be proved worse than the best candidate (or
+// the best already recorded) is rescanned exactly by the whole wavefront;
+// chunks merge with a 64-bit atomicMin of (accumulator bits << 32 | b).
+// Overflow of any norm makes E infinite, which sends every chunk to the
+// exact rescan.
 #include <cfloat>
 #include <cmath>
 
@@ -61,13 +61,10 @@ constexpr int kSplitTileRows = 16 * kSplitMB;  // B rows per LDS tile
 __host__ __device__ constexpr int split_nb(int dp) { return dp <= 128 ? 2 : 1; }
 constexpr int64_t split_target(int dp) { return dp <= 128 ? 2304 : 4096; }
 
-#ifndef CH_SPLIT_MANY_QUERIES
-#define CH_SPLIT_MANY_QUERIES 16384
-#endif
 // Launches with at least this many queries take the four-product form: they
 // split B into few, long chunks, where near-ties inside a chunk (and so
 // exact rescans, each reading the whole chunk) are frequent.
-constexpr int64_t kSplitManyQueries = CH_SPLIT_MANY_QUERIES;
+constexpr int64_t kSplitManyQueries = 16384;
 
 __host__ __device__ inline int split_dpad(int d) {
     return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
