@@ -161,7 +161,10 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_nb2 = take(mfma_supported(d, metric) ? (size_t)nB * sizeof(float) : 0);
     // low precision: cast rows of B and of the queries, scales and norms
     const bool lp = lowp_supported(d, metric, pl.precision);
-    pl.off_bsplit = take(!lp && mfma_supported(d, metric) ? split_table_bytes(nB, d) : 0);
+    const bool split = !lp && mfma_supported(d, metric);
+    pl.off_bsplit = take(split ? split_table_bytes(nB, d) : 0);
+    pl.off_xsplit = take(split ? split_table_bytes(nrow, d) : 0);
+    pl.off_xn2 = take(split ? (size_t)nrow * sizeof(float) : 0);
     const size_t rb = lp ? lowp_row_bytes(d, pl.precision) : 0;
     pl.off_bq = take(rb * (size_t)nB);
     pl.off_xq = take(rb * (size_t)nrow);
@@ -258,7 +261,7 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
 // Exact pass over queries (rows of X, or X[rows[q]]): the low-precision
 // form when requested and supported, else the float32 result (split-BF16
 // matrix cores for l2 when nb2 is given, vector ALU otherwise).  split_ready:
-// the split table of B is already in the workspace.
+// the split tables of B and of the queries are already in the workspace.
 int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64_t nx,
             const float *B, int64_t nB, unsigned long long *best, float *nb2, DevParams *p,
             hipStream_t st, bool split_ready = false) {
@@ -275,8 +278,13 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
     }
     if (nb2 != nullptr && mfma_supported(pl.d, pl.metric)) {
         uint16_t *bs = at<uint16_t>(ws, pl.off_bsplit);
-        if (!split_ready) CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
-        CH_TRY(launch_nnmin_split(X, rows, nx, B, bs, nB, pl.d, best, nb2, p, st));
+        uint16_t *xs = at<uint16_t>(ws, pl.off_xsplit);
+        float *xn2 = at<float>(ws, pl.off_xn2);
+        if (!split_ready) {
+            CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
+            CH_TRY(launch_split_queries(X, rows, nx, pl.d, xs, xn2, p, st));
+        }
+        CH_TRY(launch_nnmin_split(X, rows, nx, xs, xn2, B, bs, nB, pl.d, best, nb2, p, st));
         return CHAMFER_OK;
     }
     CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, p, st));
@@ -581,9 +589,14 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
-    // the split table of B, written after the hash tables are done with (it
-    // would evict them from the last-level cache) and just before its reader
-    if (bsplit) CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
+    // the split tables of B and of the draws, written after the hash tables
+    // are done with (they would evict them from the last-level cache) and
+    // just before their reader
+    if (bsplit) {
+        CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
+        CH_TRY(launch_split_queries(A, idx, pl.T, d, at<uint16_t>(ws, pl.off_xsplit),
+                                    at<float>(ws, pl.off_xn2), p, st));
+    }
     CH_TRY(mark(ev, 4, st));
     if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st, bsplit != nullptr)))
         return rc;

@@ -100,7 +100,7 @@ struct Plan {
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
-        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit,
+        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit, off_xsplit, off_xn2,
         off_bq, off_xq, off_lpf, total;
 };
 
@@ -358,9 +358,14 @@ size_t split_table_bytes(int64_t nB, int d);
 int64_t split_blocks(int64_t nB, int d);
 hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out,
                              const DevParams *p, hipStream_t st);
-hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                              const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
-                              const float *nb2, DevParams *p, hipStream_t st);
+// The queries' split table (rows X[rows[i]], i < nx) and their |x|^2.
+hipError_t launch_split_queries(const float *X, const int32_t *rows, int64_t nx, int d,
+                                uint16_t *out, float *n2, const DevParams *p, hipStream_t st);
+// Xs, xn2: the queries' split table and norms (launch_split_queries).
+hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
+                              const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
+                              int d, unsigned long long *best, const float *nb2, DevParams *p,
+                              hipStream_t st);
 // Low-precision (BF16 / FP8-E4M3) l2 nearest neighbours with float32 re-rank.
 int lowp_dpad(int d, int precision);
 bool lowp_supported(int d, int metric, int precision);

@@ -93,33 +93,45 @@ __device__ __forceinline__ float unpack_sp(unsigned long long p) {
     return hi == 0xffffffffu ? INFINITY : __uint_as_float(hi);
 }
 
-// Split table of B: thread t of the blk.n blocks of 256 handles 4
-// coordinates of one row.
-__device__ __forceinline__ void split_rows(const float *__restrict__ B, int64_t nB, int d, int dp,
-                                           uint16_t *out, const DevParams *p, Blk blk) {
+// Split table of n rows (row i is X[rows[i]], or X[i] without rows): thread
+// t of the blk.n blocks of 256 handles 4 coordinates of one row.  With n2,
+// also |row|^2 (float32; the d_pad / 4 threads of a row are consecutive
+// lanes of one wavefront, d_pad / 4 a power of two).
+__device__ __forceinline__ void split_rows(const float *__restrict__ X,
+                                           const int32_t *__restrict__ rows, int64_t n, int d,
+                                           int dp, uint16_t *out, float *n2, const DevParams *p,
+                                           Blk blk) {
     if (p->status != CHAMFER_OK) return;
     const int per_row = dp / 4;
     const int64_t t = blk.id * 256 + threadIdx.x;
-    if (t >= nB * per_row) return;
+    if (t >= n * per_row) return;
     const int64_t r = t / per_row;
     const int k0 = (int)(t - r * per_row) * 4;
-    const auto *b = ro(B) + r * d;
+    const int64_t src = rows ? (int64_t)ro(rows)[r] : r;
+    const auto *x = ro(X) + src * d;
     uint32_t h[4], m[4];
+    float s2 = 0.0f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float v = k0 + i < d ? b[k0 + i] : 0.0f;
+        const float v = k0 + i < d ? x[k0 + i] : 0.0f;
+        s2 = fmaf(v, v, s2);
         split2(v, h[i], m[i]);
     }
     uint16_t *row = out + (size_t)r * (2 * dp);
     *reinterpret_cast<uint2 *>(row + k0) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
     *reinterpret_cast<uint2 *>(row + dp + k0) =
         make_uint2(m[0] | (m[1] << 16), m[2] | (m[3] << 16));
+    if (n2) {
+        for (int off = per_row / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+        if (k0 == 0) n2[r] = s2;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ B, int64_t nB,
-                                                    int d, int dp, uint16_t *out,
+__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ X,
+                                                    const int32_t *__restrict__ rows, int64_t n,
+                                                    int d, int dp, uint16_t *out, float *n2,
                                                     const DevParams *p) {
-    split_rows(B, nB, d, dp, out, p, grid_blk());
+    split_rows(X, rows, n, d, dp, out, n2, p, grid_blk());
 }
 
 int64_t split_blocks(int64_t nB, int d) { return (nB * (split_dpad(d) / 4) + 255) / 256; }
@@ -127,7 +139,16 @@ int64_t split_blocks(int64_t nB, int d) { return (nB * (split_dpad(d) / 4) + 255
 hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out, const DevParams *p,
                              hipStream_t st) {
     if (nB <= 0) return hipSuccess;
-    k_split_rows<<<(unsigned)split_blocks(nB, d), 256, 0, st>>>(B, nB, d, split_dpad(d), out, p);
+    k_split_rows<<<(unsigned)split_blocks(nB, d), 256, 0, st>>>(B, nullptr, nB, d, split_dpad(d),
+                                                                out, nullptr, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_queries(const float *X, const int32_t *rows, int64_t nx, int d,
+                                uint16_t *out, float *n2, const DevParams *p, hipStream_t st) {
+    if (nx <= 0) return hipSuccess;
+    k_split_rows<<<(unsigned)split_blocks(nx, d), 256, 0, st>>>(X, rows, nx, d, split_dpad(d),
+                                                                out, n2, p);
     return hipGetLastError();
 }
 
@@ -167,9 +188,12 @@ hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevPara
 
 bool mfma_supported(int d, int metric) { return metric == CHAMFER_L2 && d >= 12 && d <= 256; }
 
-template <int DP, int NB, int TERMS>
+// XS: Xs and xn2 hold the queries' split table and |x|^2, in query order;
+// otherwise each workgroup splits its queries in registers.
+template <int DP, int NB, int TERMS, bool XS>
 __device__ __forceinline__ void nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
     const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
     DevParams *p, Blk blk) {
@@ -205,6 +229,17 @@ __device__ __forceinline__ void nnmin_l2_split(
         const int64_t qi = qbase + nb * 16 + j;
         const int64_t r = qi < nx ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
         qrow[nb] = r;
+        if constexpr (XS) {
+            const auto *xs = reinterpret_cast<const CH_RO uint4 *>(
+                ro(Xs) + (size_t)(qi < nx ? qi : 0) * (2 * DP) + g * KQ);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                qh[nb][s] = ld(xs + s);
+                qm[nb][s] = ld(xs + DP / 8 + s);
+            }
+            qn2[nb] = qi < nx ? ro(xn2)[qi] : 0.0f;
+            continue;
+        }
         const auto *xr = ro(X) + r * d;
         float s2 = 0.0f;
 #pragma unroll
@@ -419,11 +454,12 @@ __device__ __forceinline__ void nnmin_l2_split(
 template <int DP, int NB, int TERMS>
 __global__ __launch_bounds__(256) void k_nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
     const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
     DevParams *p) {
-    nnmin_l2_split<DP, NB, TERMS>(X, rows, nx, B, Bs, nB, d, nb2, chunk, nchunk, best, p,
-                                  grid_blk());
+    nnmin_l2_split<DP, NB, TERMS, true>(X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, chunk, nchunk,
+                                        best, p, grid_blk());
 }
 
 int64_t split_target_wgs(int d) { return split_target(split_dpad(d)); }
@@ -446,29 +482,34 @@ NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target) {
 }
 
 template <int DP>
-static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                           const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
-                           const float *nb2, DevParams *p, hipStream_t st) {
+static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
+                           const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
+                           int d, unsigned long long *best, const float *nb2, DevParams *p,
+                           hipStream_t st) {
     const NNGeom g = split_geom(nx, nB, d, 0);
     if (nx >= kSplitManyQueries)
         k_nnmin_l2_split<DP, split_nb(DP), 4><<<(unsigned)g.blocks, 256, 0, st>>>(
-            X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
+            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
     else
         k_nnmin_l2_split<DP, split_nb(DP), 3><<<(unsigned)g.blocks, 256, 0, st>>>(
-            X, rows, nx, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
+            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
     return hipGetLastError();
 }
 
-hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const float *B,
-                              const uint16_t *Bs, int64_t nB, int d, unsigned long long *best,
-                              const float *nb2, DevParams *p, hipStream_t st) {
+hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
+                              const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
+                              int d, unsigned long long *best, const float *nb2, DevParams *p,
+                              hipStream_t st) {
     if (nx <= 0) return hipSuccess;
+    if (Xs == nullptr || xn2 == nullptr) return hipErrorInvalidValue;
+#define CH_SPLIT_ARGS X, rows, nx, Xs, xn2, B, Bs, nB, d, best, nb2, p, st
     switch (split_dpad(d)) {
-        case 32: return go_split<32>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
-        case 64: return go_split<64>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
-        case 128: return go_split<128>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
-        default: return go_split<256>(X, rows, nx, B, Bs, nB, d, best, nb2, p, st);
+        case 32: return go_split<32>(CH_SPLIT_ARGS);
+        case 64: return go_split<64>(CH_SPLIT_ARGS);
+        case 128: return go_split<128>(CH_SPLIT_ARGS);
+        default: return go_split<256>(CH_SPLIT_ARGS);
     }
+#undef CH_SPLIT_ARGS
 }
 
 // ---------------------------------------------------------------- batched
@@ -479,16 +520,17 @@ constexpr unsigned kGridSplit = 1024, kGridNNSplit = 2048;
 
 __global__ __launch_bounds__(256) void kb_split_rows(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsCast, [&](const Job &J, Blk b) {
-        split_rows(J.B, J.nB, J.d, split_dpad(J.d), reinterpret_cast<uint16_t *>(J.bq), J.p, b);
+        split_rows(J.B, nullptr, J.nB, J.d, split_dpad(J.d), reinterpret_cast<uint16_t *>(J.bq),
+                   nullptr, J.p, b);
     });
 }
 
 template <int DP>
 __global__ __launch_bounds__(256) void kb_nn_split(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
-        nnmin_l2_split<DP, split_nb(DP), 3>(J.A, J.idx, J.T, J.B,
-                                        reinterpret_cast<const uint16_t *>(J.bq), J.nB, J.d,
-                                        J.nb2, J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
+        nnmin_l2_split<DP, split_nb(DP), 3, false>(J.A, J.idx, J.T, nullptr, nullptr, J.B,
+                                            reinterpret_cast<const uint16_t *>(J.bq), J.nB, J.d,
+                                            J.nb2, J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
     });
 }
 
