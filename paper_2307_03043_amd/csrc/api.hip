@@ -383,8 +383,10 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
         J.nb_castX = (int32_t)cast_blocks(pl.T);
         g = lowp_geom(pl.T, nB, d, pl.precision);
     } else if (mfma_supported(d, metric)) {
+        J.xsplit = at<uint16_t>(ws, pl.off_xsplit);
+        J.xn2 = at<float>(ws, pl.off_xn2);
         J.nb_castB = (int32_t)split_blocks(nB, d);
-        J.nb_castX = 0;
+        J.nb_castX = (int32_t)split_blocks(pl.T, d);
         g = split_geom(pl.T, nB, d);
     } else {
         g = valu_geom(pl.T, nB, d);

@@ -159,8 +159,10 @@ struct Job {
     int32_t *idx;
     unsigned long long *best;
     float *nb2;
-    uint8_t *bq, *xq;
+    uint8_t *bq, *xq;  // low precision: cast B and draws; float32 l2: B's split table at bq
     float *lpf;
+    uint16_t *xsplit;  // float32 l2: the draws' split table and |x|^2
+    float *xn2;
     double *eta;
     chamfer_aux aux;
     // geometry

@@ -6,9 +6,9 @@
 //
 // Split.  v = h + m + r with h = bf16(v), m = bf16(v - h) (round to nearest
 // even; v - h is exact in float32), so |m| <= 2^-8 (1 + 2^-8) |v| and
-// |r| <= 2^-16 |v|.  B is split once per call into a row-major table of
-// [h[0..DP), m[0..DP)] per row (zero padded); each query is split in
-// registers.
+// |r| <= 2^-16 |v|.  B and the queries are split once per call into
+// row-major tables of [h[0..DP), m[0..DP)] per row (zero padded), the
+// queries' (in query order) with their |x|^2.
 //
 // Scores.  s(b) = |b|^2 - 2 x~.b~ with x~.b~ = xh.bh + xm.bh + xh.bm (three
 // BF16 MFMAs per 32 coordinates, TERMS = 3) or that plus xm.bm (TERMS = 4).
@@ -188,9 +188,8 @@ hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevPara
 
 bool mfma_supported(int d, int metric) { return metric == CHAMFER_L2 && d >= 12 && d <= 256; }
 
-// XS: Xs and xn2 hold the queries' split table and |x|^2, in query order;
-// otherwise each workgroup splits its queries in registers.
-template <int DP, int NB, int TERMS, bool XS>
+// Xs and xn2 hold the queries' split table and |x|^2, in query order.
+template <int DP, int NB, int TERMS>
 __device__ __forceinline__ void nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
@@ -227,39 +226,15 @@ __device__ __forceinline__ void nnmin_l2_split(
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
-        const int64_t r = qi < nx ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
-        qrow[nb] = r;
-        if constexpr (XS) {
-            const auto *xs = reinterpret_cast<const CH_RO uint4 *>(
-                ro(Xs) + (size_t)(qi < nx ? qi : 0) * (2 * DP) + g * KQ);
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                qh[nb][s] = ld(xs + s);
-                qm[nb][s] = ld(xs + DP / 8 + s);
-            }
-            qn2[nb] = qi < nx ? ro(xn2)[qi] : 0.0f;
-            continue;
-        }
-        const auto *xr = ro(X) + r * d;
-        float s2 = 0.0f;
+        qrow[nb] = qi < nx ? (rows ? (int64_t)ro(rows)[qi] : qi) : 0;
+        const auto *xs = reinterpret_cast<const CH_RO uint4 *>(
+            ro(Xs) + (size_t)(qi < nx ? qi : 0) * (2 * DP) + g * KQ);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t h[8], m[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = g * KQ + 8 * s + e;
-                const float v = k < d ? xr[k] : 0.0f;
-                s2 = fmaf(v, v, s2);
-                split2(v, h[e], m[e]);
-            }
-            qh[nb][s] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                                   h[6] | (h[7] << 16));
-            qm[nb][s] = make_uint4(m[0] | (m[1] << 16), m[2] | (m[3] << 16), m[4] | (m[5] << 16),
-                                   m[6] | (m[7] << 16));
+            qh[nb][s] = ld(xs + s);
+            qm[nb][s] = ld(xs + DP / 8 + s);
         }
-        s2 += __shfl_xor(s2, 16);
-        s2 += __shfl_xor(s2, 32);
-        qn2[nb] = s2;
+        qn2[nb] = qi < nx ? ro(xn2)[qi] : 0.0f;
     }
 
     // Per lane and query: the largest v = x~.b~ - |b|^2 / 2 over the lane's
@@ -458,8 +433,8 @@ __global__ __launch_bounds__(256) void k_nnmin_l2_split(
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
     const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
     DevParams *p) {
-    nnmin_l2_split<DP, NB, TERMS, true>(X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, chunk, nchunk,
-                                        best, p, grid_blk());
+    nnmin_l2_split<DP, NB, TERMS>(X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, chunk, nchunk, best,
+                                  p, grid_blk());
 }
 
 int64_t split_target_wgs(int d) { return split_target(split_dpad(d)); }
@@ -513,22 +488,26 @@ hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, c
 }
 
 // ---------------------------------------------------------------- batched
-// A job's split table lives at J.bq (its cast stage fills it); served
-// batches take the three-product form.
+// A job's split tables live at J.bq (B) and J.xsplit, J.xn2 (the draws); its
+// cast stage fills them.  Served batches take the three-product form.
 
 constexpr unsigned kGridSplit = 1024, kGridNNSplit = 2048;
 
 __global__ __launch_bounds__(256) void kb_split_rows(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsCast, [&](const Job &J, Blk b) {
-        split_rows(J.B, nullptr, J.nB, J.d, split_dpad(J.d), reinterpret_cast<uint16_t *>(J.bq),
-                   nullptr, J.p, b);
+        if (b.id < J.nb_castB)
+            split_rows(J.B, nullptr, J.nB, J.d, split_dpad(J.d),
+                       reinterpret_cast<uint16_t *>(J.bq), nullptr, J.p, Blk{b.id, J.nb_castB});
+        else
+            split_rows(J.A, J.idx, J.T, J.d, split_dpad(J.d), J.xsplit, J.xn2, J.p,
+                       Blk{b.id - J.nb_castB, J.nb_castX});
     });
 }
 
 template <int DP>
 __global__ __launch_bounds__(256) void kb_nn_split(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsNN, [&](const Job &J, Blk b) {
-        nnmin_l2_split<DP, split_nb(DP), 3, false>(J.A, J.idx, J.T, nullptr, nullptr, J.B,
+        nnmin_l2_split<DP, split_nb(DP), 3>(J.A, J.idx, J.T, J.xsplit, J.xn2, J.B,
                                             reinterpret_cast<const uint16_t *>(J.bq), J.nB, J.d,
                                             J.nb2, J.nn_chunk, J.nn_nchunk, J.best, J.p, b);
     });
