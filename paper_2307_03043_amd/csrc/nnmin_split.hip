@@ -52,14 +52,15 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kSplitMB = 2;                    // 16-row MFMA blocks per LDS tile
 constexpr int kSplitTileRows = 16 * kSplitMB;  // B rows per LDS tile
-// Launch shape by padded dimension, chosen by a measured sweep on MI355X:
+// Launch shape by padded dimension, chosen by measured sweeps on MI355X:
 // two 16-query blocks per wavefront (half the LDS reads per MFMA) up to
 // d_pad = 128, one at 256 (registers: three wavefronts per SIMD either way),
-// and a workgroup target that is a whole number of resident rounds
-// (2304 = 3 x 256 CUs x 3 workgroups; 1.6 vs 2.1 ms for the 10^6-point
-// exact pass of the 2000 draws at d = 128).
+// and a workgroup target that is a whole number of resident rounds of
+// 256 CUs x 3 workgroups: 3 rounds (2304) up to d_pad = 64, 6 (4608) at 128
+// (the 10^6-point exact pass of the 2000 draws at d = 128: 1.45 ms, against
+// 1.57 with 3 rounds and 2.1 with one query block and 4096 workgroups).
 __host__ __device__ constexpr int split_nb(int dp) { return dp <= 128 ? 2 : 1; }
-constexpr int64_t split_target(int dp) { return dp <= 128 ? 2304 : 4096; }
+constexpr int64_t split_target(int dp) { return dp <= 64 ? 2304 : dp <= 128 ? 4608 : 4096; }
 
 // Launches with at least this many queries take the four-product form: they
 // split B into few, long chunks, where near-ties inside a chunk (and so
