@@ -427,8 +427,10 @@ __device__ __forceinline__ void nnmin_l2_split(
     }
 }
 
+// Three wavefronts per SIMD with the accumulators in VGPRs: the epilogue
+// reads them without AGPR copies.
 template <int DP, int NB, int TERMS>
-__global__ __launch_bounds__(256) void k_nnmin_l2_split(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
