@@ -340,21 +340,29 @@ __device__ __forceinline__ void nnmin_l2_split(
                     }
                 }
             }
-            // Lane (g, j) holds rows 16m + 4g + r of the tile for query j.
+            // Lane (g, j) holds rows 16m + 4g + r of the tile for query j,
+            // taken in pairs (r, r + 1): the pair's larger value (the lower
+            // row on a tie) against the best, and the second largest of
+            // {best, pair} = med3 against the second.
 #pragma unroll
             for (int m = 0; m < kSplitMB; ++m)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int32_t brow = (int32_t)(t0 + 16 * m + 4 * g + r);
+                for (int r = 0; r < 4; r += 2) {
+                    const int32_t row0 = (int32_t)(t0 + 16 * m + 4 * g + r);
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
-                        float v = hi[m][nb][r];
-                        if constexpr (TERMS == 4) v += lo[m][nb][r];
+                        float v0 = hi[m][nb][r], v1 = hi[m][nb][r + 1];
+                        if constexpr (TERMS == 4) {
+                            v0 += lo[m][nb][r];
+                            v1 += lo[m][nb][r + 1];
+                        }
                         const float bv = bestv[nb];
-                        second[nb] = fmaxf(second[nb], fminf(bv, v));
-                        const bool gt = v > bv;
-                        bestv[nb] = gt ? v : bv;
-                        bidx[nb] = gt ? brow : bidx[nb];
+                        const bool up = v1 > v0;
+                        const float pm = up ? v1 : v0;
+                        second[nb] = fmaxf(second[nb], __builtin_amdgcn_fmed3f(bv, v0, v1));
+                        const bool gt = pm > bv;
+                        bestv[nb] = gt ? pm : bv;
+                        bidx[nb] = gt ? row0 + (int32_t)up : bidx[nb];
                     }
                 }
         }
