@@ -165,6 +165,11 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_bsplit = take(split ? split_table_bytes(nB, d) : 0);
     pl.off_xsplit = take(split ? split_table_bytes(nrow, d) : 0);
     pl.off_xn2 = take(split ? (size_t)nrow * sizeof(float) : 0);
+    // the deferred exact pass over the draws: its (draw, chunk) records live
+    // in the hash tables' region when that is large enough (the tables are
+    // done with before the draws are taken)
+    const size_t srec = split && estimating ? split_record_bytes(pl.T, nB, d) : 0;
+    pl.off_srec = h && srec <= table_bytes(pl.L, lc, pl.window) ? pl.off_tables : take(srec);
     const size_t rb = lp ? lowp_row_bytes(d, pl.precision) : 0;
     pl.off_bq = take(rb * (size_t)nB);
     pl.off_xq = take(rb * (size_t)nrow);
@@ -262,9 +267,11 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
 // form when requested and supported, else the float32 result (split-BF16
 // matrix cores for l2 when nb2 is given, vector ALU otherwise).  split_ready:
 // the split tables of B and of the queries are already in the workspace.
+// draws: X rows are the estimator's draws (the deferred split pass may use
+// its record region).
 int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64_t nx,
             const float *B, int64_t nB, unsigned long long *best, float *nb2, DevParams *p,
-            hipStream_t st, bool split_ready = false) {
+            hipStream_t st, bool split_ready = false, bool draws = false) {
     if (lowp_supported(pl.d, pl.metric, pl.precision)) {
         uint8_t *bq = at<uint8_t>(ws, pl.off_bq);
         uint8_t *xq = at<uint8_t>(ws, pl.off_xq);
@@ -284,7 +291,9 @@ int nn_pass(const Plan &pl, void *ws, const float *X, const int32_t *rows, int64
             CH_TRY(launch_split_rows(B, nB, pl.d, bs, p, st));
             CH_TRY(launch_split_queries(X, rows, nx, pl.d, xs, xn2, p, st));
         }
-        CH_TRY(launch_nnmin_split(X, rows, nx, xs, xn2, B, bs, nB, pl.d, best, nb2, p, st));
+        uint4 *rec = draws && split_record_bytes(nx, nB, pl.d) ? at<uint4>(ws, pl.off_srec)
+                                                               : nullptr;
+        CH_TRY(launch_nnmin_split(X, rows, nx, xs, xn2, B, bs, nB, pl.d, best, nb2, p, st, rec));
         return CHAMFER_OK;
     }
     CH_TRY(launch_nnmin(X, rows, nx, B, nB, pl.d, pl.metric, best, p, st));
@@ -600,7 +609,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
                                     at<float>(ws, pl.off_xn2), p, st));
     }
     CH_TRY(mark(ev, 4, st));
-    if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st, bsplit != nullptr)))
+    if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st, bsplit != nullptr, true)))
         return rc;
     CH_TRY(mark(ev, 5, st));
     CH_TRY(launch_estimate_final(best, idx, D, pl.T, metric, p, eta_out, ax, st));

@@ -31,6 +31,7 @@ __device__ __forceinline__ void init_params(DevParams *p, uint32_t *lohi, int d,
         p->S = 0.0;
         p->b2max_bits = 0;
         p->fallbacks = 0;
+        p->nredo = 0;
     }
     if (lohi != nullptr)
         for (int64_t k = t; k < (int64_t)kLohiReps * 2 * d; k += b.n * blockDim.x)

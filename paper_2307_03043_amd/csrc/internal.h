@@ -43,7 +43,9 @@ struct DevParams {
     double S;            // sum_k (hi_k - lo_k)
     uint32_t b2max_bits; // bits of max_b |b|^2 (float32, >= 0)
     uint32_t fallbacks;  // (query, chunk) pairs rescanned exactly by the MFMA pass
-    uint64_t pad[2];
+    uint32_t nredo;      // (query, chunk) pairs listed for the deferred pass's rescan
+    uint32_t pad32;
+    uint64_t pad[1];
 };
 
 // One bucket of a scale's open-addressing table: key -> lowest b index.
@@ -100,7 +102,7 @@ struct Plan {
     int log2cap;  // per-scale table capacity is 2^log2cap
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
-        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit, off_xsplit, off_xn2,
+        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit, off_xsplit, off_xn2, off_srec,
         off_bq, off_xq, off_lpf, total;
 };
 
@@ -364,10 +366,16 @@ hipError_t launch_split_rows(const float *B, int64_t nB, int d, uint16_t *out,
 hipError_t launch_split_queries(const float *X, const int32_t *rows, int64_t nx, int d,
                                 uint16_t *out, float *n2, const DevParams *p, hipStream_t st);
 // Xs, xn2: the queries' split table and norms (launch_split_queries).
+// rec (may be null): split_record_bytes(nx, nB, d) bytes for the deferred
+// form of launches over fewer than 16384 queries (the pass records its
+// chunk candidates, a second kernel certifies them per query and lists the
+// chunks to rescan, a third rescans them); null, or a launch over more
+// queries, certifies inside the pass.
+size_t split_record_bytes(int64_t nx, int64_t nB, int d);
 hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
                               const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
                               int d, unsigned long long *best, const float *nb2, DevParams *p,
-                              hipStream_t st);
+                              hipStream_t st, uint4 *rec = nullptr);
 // Low-precision (BF16 / FP8-E4M3) l2 nearest neighbours with float32 re-rank.
 int lowp_dpad(int d, int precision);
 bool lowp_supported(int d, int metric, int precision);

@@ -40,6 +40,15 @@
 // chunks merge with a 64-bit atomicMin of (accumulator bits << 32 | b).
 // Overflow of any norm makes E infinite, which sends every chunk to the
 // exact rescan.
+//
+// Deferred form (the estimator's draws): the pass only records, per (query,
+// chunk), the chunk's largest v, its row and the second largest v of the
+// whole chunk; k_split_resolve then takes each query in one wavefront,
+// bounds its minimum from above over all chunks, evaluates the canonical
+// distance of only those chunk candidates whose lower bound reaches that
+// bound (one per query on most data, instead of four per chunk), and lists
+// the chunks whose other rows it cannot exclude; k_split_redo rescans them
+// in pieces spread over the whole device.
 #include <cfloat>
 #include <cmath>
 
@@ -190,13 +199,15 @@ hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevPara
 bool mfma_supported(int d, int metric) { return metric == CHAMFER_L2 && d >= 12 && d <= 256; }
 
 // Xs and xn2 hold the queries' split table and |x|^2, in query order.
-template <int DP, int NB, int TERMS>
+// DEFER: write the (query, chunk) record to rec[query * nchunk + chunk]
+// instead of the re-rank and certificate (k_split_resolve completes them).
+template <int DP, int NB, int TERMS, bool DEFER = false>
 __device__ __forceinline__ void nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
     const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
-    DevParams *p, Blk blk) {
+    DevParams *p, Blk blk, uint4 *__restrict__ rec = nullptr) {
     constexpr int KQ = DP / 4;                   // coordinates per 16-lane group
     constexpr int NS = KQ / 8;                   // MFMA steps (8 coordinates per lane)
     constexpr int RB = 4 * DP;                   // bytes per split row (h then m)
@@ -371,6 +382,31 @@ __device__ __forceinline__ void nnmin_l2_split(
     }
     if (!wave_active) return;
 
+    if constexpr (DEFER) {
+        // the chunk's largest v over the four lane groups (the lower row on
+        // a tie) and the largest v of every other row of the chunk: the
+        // groups' second-best values and the other groups' best ones
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            float v1 = bestv[nb], v2 = second[nb];
+            int32_t i1 = bidx[nb];
+#pragma unroll
+            for (int off = 16; off <= 32; off <<= 1) {
+                const float o1 = __shfl_xor(v1, off), o2 = __shfl_xor(v2, off);
+                const int32_t oi = __shfl_xor(i1, off);
+                v2 = fmaxf(fmaxf(v2, o2), fminf(v1, o1));
+                const bool take = o1 > v1 || (o1 == v1 && oi < i1);
+                i1 = take ? oi : i1;
+                v1 = take ? o1 : v1;
+            }
+            const int64_t qi = qbase + nb * 16 + j;
+            if (g == 0 && qi < nx)
+                rec[(size_t)qi * nchunk + cb] =
+                    make_uint4(__float_as_uint(v1), (uint32_t)i1, __float_as_uint(v2), 0u);
+        }
+        return;
+    }
+
     // ---- re-rank and certificate, per block of 16 queries ----
     constexpr double kU = 1.0 / 16777216.0;                       // 2^-24
     constexpr double kTiny = 1.1754943508222875e-38;               // 2^-126
@@ -437,15 +473,141 @@ __device__ __forceinline__ void nnmin_l2_split(
 
 // Three wavefronts per SIMD with the accumulators in VGPRs: the epilogue
 // reads them without AGPR copies.
-template <int DP, int NB, int TERMS>
+template <int DP, int NB, int TERMS, bool DEFER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nnmin_l2_split(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const uint16_t *__restrict__ Xs, const float *__restrict__ xn2,
     const float *__restrict__ B, const uint16_t *__restrict__ Bs, int64_t nB, int d,
     const float *__restrict__ nb2, int64_t chunk, int nchunk, unsigned long long *best,
-    DevParams *p) {
-    nnmin_l2_split<DP, NB, TERMS>(X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, chunk, nchunk, best,
-                                  p, grid_blk());
+    DevParams *p, uint4 *__restrict__ rec) {
+    nnmin_l2_split<DP, NB, TERMS, DEFER>(X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, chunk, nchunk,
+                                         best, p, grid_blk(), rec);
+}
+
+// Second phase of the deferred form: one wavefront per query q (4 per
+// workgroup) over the nchunk records of q, with the bound E of the
+// three-product form.  (1) ub = the smallest upper bound (1 + 2 rho)
+// (s + E + |x|^2 (1 + 2 rho)) over the chunk candidates, s = -2 v: the
+// canonical minimum is at most ub.  (2) Every candidate whose lower bound
+// (1 - rho)(s - E + |x|^2 (1 - rho)) does not exceed ub is evaluated with the
+// canonical float32 distance; the others cannot reach the minimum, and thr
+// is the smallest value found.  (3) A chunk whose other rows have the lower
+// bound (1 - rho)(cut - E + |x|^2 (1 - rho)) > thr, cut = -2 v2, is settled;
+// the others are rescanned here when chunks are short (redo null), else
+// listed in redo (p->nredo entries) for k_split_redo.  best[q] = the
+// smallest (value, row) found.
+__global__ __launch_bounds__(256) void k_split_resolve(
+    const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
+    const float *__restrict__ xn2, const float *__restrict__ B, int64_t nB, int d, int DP,
+    int64_t chunk, int nchunk, const uint4 *__restrict__ rec, uint2 *__restrict__ redo,
+    unsigned long long *best, DevParams *p) {
+    if (p->status != CHAMFER_OK) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nx) return;  // uniform over the wavefront
+    constexpr double kU = 1.0 / 16777216.0;          // 2^-24
+    constexpr double kTiny = 1.1754943508222875e-38;  // 2^-126
+    const double rho = (double)(d + 4) * kU * 1.1;
+    const double crel = (double)(3 * DP + 8) * kU * 1.1;
+    const double ctr = 3.03 / 65536.0 * 1.1;
+    const double cabs = (double)(20 * DP + 16) * kTiny * 1.1;
+    const double cden = 8.0 * sqrt((double)DP) * kTiny * 1.1;
+    const double b2m = (double)__uint_as_float(p->b2max_bits) * (1.0 + rho);
+    const double bm = sqrt(b2m);
+    const double xn = (double)ro(xn2)[q];
+    const double xabs = sqrt(xn * (1.0 + rho));
+    const double E = cabs + cden * (xabs + bm) + crel * (b2m + 2.0 * xabs * bm) +
+                     2.0 * ctr * xabs * bm;
+    const double xlo = xn * (1.0 - rho), xhi = xn * (1.0 + 2.0 * rho);
+    const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
+    const CH_RO uint4 *r = ro(rec) + (size_t)q * nchunk;
+
+    double ub = INFINITY;
+    for (int c = lane; c < nchunk; c += 64) {
+        const float v = __uint_as_float(ld(r + c).x);
+        if (v > -INFINITY) ub = fmin(ub, (1.0 + 2.0 * rho) * (-2.0 * (double)v + E + xhi));
+    }
+    for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off));
+
+    unsigned long long m = ~0ull;
+    for (int c = lane; c < nchunk; c += 64) {
+        const uint4 w = ld(r + c);
+        const float v = __uint_as_float(w.x);
+        if (v > -INFINITY && !((1.0 - rho) * (-2.0 * (double)v - E + xlo) > ub))
+            m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + (int64_t)w.y * d, d), w.y));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
+    const double thr = (double)unpack_sp(m);
+
+    for (int c0 = 0; c0 < nchunk; c0 += 64) {
+        bool flag = false;
+        if (c0 + lane < nchunk) {
+            const float v2 = __uint_as_float(ld(r + c0 + lane).z);
+            flag = !((1.0 - rho) * (-2.0 * (double)v2 - E + xlo) > thr);
+        }
+        unsigned long long mask = __ballot(flag);
+        if (mask == 0) continue;
+        if (redo == nullptr) {
+            if (lane == 0) atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
+            while (mask) {
+                const int64_t c = c0 + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const int64_t b0 = c * chunk, b1 = min(nB, b0 + chunk);
+                for (int64_t b = b0 + lane; b < b1; b += 64)
+                    m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + b * d, d), b));
+            }
+            continue;
+        }
+        uint32_t base = 0;
+        if (lane == 0) {
+            base = atomicAdd(&p->nredo, (uint32_t)__popcll(mask));
+            atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
+        }
+        base = __shfl(base, 0);
+        if (flag)
+            redo[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] =
+                make_uint2((uint32_t)q, (uint32_t)(c0 + lane));
+    }
+    if (redo == nullptr)
+        for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
+    if (lane == 0) best[q] = m;
+}
+
+// Rescans of the deferred form: each listed (query, chunk) pair is cut into
+// pieces of kRedoRows rows dealt to the wavefronts of a fixed grid, so a
+// few long chunks do not serialise on one wavefront; each piece merges its
+// canonical minimum into best[query] with a 64-bit atomicMin.
+constexpr int64_t kRedoRows = 256;
+constexpr unsigned kGridRedo = 256;
+// Chunks up to this many rows are rescanned by the resolving wavefront
+// itself (a third launch costs more than such rescans at 10^5 points: 347-row
+// chunks); longer ones go to k_split_redo (3472-row chunks at 10^6).
+constexpr int64_t kRedoInlineRows = 512;
+
+__global__ __launch_bounds__(256) void k_split_redo(
+    const float *__restrict__ X, const int32_t *__restrict__ rows, const float *__restrict__ B,
+    int64_t nB, int d, int64_t chunk, const uint2 *__restrict__ redo,
+    unsigned long long *best, const DevParams *p) {
+    if (p->status != CHAMFER_OK) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t pieces = (chunk + kRedoRows - 1) / kRedoRows;
+    const int64_t total = (int64_t)p->nredo * pieces;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < total; t += nw) {
+        // (query, chunk) as the low and high words of one 64-bit load
+        const unsigned long long it =
+            ro(reinterpret_cast<const unsigned long long *>(redo))[t / pieces];
+        const int64_t q = (uint32_t)it, c = (uint32_t)(it >> 32);
+        const int64_t b0 = c * chunk + (t % pieces) * kRedoRows;
+        const int64_t b1 = min(min(nB, (c + 1) * chunk), b0 + kRedoRows);
+        const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
+        unsigned long long m = ~0ull;
+        for (int64_t b = b0 + lane; b < b1; b += 64)
+            m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + b * d, d), b));
+        for (int off = 32; off > 0; off >>= 1)
+            m = min(m, (unsigned long long)__shfl_xor(m, off));
+        if (lane == 0 && m != ~0ull) atomicMin(&best[q], m);
+    }
 }
 
 int64_t split_target_wgs(int d) { return split_target(split_dpad(d)); }
@@ -467,28 +629,47 @@ NNGeom split_geom(int64_t nx, int64_t nB, int d, int64_t target) {
     return g;
 }
 
+size_t split_record_bytes(int64_t nx, int64_t nB, int d) {
+    if (nx <= 0 || nB <= 0 || nx >= kSplitManyQueries) return 0;
+    // a record per (query, chunk), then room to list every pair for rescan
+    return (size_t)nx * (size_t)split_geom(nx, nB, d, 0).nchunk * (sizeof(uint4) + sizeof(uint2));
+}
+
 template <int DP>
 static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
                            const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
                            int d, unsigned long long *best, const float *nb2, DevParams *p,
-                           hipStream_t st) {
+                           uint4 *rec, hipStream_t st) {
     const NNGeom g = split_geom(nx, nB, d, 0);
-    if (nx >= kSplitManyQueries)
-        k_nnmin_l2_split<DP, split_nb(DP), 4><<<(unsigned)g.blocks, 256, 0, st>>>(
-            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
-    else
-        k_nnmin_l2_split<DP, split_nb(DP), 3><<<(unsigned)g.blocks, 256, 0, st>>>(
-            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p);
+    if (nx >= kSplitManyQueries) {
+        k_nnmin_l2_split<DP, split_nb(DP), 4, false><<<(unsigned)g.blocks, 256, 0, st>>>(
+            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p, nullptr);
+    } else if (rec != nullptr) {
+        k_nnmin_l2_split<DP, split_nb(DP), 3, true><<<(unsigned)g.blocks, 256, 0, st>>>(
+            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p, rec);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint2 *redo = g.chunk > kRedoInlineRows
+                          ? reinterpret_cast<uint2 *>(rec + (size_t)nx * g.nchunk)
+                          : nullptr;
+        k_split_resolve<<<(unsigned)((nx + 3) / 4), 256, 0, st>>>(
+            X, rows, nx, xn2, B, nB, d, DP, g.chunk, g.nchunk, rec, redo, best, p);
+        if (redo != nullptr)
+            k_split_redo<<<kGridRedo, 256, 0, st>>>(X, rows, B, nB, d, g.chunk, redo, best, p);
+    } else {
+        k_nnmin_l2_split<DP, split_nb(DP), 3, false><<<(unsigned)g.blocks, 256, 0, st>>>(
+            X, rows, nx, Xs, xn2, B, Bs, nB, d, nb2, g.chunk, g.nchunk, best, p, nullptr);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_nnmin_split(const float *X, const int32_t *rows, int64_t nx, const uint16_t *Xs,
                               const float *xn2, const float *B, const uint16_t *Bs, int64_t nB,
                               int d, unsigned long long *best, const float *nb2, DevParams *p,
-                              hipStream_t st) {
+                              hipStream_t st, uint4 *rec) {
     if (nx <= 0) return hipSuccess;
     if (Xs == nullptr || xn2 == nullptr) return hipErrorInvalidValue;
-#define CH_SPLIT_ARGS X, rows, nx, Xs, xn2, B, Bs, nB, d, best, nb2, p, st
+#define CH_SPLIT_ARGS X, rows, nx, Xs, xn2, B, Bs, nB, d, best, nb2, p, rec, st
     switch (split_dpad(d)) {
         case 32: return go_split<32>(CH_SPLIT_ARGS);
         case 64: return go_split<64>(CH_SPLIT_ARGS);

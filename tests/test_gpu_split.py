@@ -140,3 +140,58 @@ def test_estimate_matches_oracle_on_offset_data(ch, orc):
     assert np.array_equal(host(out["sample_nn"]), a32)
     assert np.array_equal(host(out["sample_min"]).view(np.uint32), m32.view(np.uint32))
     assert float(host(out["eta"])[0]) == pytest.approx(ref["eta"], rel=1e-5)
+
+
+def check_estimate_draws(ch, orc, A, B, eps, T, seed):
+    out = ch.chamfer_estimate(dev(A), dev(B), L2, eps, T, seed)
+    ref = orc.chamfer_estimate(A, B, L2, eps, T, seed)
+    assert np.array_equal(host(out["sample_idx"]), ref["idx"])
+    m32, a32 = orc.nn_f32(A, B, L2, rows=ref["idx"])
+    assert np.array_equal(host(out["sample_nn"]), a32)
+    assert np.array_equal(host(out["sample_min"]).view(np.uint32), m32.view(np.uint32))
+
+
+def test_estimate_draws_near_ties(ch, orc):
+    """The estimator's pass over its draws (chunk candidates recorded, then
+    certified per draw) on near-ties one float32 ulp apart: each draw's two
+    nearest rows of B are in different chunks or the same one."""
+    banner("split estimate near ties")
+    rng = np.random.default_rng(8)
+    d = 96
+    A = rng.normal(size=(3000, d)).astype(np.float32)
+    base = A[rng.integers(0, 3000, size=1500)]
+    B = np.empty((3000, d), np.float32)
+    B[0::2] = base + np.float32(0.25)
+    B[1::2] = base + np.float32(0.25)
+    B[1::2, 0] = np.nextafter(B[1::2, 0], np.float32(np.inf))
+    # and a second copy far away in B's order (another chunk)
+    B = np.concatenate([B, B[::-1]]).astype(np.float32)
+    check_estimate_draws(ch, orc, A, B, 0.2, 600, 3)
+
+
+def test_estimate_draws_duplicates(ch, orc):
+    """Exact duplicate rows of B next to each other (equal candidates in one
+    chunk: the chunk is rescanned) and the lowest index must win."""
+    banner("split estimate duplicates")
+    A, B0 = workloads.clusters_l2(seed=17, n=2500, d=128, k=25, n_b=900)
+    B = np.repeat(B0, 3, axis=0).astype(np.float32)
+    check_estimate_draws(ch, orc, A, B, 0.2, 500, 11)
+
+
+@pytest.mark.parametrize("d", [16, 64, 200])
+def test_estimate_draws_dimension_classes(ch, orc, d):
+    banner(f"split estimate d={d}")
+    A, B = workloads.clusters_l2(seed=60 + d, n=4000, d=d, k=40, n_b=5000)
+    check_estimate_draws(ch, orc, A, B, 0.2, 700, 2)
+
+
+@pytest.mark.parametrize("offset", [0.0, 300.0])
+def test_estimate_draws_long_chunks(ch, orc, offset):
+    """2000 draws against 80000 rows at d = 16: chunks of more than 512
+    rows, whose rescans are cut into pieces over the whole device; with an
+    offset of 300 most (draw, chunk) pairs are rescanned."""
+    banner(f"split estimate long chunks offset={offset}")
+    A, B = workloads.clusters_l2(seed=77, n=5000, d=16, k=50, n_b=80000)
+    A = (A + np.float32(offset)).astype(np.float32)
+    B = (B + np.float32(offset)).astype(np.float32)
+    check_estimate_draws(ch, orc, A, B, 0.1, 2000, 4)
