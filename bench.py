@@ -118,9 +118,10 @@ def algorithmic_sample_pass(metric, T, n_b, d):
 
 
 def measured_traffic(workload, kernel_ms):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    record (FETCH_SIZE/WRITE_SIZE, copy-calibrated), or None when there is no
-    record for this workload or the kernel source changed since it was taken."""
+    """HBM bytes per launch of the exact pass over the draws (the sum over its
+    kernels) from the committed counter record (FETCH_SIZE/WRITE_SIZE,
+    copy-calibrated), or None when there is no record for this workload or
+    the kernels' sources changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
@@ -739,7 +740,8 @@ def main():
     dom = int(np.argmax(stage.mean(axis=0)))
     lam = float(aux["D"].item())
 
-    # roofline of the exact pass over the draws (one kernel, stage 4 -> 5)
+    # roofline of the exact pass over the draws (stage 4 -> 5: for l2 the
+    # record pass on the matrix cores and the per-draw resolve kernel)
     work = algorithmic_sample_pass(metric, T, n_b, d)
     kernel_ms = stages_ms["exact_pass"]
     achieved = work["ops"] / (kernel_ms * 1e-3) / 1e12
@@ -749,7 +751,8 @@ def main():
                 "traffic": measured_traffic(args.workload, kernel_ms), "kernel_ms": kernel_ms,
                 "algorithmic": work["note"]}
     if "products" in work:
-        roofline["kernel"] = "k_nnmin_l2_split (exact pass over the T draws)"
+        roofline["kernel"] = ("k_nnmin_l2_split record pass + k_split_resolve "
+                              "(exact pass over the T draws)")
         roofline["mfma_dtype"] = "bf16"
         roofline["frac_of_split_ceiling"] = achieved * work["products"] / work["peak"]
 

@@ -233,11 +233,12 @@ __device__ __forceinline__ uint4 ld(const CH_RO uint4 *p) {
 // Canonical float32 distance accumulator between rows a and b: k ascending,
 // one rounding per operation; l1: acc + |a_k - b_k|, l2: fma(t, t, acc) with
 // t = a_k - b_k (the caller takes the square root for l2).  Loads are issued
-// in batches of 8 x 16 bytes ahead of the (sequential) arithmetic, so a row
-// costs a few memory round trips instead of one per 16 bytes.  Both rows
-// must be read-only for the kernel that calls it (they are read through
-// the constant address space).
-template <int METRIC>
+// in batches of BATCH x 16 bytes ahead of the (sequential) arithmetic, so a
+// row costs a few memory round trips instead of one per 16 bytes (kernels
+// with registers to spare take BATCH = 16: two round trips at d = 128).
+// Both rows must be read-only for the kernel that calls it (they are read
+// through the constant address space).
+template <int METRIC, int BATCH = 8>
 __device__ __forceinline__ float canon_acc(const float *__restrict__ a,
                                            const float *__restrict__ b, int d) {
     float acc = 0.0f;
@@ -250,7 +251,7 @@ __device__ __forceinline__ float canon_acc(const float *__restrict__ a,
         const auto *a4 = reinterpret_cast<const CH_RO float4 *>(ro(a));
         const auto *b4 = reinterpret_cast<const CH_RO float4 *>(ro(b));
         const int d4 = d >> 2;
-        constexpr int kBatch = 8;
+        constexpr int kBatch = BATCH;
         for (int k0 = 0; k0 < d4; k0 += kBatch) {
             float4 u[kBatch], v[kBatch];
 #pragma unroll

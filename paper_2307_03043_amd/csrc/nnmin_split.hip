@@ -496,6 +496,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // the others are rescanned here when chunks are short (redo null), else
 // listed in redo (p->nredo entries) for k_split_redo.  best[q] = the
 // smallest (value, row) found.
+// K > 0: the query's records are read once into K registers per lane
+// (nchunk <= 64 K), so the three passes over them wait on one round of
+// loads; K = 0 reads them from memory in each pass.
+template <int K>
 __global__ __launch_bounds__(256) void k_split_resolve(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const float *__restrict__ xn2, const float *__restrict__ B, int64_t nB, int d, int DP,
@@ -505,6 +509,22 @@ __global__ __launch_bounds__(256) void k_split_resolve(
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= nx) return;  // uniform over the wavefront
+    const CH_RO uint4 *r = ro(rec) + (size_t)q * nchunk;
+    // records past nchunk read as empty chunks (v = v2 = -inf)
+    const uint4 none = make_uint4(0xff800000u, 0u, 0xff800000u, 0u);
+    uint4 w[K > 0 ? K : 1];
+    if constexpr (K > 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            w[i] = i * 64 + lane < nchunk ? ld(r + i * 64 + lane) : none;
+    }
+    auto rec_at = [&](int i) -> uint4 {
+        if constexpr (K > 0) return w[i];
+        return i * 64 + lane < nchunk ? ld(r + i * 64 + lane) : none;
+    };
+    const int iters = K > 0 ? K : (nchunk + 63) / 64;
+    constexpr int kUnroll = K > 0 ? K : 1;
+
     constexpr double kU = 1.0 / 16777216.0;          // 2^-24
     constexpr double kTiny = 1.1754943508222875e-38;  // 2^-126
     const double rho = (double)(d + 4) * kU * 1.1;
@@ -520,31 +540,32 @@ __global__ __launch_bounds__(256) void k_split_resolve(
                      2.0 * ctr * xabs * bm;
     const double xlo = xn * (1.0 - rho), xhi = xn * (1.0 + 2.0 * rho);
     const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
-    const CH_RO uint4 *r = ro(rec) + (size_t)q * nchunk;
 
     double ub = INFINITY;
-    for (int c = lane; c < nchunk; c += 64) {
-        const float v = __uint_as_float(ld(r + c).x);
+#pragma unroll kUnroll
+    for (int i = 0; i < iters; ++i) {
+        const float v = __uint_as_float(rec_at(i).x);
         if (v > -INFINITY) ub = fmin(ub, (1.0 + 2.0 * rho) * (-2.0 * (double)v + E + xhi));
     }
     for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off));
 
     unsigned long long m = ~0ull;
-    for (int c = lane; c < nchunk; c += 64) {
-        const uint4 w = ld(r + c);
-        const float v = __uint_as_float(w.x);
+#pragma unroll kUnroll
+    for (int i = 0; i < iters; ++i) {
+        const uint4 c = rec_at(i);
+        const float v = __uint_as_float(c.x);
         if (v > -INFINITY && !((1.0 - rho) * (-2.0 * (double)v - E + xlo) > ub))
-            m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + (int64_t)w.y * d, d), w.y));
+            m = min(m, pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + (int64_t)c.y * d, d), c.y));
     }
     for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
     const double thr = (double)unpack_sp(m);
 
-    for (int c0 = 0; c0 < nchunk; c0 += 64) {
-        bool flag = false;
-        if (c0 + lane < nchunk) {
-            const float v2 = __uint_as_float(ld(r + c0 + lane).z);
-            flag = !((1.0 - rho) * (-2.0 * (double)v2 - E + xlo) > thr);
-        }
+#pragma unroll kUnroll
+    for (int i = 0; i < iters; ++i) {
+        const int c0 = i * 64;
+        const float v2 = __uint_as_float(rec_at(i).z);
+        const bool flag =
+            c0 + lane < nchunk && !((1.0 - rho) * (-2.0 * (double)v2 - E + xlo) > thr);
         unsigned long long mask = __ballot(flag);
         if (mask == 0) continue;
         if (redo == nullptr) {
@@ -554,7 +575,7 @@ __global__ __launch_bounds__(256) void k_split_resolve(
                 mask &= mask - 1;
                 const int64_t b0 = c * chunk, b1 = min(nB, b0 + chunk);
                 for (int64_t b = b0 + lane; b < b1; b += 64)
-                    m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + b * d, d), b));
+                    m = min(m, pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + b * d, d), b));
             }
             continue;
         }
@@ -583,6 +604,9 @@ constexpr unsigned kGridRedo = 256;
 // itself (a third launch costs more than such rescans at 10^5 points: 347-row
 // chunks); longer ones go to k_split_redo (3472-row chunks at 10^6).
 constexpr int64_t kRedoInlineRows = 512;
+// Records per lane that k_split_resolve keeps in registers (up to 512
+// chunks: 288 for the 2000 draws at d <= 128).
+constexpr int kResolveRegs = 8;
 
 __global__ __launch_bounds__(256) void k_split_redo(
     const float *__restrict__ X, const int32_t *__restrict__ rows, const float *__restrict__ B,
@@ -603,7 +627,7 @@ __global__ __launch_bounds__(256) void k_split_redo(
         const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
         unsigned long long m = ~0ull;
         for (int64_t b = b0 + lane; b < b1; b += 64)
-            m = min(m, pack_sp(canon_acc<CHAMFER_L2>(x, B + b * d, d), b));
+            m = min(m, pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + b * d, d), b));
         for (int off = 32; off > 0; off >>= 1)
             m = min(m, (unsigned long long)__shfl_xor(m, off));
         if (lane == 0 && m != ~0ull) atomicMin(&best[q], m);
@@ -652,8 +676,13 @@ static hipError_t go_split(const float *X, const int32_t *rows, int64_t nx, cons
         uint2 *redo = g.chunk > kRedoInlineRows
                           ? reinterpret_cast<uint2 *>(rec + (size_t)nx * g.nchunk)
                           : nullptr;
-        k_split_resolve<<<(unsigned)((nx + 3) / 4), 256, 0, st>>>(
-            X, rows, nx, xn2, B, nB, d, DP, g.chunk, g.nchunk, rec, redo, best, p);
+        const unsigned nbr = (unsigned)((nx + 3) / 4);
+        if (g.nchunk <= 64 * kResolveRegs)
+            k_split_resolve<kResolveRegs><<<nbr, 256, 0, st>>>(
+                X, rows, nx, xn2, B, nB, d, DP, g.chunk, g.nchunk, rec, redo, best, p);
+        else
+            k_split_resolve<0><<<nbr, 256, 0, st>>>(X, rows, nx, xn2, B, nB, d, DP, g.chunk,
+                                                    g.nchunk, rec, redo, best, p);
         if (redo != nullptr)
             k_split_redo<<<kGridRedo, 256, 0, st>>>(X, rows, B, nB, d, g.chunk, redo, best, p);
     } else {

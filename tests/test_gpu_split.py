@@ -195,3 +195,12 @@ def test_estimate_draws_long_chunks(ch, orc, offset):
     A = (A + np.float32(offset)).astype(np.float32)
     B = (B + np.float32(offset)).astype(np.float32)
     check_estimate_draws(ch, orc, A, B, 0.1, 2000, 4)
+
+
+def test_estimate_draws_many_chunks(ch, orc):
+    """100 draws against 200000 rows: one block of draws, so B is cut into
+    more than 512 chunks and the per-draw certificate reads its records from
+    memory in each pass instead of holding them in registers."""
+    banner("split estimate many chunks")
+    A, B = workloads.clusters_l2(seed=91, n=3000, d=16, k=60, n_b=200000)
+    check_estimate_draws(ch, orc, A, B, 0.2, 100, 6)
