@@ -88,6 +88,7 @@ def lib():
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_INT)]
     L.or_hash_keys.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _INT, _INT,
                                _F32, _U64, _U64]
+    L.or_hashed_coords.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _F32]
     L.or_crude_nn.argtypes = [_U64, _I64, _U64, _I64, _INT, _F32, _F32, _INT, _INT,
                               _I32, _I32, _F32]
     L.or_crude_window.argtypes = [_U64, _I64, _U64, _I64, _INT, _INT, _F32, _F32, _INT, _INT,
@@ -179,6 +180,20 @@ def calibrate(A, B):
     e = _INT()
     lib().or_calibrate(A, A.shape[0], B, B.shape[0], d, lo, hi, ctypes.byref(S), ctypes.byref(e))
     return lo, hi, S.value, e.value
+
+
+def hashed_coords(X, metric, lo, Zs) -> np.ndarray:
+    """The coordinates the grid hash sees, Y[n, kh]: x - lo for l1 and, for
+    l2, the embedding T(x - lo) of the appendix theorem embedding l2 into l1,
+    accumulated as a float32 fused multiply-add chain in ascending k."""
+    X = _f32(X)
+    n, d = X.shape
+    kh = d if metric == 1 else Zs.shape[0]
+    Y = np.zeros((n, kh), np.float32)
+    Zs = None if Zs is None else _f32(Zs)
+    zp = None if Zs is None else Zs.ctypes.data
+    lib().or_hashed_coords(X, n, d, metric, _f32(lo), zp, 0 if Zs is None else Zs.shape[0], Y)
+    return Y
 
 
 def hash_keys(X, metric, lo, Zs, L, e_top, zfrac, mult) -> np.ndarray:

@@ -228,6 +228,16 @@ static void hashed_coords(const float *x, int d, int metric, const float *lo,
     }
 }
 
+/* The hashed coordinates of every point of X, Y[n][kh] (kh = d for l1,
+ * ke for l2); exported so the embedding step can be checked on its own. */
+void or_hashed_coords(const float *X, int64_t n, int d, int metric, const float *lo,
+                      const float *Zs, int ke, float *Y)
+{
+    int kh = metric == OR_L1 ? d : ke;
+    for (int64_t p = 0; p < n; ++p)
+        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, Y + (size_t)p * kh);
+}
+
 /* Bucket key of point y at scale i (side 2^e):
  *   cell_k = ceilf(ldexpf(y_k, -e) + z'_ik) + 0.0f   (the +0 folds -0 into +0)
  *   key    = (sum_k bits(cell_k) * M_ik mod 2^64) >> 1

@@ -231,6 +231,117 @@ def test_embedding_normalisation(orc):
     assert stats.kstest(Zs.ravel(), "norm").pvalue > 1e-4
 
 
+def _embed_bound(Zs, Xc):
+    """Rounding bound of the float32 embedding: x - lo rounds once (u), and
+    the d-term fused multiply-add chain rounds d times, so
+    |y - Zs (x - lo)| <= (d + 1) u (1 + 2du) sum_k |Zs_jk| |x_k - lo_k|."""
+    d = Xc.shape[1]
+    return (d + 1) * U32 * (1 + 2 * d * U32) * (np.abs(Xc) @ np.abs(Zs.astype(np.float64)).T)
+
+
+@pytest.mark.parametrize("d", [5, 32, 128])
+def test_l2_hashed_coords_vs_float64(orc, d):
+    """The l2 hashed coordinates are the embedding T(x - lo) of the appendix
+    theorem embedding l2 into l1 (T = Zs, one row per embedded coordinate):
+    compared with a float64 matrix product within the float32 rounding bound.
+    d = 32 = ke makes a transposed matrix index produce a valid but different
+    product, and the offset of the cloud makes a dropped - lo visible; both
+    planted mistakes are shown to fail the bound."""
+    rng = np.random.default_rng(100 + d)
+    X = (rng.standard_normal((300, d)) * 3.0 + 40.0).astype(np.float32)
+    lo = X.min(axis=0) - np.float32(0.5)
+    Zs = orc.embedding(11, d, 32)
+    Y = orc.hashed_coords(X, 2, lo, Zs).astype(np.float64)
+    Xc = X.astype(np.float64) - lo.astype(np.float64)
+    ref = Xc @ Zs.astype(np.float64).T
+    bound = _embed_bound(Zs, Xc)
+    assert Y.shape == (300, 32)
+    assert np.all(np.abs(Y - ref) <= bound), np.max(np.abs(Y - ref) / bound)
+    # l1 hashes x - lo, one float32 subtraction per coordinate
+    Y1 = orc.hashed_coords(X, 1, lo, None)
+    assert np.array_equal(Y1, (X - lo).astype(np.float32))
+    # the pin rejects the plausible mistakes
+    no_lo = X.astype(np.float64) @ Zs.astype(np.float64).T
+    assert np.any(np.abs(no_lo - ref) > bound)
+    if d == 32:
+        transposed = Xc @ Zs.astype(np.float64)
+        assert np.any(np.abs(transposed - ref) > bound)
+
+
+def _key_from_cells(cells32, mult):
+    """(sum_k bits(cell_k) M_k mod 2^64) >> 1 in Python integers."""
+    bits = cells32.view(np.uint32).astype(object)
+    acc = 0
+    for b, m in zip(bits, mult.astype(object)):
+        acc = (acc + int(b) * int(m)) % (1 << 64)
+    return acc >> 1
+
+
+def test_l2_keys_from_float64_cells(orc):
+    """l2 keys end to end: cells ceil(y / r + z') computed from the float64
+    embedding, keyed in Python integers, equal the oracle's keys at every
+    scale for every coordinate whose cell boundary is farther away than the
+    float32 rounding of y and of the shifted coordinate (the others are
+    skipped: there either cell is right)."""
+    rng = np.random.default_rng(7)
+    n, d, ke, L = 200, 24, 32, 6
+    X = (rng.standard_normal((n, d)) * 2.0 - 5.0).astype(np.float32)
+    lo = X.min(axis=0)
+    Zs = orc.embedding(5, d, ke)
+    zf, mt = orc.grid_tables(5, L, ke)
+    e_top = 3
+    keys = orc.hash_keys(X, 2, lo, Zs, L, e_top, zf, mt)
+    Xc = X.astype(np.float64) - lo.astype(np.float64)
+    y64 = Xc @ Zs.astype(np.float64).T
+    yerr = _embed_bound(Zs, Xc)
+    checked = 0
+    for i in range(L):
+        e = e_top - (L - 1 - i)
+        q = np.ldexp(y64, -e) + zf[i].astype(np.float64)
+        # float32 of y, then one rounding of the shifted sum
+        margin = np.ldexp(yerr, -e) + 2 * U32 * (np.abs(q) + 1.0)
+        frac_dist = q - np.floor(q)
+        near = (frac_dist <= margin) | (1.0 - frac_dist <= margin)
+        cells = (np.ceil(q).astype(np.float32) + np.float32(0.0)).astype(np.float32)
+        for p in range(n):
+            if near[p].any():
+                continue
+            assert int(keys[i, p]) == _key_from_cells(cells[p], mt[i]), (i, p)
+            checked += 1
+    assert checked > 0.9 * n * L
+
+
+@pytest.mark.parametrize("ratio", [0.3, 1.0, 2.5])
+def test_l2_collision_probability(orc, ratio):
+    """l2 grid hash through the embedding: given the embedding Zs drawn by a
+    seed, the keys of x and x' at side r collide with probability
+    prod_j max(0, 1 - |(Zs (x - x'))_j| / r) (appendix lemma on the grid
+    hash, applied to the embedded coordinates; shifts and embedding come
+    from independent streams).  Monte Carlo over seeds: the mean of the
+    collision indicator matches the mean predicted probability."""
+    d, ke, e = 6, 32, 0
+    rng = np.random.default_rng(int(ratio * 10))
+    x = rng.uniform(0.0, 4.0, d).astype(np.float32)
+    v = rng.standard_normal(d)
+    xp = (x + ratio * v / np.linalg.norm(v)).astype(np.float32)
+    X = np.stack([x, xp])
+    lo = np.zeros(d, np.float32)
+    n_seeds = 2500
+    hits, probs = 0, []
+    for s in range(n_seeds):
+        Zs = orc.embedding(3000 + s, d, ke)
+        zf, mt = orc.grid_tables(3000 + s, 1, ke)
+        k = orc.hash_keys(X, 2, lo, Zs, 1, e, zf, mt)[0]
+        hits += int(k[0] == k[1])
+        dy = Zs.astype(np.float64) @ (xp.astype(np.float64) - x.astype(np.float64))
+        probs.append(float(np.prod(np.maximum(0.0, 1.0 - np.abs(dy) / 2.0 ** e))))
+    probs = np.array(probs)
+    p = probs.mean()
+    sd = math.sqrt(max(float(np.mean(probs * (1 - probs))), 1e-12) / n_seeds)
+    assert abs(hits / n_seeds - p) <= 4.5 * sd + 1e-3, (ratio, hits / n_seeds, p)
+    assert 0.02 < p < 0.95
+
+
 # -------------------------------------------------------------- CrudeNN ----
 
 @pytest.mark.parametrize("metric", [1, 2])
