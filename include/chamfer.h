@@ -14,8 +14,11 @@
  *   [n, d] (row p at X + p*d).  Every other array argument is a device
  *   pointer too, unless marked "host".  The caller owns all memory,
  *   including the workspace `ws` (size from chamfer_workspace_bytes); the
- *   library never allocates or frees device memory and keeps no state
- *   between calls.
+ *   library never allocates or frees device memory.  It keeps no state
+ *   between calls, with two exceptions: a server (chamfer_server_create)
+ *   owns its arena and lanes until chamfer_server_destroy, and
+ *   chamfer_retrieve creates three side streams per device on its first
+ *   call there and keeps them until the process ends.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *   work is enqueued on it asynchronously; the caller synchronises.  Output
  *   buffers are valid once the stream has reached the end of the call.
@@ -26,6 +29,14 @@
  *   optional device status word and make the floating outputs NaN.
  * - Calls on one stream with one workspace must not overlap; calls with
  *   distinct workspaces may run concurrently on distinct streams.
+ * - Graph capture: chamfer_exact, chamfer_nn_min, crude_nn and
+ *   chamfer_estimate with l1 (or with uniform sampling) enqueue kernels
+ *   only, with no host synchronisation, and may be captured into a HIP
+ *   graph.  An l2 call that hashes (crude_nn, chamfer_hash_keys,
+ *   chamfer_estimate with importance sampling) uploads the embedding
+ *   matrix, drawn on the host for this seed, from a host buffer that the
+ *   next call overwrites: a replay would read whatever that buffer then
+ *   holds.  Such calls return CHAMFER_EINVAL when `stream` is capturing.
  * - Results are deterministic: the same arguments give bit-identical outputs
  *   on every run, whatever the launch configuration (no floating-point
  *   atomics; integer atomics only for min/max, whose result is order-free).
@@ -104,9 +115,12 @@ typedef struct chamfer_aux {
     /* Host array of CHAMFER_STAGE_EVENTS hipEvent_t (as void*), or NULL.  When
      * set, event i is recorded on the stream at stage boundary i: 0 start,
      * 1 calibration and tables done, 2 B bucketed, 3 CrudeNN done (D_a),
-     * 4 weights and draws (and, for l2, the BF16 split table of B) done,
-     * 5 exact pass over the draws done, 6 end.
-     * Stage 4->5 is a single kernel (the nearest-neighbour pass). */
+     * 4 weights and draws done, 5 exact pass over the draws done, 6 end.
+     * Stage 4->5 is the nearest-neighbour pass over the draws: for l2 with
+     * 12 <= d <= 256 the BF16 split tables of B and of the draws, the
+     * matrix-core record kernel, the per-draw resolve kernel and, when B's
+     * chunks are longer than 512 rows, the rescan kernel; otherwise one
+     * vector-ALU kernel. */
     void **stage_events;
 } chamfer_aux;
 
@@ -406,6 +420,15 @@ int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps); /* L defau
  * host memory; the same matrix chamfer_estimate uses for `seed`. */
 int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, float *Z_host);
 const char *chamfer_strerror(int status);
+/* The bound E of the l2 exact pass's certificate (the exact pass of
+ * chamfer_exact, chamfer_nn_min and chamfer_estimate for l2 with
+ * 12 <= d <= 256, FP32 precision): for a query x with float32 |x|^2 = xn2
+ * and rows b with float32 |b|^2 <= b2max, the matrix-core score of every b
+ * is within E of |b|^2 - 2 x.b, assuming the matrix cores add each product
+ * to their float32 accumulator with one rounding to nearest.  terms = 3
+ * (the estimator's draws, batches below 16384 queries) or 4 (larger
+ * batches).  Returns -1 for d outside 1..256 or other terms. */
+double chamfer_split_score_bound(int32_t d, int32_t terms, float xn2, float b2max);
 
 #ifdef __cplusplus
 }

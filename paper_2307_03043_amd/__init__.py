@@ -96,6 +96,7 @@ _SIGS = {
                                              _VP]),
     "chamfer_default_scales": (ctypes.c_int32, [_I64, _I64, _F64]),
     "chamfer_embedding_matrix": (ctypes.c_int, [_U64, _I32, _I32, _VP]),
+    "chamfer_split_score_bound": (ctypes.c_double, [_I32, _I32, ctypes.c_float, ctypes.c_float]),
     "chamfer_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "chamfer_server_create": (ctypes.c_int, [ctypes.c_size_t, _I32, _VP]),
     "chamfer_server_warm": (ctypes.c_int, [_VP, _I32, _I32, _I32, _I32]),
@@ -195,6 +196,11 @@ def chamfer_default_samples(n_a: int, eps: float) -> int:
 
 def chamfer_default_scales(n_a: int, n_b: int, eps: float) -> int:
     return int(lib().chamfer_default_scales(n_a, n_b, eps))
+
+
+def chamfer_split_score_bound(d: int, terms: int, xn2: float, b2max: float) -> float:
+    """The certificate bound E of the l2 exact pass (host arithmetic only)."""
+    return float(lib().chamfer_split_score_bound(d, terms, xn2, b2max))
 
 
 def chamfer_embedding_matrix(seed: int, d: int, embed_dim: int = 32) -> np.ndarray:

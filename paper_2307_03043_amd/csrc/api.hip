@@ -207,7 +207,12 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
                         at<uint64_t>(ws, pl.off_mult), nullptr, 0, st));
     if (pl.metric == CHAMFER_L2) {
         // The embedding matrix is drawn on the host (it needs log and cos in
-        // double precision) and uploaded transposed, [d][ke].
+        // double precision) and uploaded transposed, [d][ke], from a buffer
+        // the next call overwrites: a captured copy would replay from it, so
+        // a capturing stream is refused.
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        CH_TRY(hipStreamIsCapturing(st, &cs));
+        if (cs != hipStreamCaptureStatusNone) return CHAMFER_EINVAL;
         thread_local std::vector<float> zt;
         zt.resize((size_t)pl.ke * pl.d);
         embedding_transposed(seed, pl.d, pl.ke, zt.data());
@@ -600,15 +605,15 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
-    // the split tables of B and of the draws, written after the hash tables
-    // are done with (they would evict them from the last-level cache) and
-    // just before their reader
+    CH_TRY(mark(ev, 4, st));
+    // the split tables of B and of the draws (part of the exact pass),
+    // written after the hash tables are done with (they would evict them
+    // from the last-level cache) and just before their reader
     if (bsplit) {
         CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
         CH_TRY(launch_split_queries(A, idx, pl.T, d, at<uint16_t>(ws, pl.off_xsplit),
                                     at<float>(ws, pl.off_xn2), p, st));
     }
-    CH_TRY(mark(ev, 4, st));
     if ((rc = nn_pass(pl, ws, A, idx, pl.T, B, n_B, best, nb2, p, st, bsplit != nullptr, true)))
         return rc;
     CH_TRY(mark(ev, 5, st));

@@ -14,23 +14,31 @@
 // BF16 MFMAs per 32 coordinates, TERMS = 3) or that plus xm.bm (TERMS = 4).
 // The accumulator of each (b, x) starts at -|b|^2 / 2 (exact), so it ends at
 // v = -s / 2 and the selection keeps the largest v.  BF16 products are
-// exact in float32.  The dropped terms sum to at most
-// c_tr |x| |b| (Cauchy-Schwarz over k): (xh + xm).rb + rx.(bh + bm) + rx.rb
-// gives 2.01 * 2^-16 and xm.bm adds at most 1.02 * 2^-16.  With adders that
-// round to nearest (the model assumed for the matrix cores), the float32
-// accumulation errs by at most u per addition times the sum of the terms'
-// magnitudes.  TERMS = 3 accumulates all 3 DP products in one register
-// (|b|^2 / 2 + 1.02 |x||b| of magnitude): c_rel = (3 DP + 8) u 1.1.
-// TERMS = 4 keeps the leading products xh.bh (DP additions,
-// |b|^2 / 2 + 1.008 |x||b|) apart from the three small ones (3 DP additions,
-// 0.008 |x||b|) and adds the two at the end: c_rel = (DP + 8) u 1.1.  With
-// the rounding of |b|^2 itself ((d + 1) u |b|^2), the computed score is within
-//   E = c_abs + c_den (|x| + |b|max) + c_rel (|b|max^2 + 2 |x| |b|max)
-//       + 2 c_tr 1.1 |x| |b|max
-// of |b|^2 - 2 x.b, c_abs and c_den absorbing flushes of subnormal operands,
-// products and sums to zero.  TERMS = 4 has the smaller E (fewer exact
-// rescans) and TERMS = 3 the fewer registers and MFMAs; launches over many
-// queries take TERMS = 4.
+// exact in float32.  Error of the computed score against |b|^2 - 2 x.b
+// (split_score_bound below; every term is a sum of magnitudes):
+//   - dropped split terms, at most c_tr |x| |b| (Cauchy-Schwarz over k):
+//     (xh + xm).rb + rx.(bh + bm) + rx.rb gives 2.01 * 2^-16 and xm.bm adds
+//     at most 1.02 * 2^-16 (TERMS = 3);
+//   - the accumulation, under the assumed model of the matrix cores: every
+//     product is added to the float32 accumulator with one rounding to
+//     nearest, which errs by at most u = 2^-24 times the partial sum.
+//     TERMS = 3 accumulates all 3 DP products in one register (partial sums
+//     at most |b|^2 / 2 + 1.02 |x||b|): (3 DP + 8) u (|b|^2 + 2.04 |x||b|)
+//     after doubling.  TERMS = 4 keeps the leading products xh.bh (DP
+//     additions) apart from the three small ones (3 DP additions, partial
+//     sums at most 0.008 |x||b|) and adds the two at the end:
+//     (DP + 8) u (|b|^2 + 2.04 |x||b|);
+//   - the float32 |b|^2 the accumulator starts from, an fma chain over the
+//     d coordinates: at most (d + 1) u |b|^2;
+//   - c_abs and c_den absorb flushes of subnormal operands, products and
+//     sums to zero.
+// The factors 1.1 cover the second-order terms.  With |b|^2 and |x| taken
+// at their largest values this gives
+//   E = c_abs + c_den (|x| + |b|max) + c_rel (|b|max^2 + 2.04 |x| |b|max)
+//       + c_nrm |b|max^2 + 2 c_tr |x| |b|max,
+// c_rel = (N + 8) u 1.1 (N = 3 DP or DP), c_nrm = (d + 1) u 1.1.
+// TERMS = 4 has the smaller E (fewer exact rescans) and TERMS = 3 the fewer
+// registers and MFMAs; launches over many queries take TERMS = 4.
 //
 // Candidates and certificate: each lane keeps its best score (with its b)
 // and its second-best score per query; the four lane-group bests are
@@ -78,6 +86,32 @@ constexpr int64_t kSplitManyQueries = 16384;
 
 __host__ __device__ inline int split_dpad(int d) {
     return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
+}
+
+// Certificate constants of a launch and the bound E of one query (see the
+// header): |computed score - (|b|^2 - 2 x.b)| <= E for every row b, given
+// the float32 |x|^2 of the query and the float32 maximum of |b|^2 over B.
+// rho bounds the relative error of the canonical float32 accumulator (and
+// of the float32 norms) against the exact squared distance (norm).
+__host__ __device__ inline double split_rho(int d) {
+    return (double)(d + 4) * (1.0 / 16777216.0) * 1.1;
+}
+
+__host__ __device__ inline double split_score_bound(int d, int dp, int terms, double xn2,
+                                                    double b2max) {
+    constexpr double kU = 1.0 / 16777216.0;           // 2^-24
+    constexpr double kTiny = 1.1754943508222875e-38;  // 2^-126
+    const double rho = split_rho(d);
+    const double crel = (double)((terms == 4 ? 1 : 3) * dp + 8) * kU * 1.1;
+    const double cnrm = (double)(d + 1) * kU * 1.1;
+    const double ctr = (terms == 4 ? 2.01 : 3.03) / 65536.0 * 1.1;
+    const double cabs = (double)(20 * dp + 16) * kTiny * 1.1;
+    const double cden = 8.0 * sqrt((double)dp) * kTiny * 1.1;
+    const double b2m = b2max * (1.0 + rho);
+    const double bm = sqrt(b2m);
+    const double xabs = sqrt(xn2 * (1.0 + rho));
+    return cabs + cden * (xabs + bm) + crel * (b2m + 2.04 * xabs * bm) + cnrm * b2m +
+           2.0 * ctr * xabs * bm;
 }
 
 size_t split_table_bytes(int64_t nB, int d) { return (size_t)nB * split_dpad(d) * 4; }
@@ -408,15 +442,8 @@ __device__ __forceinline__ void nnmin_l2_split(
     }
 
     // ---- re-rank and certificate, per block of 16 queries ----
-    constexpr double kU = 1.0 / 16777216.0;                       // 2^-24
-    constexpr double kTiny = 1.1754943508222875e-38;               // 2^-126
-    const double rho = (double)(d + 4) * kU * 1.1;
-    const double crel = (double)((TERMS == 4 ? 1 : 3) * DP + 8) * kU * 1.1;
-    const double ctr = (TERMS == 4 ? 2.01 : 3.03) / 65536.0 * 1.1;
-    const double cabs = (double)(20 * DP + 16) * kTiny * 1.1;
-    const double cden = 8.0 * sqrt((double)DP) * kTiny * 1.1;
-    const double b2m = (double)__uint_as_float(p->b2max_bits) * (1.0 + rho);
-    const double bm = sqrt(b2m);
+    const double rho = split_rho(d);
+    const double b2max = (double)__uint_as_float(p->b2max_bits);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
@@ -436,9 +463,7 @@ __device__ __forceinline__ void nnmin_l2_split(
         vcut = fmaxf(vcut, __shfl_xor(vcut, 32));
         const double bmin = -2.0 * (double)vmax, cut = -2.0 * (double)vcut;
         const double xn2 = (double)qn2[nb];
-        const double xabs = sqrt(xn2 * (1.0 + rho));
-        const double E = cabs + cden * (xabs + bm) + crel * (b2m + 2.0 * xabs * bm) +
-                         2.0 * ctr * xabs * bm;
+        const double E = split_score_bound(d, DP, TERMS, xn2, b2max);
         const double xlo = xn2 * (1.0 - rho);
         const double lb_all = (1.0 - rho) * (bmin - E + xlo);
         const bool need = valid && !(lb_all > (double)gacc);
@@ -525,19 +550,10 @@ __global__ __launch_bounds__(256) void k_split_resolve(
     const int iters = K > 0 ? K : (nchunk + 63) / 64;
     constexpr int kUnroll = K > 0 ? K : 1;
 
-    constexpr double kU = 1.0 / 16777216.0;          // 2^-24
-    constexpr double kTiny = 1.1754943508222875e-38;  // 2^-126
-    const double rho = (double)(d + 4) * kU * 1.1;
-    const double crel = (double)(3 * DP + 8) * kU * 1.1;
-    const double ctr = 3.03 / 65536.0 * 1.1;
-    const double cabs = (double)(20 * DP + 16) * kTiny * 1.1;
-    const double cden = 8.0 * sqrt((double)DP) * kTiny * 1.1;
-    const double b2m = (double)__uint_as_float(p->b2max_bits) * (1.0 + rho);
-    const double bm = sqrt(b2m);
+    const double rho = split_rho(d);
     const double xn = (double)ro(xn2)[q];
-    const double xabs = sqrt(xn * (1.0 + rho));
-    const double E = cabs + cden * (xabs + bm) + crel * (b2m + 2.0 * xabs * bm) +
-                     2.0 * ctr * xabs * bm;
+    const double E =
+        split_score_bound(d, DP, 3, xn, (double)__uint_as_float(p->b2max_bits));
     const double xlo = xn * (1.0 - rho), xhi = xn * (1.0 + 2.0 * rho);
     const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
 
@@ -750,3 +766,9 @@ hipError_t launch_batch_split(const Batch *bt, int d, hipStream_t st) {
 }
 
 }  // namespace chamfer
+
+extern "C" double chamfer_split_score_bound(int32_t d, int32_t terms, float xn2, float b2max) {
+    if (d < 1 || d > 256 || (terms != 3 && terms != 4)) return -1.0;
+    return chamfer::split_score_bound(d, chamfer::split_dpad(d), terms, (double)xn2,
+                                      (double)b2max);
+}

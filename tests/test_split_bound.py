@@ -102,3 +102,181 @@ def test_bound_is_nearly_attained():
     norm = float(np.linalg.norm(x.astype(np.float64)) ** 2)
     ratio = abs(exact - three) / (2.0 ** -16 * norm)
     assert 0.05 < ratio <= 3.03
+
+
+# ------------------------------------------------ the certificate bound E ---
+#
+# The l2 exact pass starts each accumulator at -|b|^2 / 2, with |b|^2 the
+# float32 fma chain over b's coordinates, and adds the BF16 split products;
+# the certificate needs |computed score - (|b|^2 - 2 x.b)| <= E for the E the
+# library computes (chamfer_split_score_bound, the function the kernels call).
+# Below, the accumulation is emulated under the model the bound assumes
+# (every product added with one float32 rounding to nearest, in the order
+# of the kernel's K steps) on inputs built to make each error source as
+# large as it can be, and the error is measured exactly with Fractions.
+
+U = 2.0 ** -24
+
+
+def f32_round(fr):
+    """Round a Fraction to the nearest float32 (ties to even), exactly."""
+    if fr == 0:
+        return np.float32(0.0)
+    sign = -1 if fr < 0 else 1
+    mag = abs(fr)
+    e = math.frexp(float(mag))[1] - 1
+    while Fraction(2) ** e > mag:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= mag:
+        e += 1
+    spacing = Fraction(2) ** (max(e, -126) - 23)
+    q = mag / spacing
+    n = q.numerator // q.denominator
+    r = q - n
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return np.float32(sign * float(n * spacing))
+
+
+def fma_norm(b, d):
+    """float32 fma chain of b_k^2 over k ascending (the row norm)."""
+    acc = np.float32(0.0)
+    for k in range(d):
+        acc = f32_round(Fraction(float(b[k])) ** 2 + Fraction(float(acc)))
+    return acc
+
+
+def dpad(d):
+    return 32 if d <= 32 else 64 if d <= 64 else 128 if d <= 128 else 256
+
+
+def emulate_score(x, b, d, terms):
+    """Score -2 v of the kernel's accumulation of (x, b) under the model."""
+    dp = dpad(d)
+    xp = np.zeros(dp, np.float32)
+    bp = np.zeros(dp, np.float32)
+    xp[:d], bp[:d] = x, b
+    xh, xm = split(xp)
+    bh, bm = split(bp)
+    A = np.float32(-0.5) * fma_norm(b, d)
+    kq = dp // 4
+    order = [g * kq + 8 * s + t for s in range(kq // 8) for g in range(4) for t in range(8)]
+    hi, lo = A, np.float32(0.0)
+    small = [(bh, xm), (bm, xh)] + ([(bm, xm)] if terms == 4 else [])
+    for s in range(kq // 8):
+        ks = order[32 * s:32 * s + 32]
+        for k in ks:
+            hi = np.float32(hi + np.float32(bh[k] * xh[k]))
+        for P, Q in small:
+            for k in ks:
+                if terms == 4:
+                    lo = np.float32(lo + np.float32(P[k] * Q[k]))
+                else:
+                    hi = np.float32(hi + np.float32(P[k] * Q[k]))
+    v = np.float32(hi + lo) if terms == 4 else hi
+    return -2.0 * float(v)
+
+
+def exact_score(x, b):
+    xf = [Fraction(float(t)) for t in x]
+    bf = [Fraction(float(t)) for t in b]
+    return sum(t * t for t in bf) - 2 * sum(p * q for p, q in zip(xf, bf))
+
+
+def query_norm(x):
+    """|x|^2 as the split kernel computes it (4-term fma chains, then a tree);
+    it only enters E through |x|, inflated by rho."""
+    return np.float32(np.sum(x.astype(np.float64) ** 2))
+
+
+def rounded_up_row(d, rng):
+    """b_k = 1 + j_k 2^-23 chosen one coordinate at a time so that every step
+    of the fma chain rounds up by nearly half a float32 spacing: the row norm
+    the accumulator starts from is as large as the chain allows."""
+    j = np.arange(4096, dtype=np.int64)
+    sq = (1 << 46) + (j << 24) + j * j   # b^2 in units of 2^-46
+    acc = 0                              # the chain's value in the same units
+    b = np.zeros(d, np.float32)
+    for k in range(d):
+        V = acc + sq
+        e = int(V.max()).bit_length() - 1
+        sp = 1 << max(e - 23, 0)
+        r = V % sp
+        up = np.where(r * 2 > sp, sp - r, np.where(r * 2 == sp, 0, -r))
+        pick = int(np.argmax(up))
+        b[k] = np.float32(1.0 + float(j[pick]) * 2.0 ** -23)
+        acc = int(V[pick] + up[pick])
+    return b
+
+
+def lost_products_query(b, d):
+    """x_k = the largest BF16 value whose product with bf16(b_k) stays below
+    half a float32 spacing of the accumulator's start: every leading product
+    is lost to rounding, in the same direction as the rounded-up norm."""
+    A = abs(float(np.float32(-0.5) * fma_norm(b, d)))
+    half = 2.0 ** (math.frexp(A)[1] - 1 - 24)
+    bh, _ = split(b)
+    x = np.zeros(d, np.float32)
+    for k in range(d):
+        # BF16 values are float32 values with 16 zero low bits: truncate, then
+        # step down one BF16 spacing while the product reaches half
+        bits = int(np.float32(half / float(bh[k])).view(np.uint32)) & 0xFFFF0000
+        while float(np.uint32(bits).view(np.float32)) * float(bh[k]) >= half:
+            bits -= 0x10000
+        x[k] = np.uint32(bits).view(np.float32)
+    return x
+
+
+def old_bound(d, terms, xn2, b2max):
+    """E without the row-norm rounding term (for the regression check)."""
+    rho = (d + 4) * U * 1.1
+    dp = dpad(d)
+    crel = ((terms == 4 and 1 or 3) * dp + 8) * U * 1.1
+    ctr = (2.01 if terms == 4 else 3.03) / 65536.0 * 1.1
+    b2m = b2max * (1 + rho)
+    bm, xa = math.sqrt(b2m), math.sqrt(xn2 * (1 + rho))
+    return crel * (b2m + 2 * xa * bm) + 2 * ctr * xa * bm
+
+
+@pytest.mark.parametrize("d", [12, 64, 128, 200, 256])
+@pytest.mark.parametrize("terms", [3, 4])
+def test_certificate_bound_worst_cases(d, terms):
+    import paper_2307_03043_amd as ch
+    rng = np.random.default_rng(d * 10 + terms)
+    b_up = rounded_up_row(d, rng)
+    cases = {
+        # query at the origin, the row's norm rounded up at every step
+        "origin": (np.zeros(d, np.float32), b_up),
+        # every leading product lost to rounding, same sign as the norm error
+        "lost": (lost_products_query(b_up, d), b_up),
+        # the query far larger than the row, and the reverse
+        "big_x": ((rng.standard_normal(d) * 1e3).astype(np.float32),
+                  rng.standard_normal(d).astype(np.float32)),
+        "big_b": (rng.standard_normal(d).astype(np.float32) * np.float32(1e-3),
+                  (rng.standard_normal(d) * 1e2).astype(np.float32)),
+        # a common offset: |b|^2 and 2 x.b cancel almost entirely
+        "offset": ((1e4 + rng.standard_normal(d)).astype(np.float32),
+                   (1e4 + rng.standard_normal(d)).astype(np.float32)),
+    }
+    for name, (x, b) in cases.items():
+        err = abs(Fraction(emulate_score(x, b, d, terms)) - exact_score(x, b))
+        b2max = float(fma_norm(b, d))
+        xn2 = float(query_norm(x))
+        E = ch.chamfer_split_score_bound(d, terms, xn2, b2max)
+        assert float(err) <= E, (name, float(err), E)
+        if name == "lost" and terms == 4 and d in (64, 128, 256):
+            # the norm's rounding is a real part of the error: without its
+            # term the bound fails on this row (|b|^2 / 2 just above a power
+            # of two, where a lost product is a full half spacing)
+            assert float(err) > old_bound(d, terms, xn2, b2max), (float(err), E)
+        if name == "lost":
+            # the construction reaches the accumulation model's regime
+            assert float(err) > 0.5 * (dpad(d) if terms == 4 else d) * U * b2max * 0.5
+
+
+def test_certificate_bound_rejects_bad_arguments():
+    import paper_2307_03043_amd as ch
+    assert ch.chamfer_split_score_bound(0, 3, 1.0, 1.0) == -1.0
+    assert ch.chamfer_split_score_bound(257, 3, 1.0, 1.0) == -1.0
+    assert ch.chamfer_split_score_bound(128, 2, 1.0, 1.0) == -1.0
+    assert math.isinf(ch.chamfer_split_score_bound(128, 3, 1.0, float("inf")))
