@@ -58,7 +58,9 @@ enum chamfer_status {
     CHAMFER_EINVAL = -1,      /* bad argument (host check, nothing launched)   */
     CHAMFER_EWORKSPACE = -2,  /* ws NULL or ws_bytes < chamfer_workspace_bytes */
     CHAMFER_EHIP = -3,        /* a HIP launch or runtime call failed           */
-    CHAMFER_ENONFINITE = -4   /* device status: an input coordinate is NaN/Inf */
+    CHAMFER_ENONFINITE = -4,  /* device status: an input coordinate is NaN/Inf */
+    CHAMFER_ETOOLARGE = -5    /* chamfer_estimate_noalloc: the call needs more
+                                 workspace than CHAMFER_STATIC_SCRATCH_BYTES */
 };
 
 enum chamfer_precision {
@@ -261,6 +263,32 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
                      int32_t metric, double eps, int64_t T, uint64_t seed, double *eta_out,
                      chamfer_aux *aux, const chamfer_opts *opts, void *ws, size_t ws_bytes,
                      void *stream);
+
+/*
+ * chamfer_estimate without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The workspace is a static
+ * device array of CHAMFER_STATIC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on each device it runs on until the process ends; its address is
+ * looked up once per device on the first call there.  The call allocates
+ * nothing: arguments, outputs and results are exactly those of
+ * chamfer_estimate with ws = that array.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero (every region the
+ * estimate reads is written earlier in the same call).  All calls on one
+ * device share the one array, so calls that overlap on a device (on
+ * different streams, or from different host threads) race and give wrong
+ * results: serialise them.  opts.reduction must be CHAMFER_REDUCE_NONE.
+ * Errors: as chamfer_estimate, plus CHAMFER_ETOOLARGE when
+ * chamfer_workspace_bytes(n_A, n_B, d, metric, eps, T, opts) exceeds
+ * CHAMFER_STATIC_SCRATCH_BYTES (about 30,000 x 30,000 points at d = 128, or
+ * 65,000 x 65,000 at d = 3, with the default options), checked before any
+ * launch.
+ */
+#define CHAMFER_STATIC_SCRATCH_BYTES (64u << 20)
+int chamfer_estimate_noalloc(const float *A, const float *B, int64_t n_A, int64_t n_B,
+                             int32_t d, int32_t metric, double eps, int64_t T, uint64_t seed,
+                             double *eta_out, chamfer_aux *aux, const chamfer_opts *opts,
+                             void *stream);
 
 /*
  * The bucket keys CrudeNN joins on, for inspection and testing (appendix

@@ -26,7 +26,8 @@ L2 = 2
 FP32, BF16, FP8 = 0, 1, 2
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "workspace missing or too small",
-           -3: "HIP launch or runtime error", -4: "input contains NaN or Inf"}
+           -3: "HIP launch or runtime error", -4: "input contains NaN or Inf",
+           -5: "problem needs more workspace than the static scratch buffer holds"}
 
 
 class ChamferError(RuntimeError):
@@ -76,6 +77,8 @@ _SIGS = {
                                 _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_estimate": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _I64, _U64,
                                         _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "chamfer_estimate_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _I64,
+                                                _U64, _VP, _VP, _VP, _VP]),
     "chamfer_hash_keys": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I32, _I32, _F64, _U64, _VP,
                                          _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "chamfer_nn_min": (ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _I32, _I32, _VP, _VP, _VP,
@@ -328,6 +331,41 @@ def chamfer_estimate(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
                                   _ptr(out["eta"]), None if reduction else ctypes.byref(aux),
                                   ctypes.byref(o),
                                   _ptr(ws), ws.numel(), _stream(dev)), "chamfer_estimate")
+    return out
+
+
+def chamfer_estimate_noalloc(A, B, metric, eps, T=0, seed=0, *, n_scales=0, embed_dim=0,
+                             precision=0, window=0, reps=0, sampling=0):
+    """chamfer_estimate on the library's static scratch array instead of a
+    workspace (no device allocation inside the call; the outputs below are
+    allocated here, by the caller).  Same outputs as chamfer_estimate."""
+    torch = _torch()
+    A, B = _points(A, "A"), _points(B, "B")
+    n_a, d = A.shape
+    n_b = B.shape[0]
+    dev = A.device
+    o = _opts(n_scales, embed_dim, precision, window, reps, sampling)
+    if T == 0 and 0.0 < eps < 1.0:
+        T = chamfer_default_samples(max(n_a, 1), eps)
+    out = {"eta": torch.empty(1, dtype=torch.float64, device=dev), "T": T}
+    out.update(
+        sample_idx=torch.empty(T, dtype=torch.int32, device=dev),
+        sample_min=torch.empty(T, dtype=torch.float32, device=dev),
+        sample_nn=torch.empty(T, dtype=torch.int32, device=dev),
+        D=torch.empty(1, dtype=torch.float64, device=dev),
+        W=torch.empty(1, dtype=torch.int64, device=dev),
+        s=torch.empty(1, dtype=torch.int32, device=dev),
+        status=torch.empty(1, dtype=torch.int32, device=dev),
+        crude_D=torch.empty(n_a, dtype=torch.float32, device=dev),
+        crude_nn=torch.empty(n_a, dtype=torch.int32, device=dev),
+        crude_scale=torch.empty(n_a, dtype=torch.int32, device=dev),
+    )
+    aux = Aux()
+    for f in _AUX_ARRAYS:
+        setattr(aux, f, out[f].data_ptr())
+    _check(lib().chamfer_estimate_noalloc(_ptr(A), _ptr(B), n_a, n_b, d, metric, eps, T, seed,
+                                          _ptr(out["eta"]), ctypes.byref(aux), ctypes.byref(o),
+                                          _stream(dev)), "chamfer_estimate_noalloc")
     return out
 
 

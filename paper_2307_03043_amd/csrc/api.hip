@@ -3,6 +3,7 @@
 // caller's stream; nothing here waits for the device.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -467,6 +468,42 @@ int launch_estimate_batch(const Batch *bt, int d, int metric, int ke, int precis
 
 }  // namespace chamfer
 
+// ------------------------------------------------------ static scratch
+// The workspace of chamfer_estimate_noalloc: one array per device, loaded
+// with the code object and kept until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: it takes the device
+// address from hipGetSymbolAddress, once per device with that device
+// current, and uses only that address.
+
+static __device__ __align__(256) uint8_t scratch[CHAMFER_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on the device of `st`.
+int scratch_for_stream(hipStream_t st, void **out) {
+    int dev = 0, cur = 0;
+    if (hipStreamGetDevice(st, &dev) != hipSuccess || hipGetDevice(&cur) != hipSuccess)
+        return CHAMFER_EHIP;
+    if (dev < 0 || dev >= kMaxScratchDevices) return CHAMFER_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        if (dev != cur && hipSetDevice(dev) != hipSuccess) return CHAMFER_EHIP;
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (dev != cur && hipSetDevice(cur) != hipSuccess) return CHAMFER_EHIP;
+        if (e != hipSuccess || ptr == nullptr) return CHAMFER_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CHAMFER_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t chamfer_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,
@@ -622,6 +659,21 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     return CHAMFER_OK;
 }
 
+int chamfer_estimate_noalloc(const float *A, const float *B, int64_t n_A, int64_t n_B,
+                             int32_t d, int32_t metric, double eps, int64_t T, uint64_t seed,
+                             double *eta_out, chamfer_aux *aux, const chamfer_opts *opts,
+                             void *stream) {
+    if (opts && opts->reduction != CHAMFER_REDUCE_NONE) return CHAMFER_EINVAL;
+    Plan pl;
+    int rc = make_plan(pl, n_A, n_B, d, metric, eps, T, opts, true);
+    if (rc) return rc;
+    if (pl.total > (size_t)CHAMFER_STATIC_SCRATCH_BYTES) return CHAMFER_ETOOLARGE;
+    void *ws = nullptr;
+    if ((rc = scratch_for_stream(static_cast<hipStream_t>(stream), &ws))) return rc;
+    return chamfer_estimate(A, B, n_A, n_B, d, metric, eps, T, seed, eta_out, aux, opts, ws,
+                            (size_t)CHAMFER_STATIC_SCRATCH_BYTES, stream);
+}
+
 int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, int32_t d,
                       int32_t metric, double eps, uint64_t seed, uint64_t *keys_A_out,
                       uint64_t *keys_B_out, int32_t *e_top_out, const chamfer_opts *opts,
@@ -715,6 +767,8 @@ const char *chamfer_strerror(int status) {
         case CHAMFER_EWORKSPACE: return "workspace missing or too small";
         case CHAMFER_EHIP: return "HIP launch or runtime error";
         case CHAMFER_ENONFINITE: return "input contains NaN or Inf";
+        case CHAMFER_ETOOLARGE:
+            return "problem needs more workspace than the static scratch buffer holds";
         default: return "unknown status";
     }
 }

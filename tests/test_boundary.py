@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror():
     lib = ch.lib()
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert lib.chamfer_strerror(code)
     assert lib.chamfer_strerror(0) == b"ok"
 
@@ -237,3 +237,22 @@ def test_server_argument_errors_are_host_side():
     assert lib.chamfer_server_warm(None, 3, 2, 0, 0) == -1
     assert lib.chamfer_server_progress(None) == -1
     assert lib.chamfer_server_destroy(None) == -1
+
+
+def test_noalloc_checks_before_launch():
+    """chamfer_estimate_noalloc refuses bad arguments and sizes beyond its
+    static scratch array on the host, before it touches a device."""
+    lib = ch.lib()
+    n, d = 100_000, 128
+    assert ch.chamfer_workspace_bytes(n, n, d, 2, 0.1) > 64 << 20
+    rc = lib.chamfer_estimate_noalloc(None, None, n, n, d, 2, 0.1, 2000, 1, None, None, None,
+                                      None)
+    assert rc == -5
+    assert b"static scratch" in lib.chamfer_strerror(-5)
+    rc = lib.chamfer_estimate_noalloc(None, None, 10, 10, 0, 2, 0.1, 20, 1, None, None, None,
+                                      None)
+    assert rc == -1
+    o = ch.Opts(reduction=1)
+    rc = lib.chamfer_estimate_noalloc(None, None, 10, 10, 3, 2, 0.1, 20, 1, None, None,
+                                      ctypes.byref(o), None)
+    assert rc == -1
