@@ -24,6 +24,7 @@ REL = 1e-5
 CONFIGS = {
     # name: generator, kwargs, metric, eps, T, L, rows of T checked in float64
     "l2_100k_d128": ("clusters_l2", dict(n=100_000, d=128, k=1000), 2, 0.1, 2000, 20, 2000),
+    "l2_1m_d128": ("clusters_l2", dict(n=1_000_000, d=128, k=1000), 2, 0.1, 2000, 24, 2000),
     "l1_1m_d64": ("mixed_l1", dict(n=1_000_000, d=64, k=5000), 1, 0.1, 2000, 24, 2000),
     "l2_1m_d256": ("precision_l2", dict(n=1_000_000, d=256, k=10_000), 2, 0.1, 2000, 24, 300),
 }
@@ -39,15 +40,27 @@ def ch():
 
 
 _data = {}
+_crude = {}
 
 
 def data(name):
     if name not in _data:
         _data.clear()
+        _crude.clear()
         gen, kw, *_ = CONFIGS[name]
         A, B = getattr(workloads, gen)(seed=42, **kw)
         _data[name] = (A, B, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
     return _data[name]
+
+
+def oracle_crude(orc, name):
+    """The oracle's CrudeNN of the workload with seed 1 (kept for the tests
+    of one workload, which run one after another)."""
+    if name not in _crude:
+        gen, kw, metric, eps, T, L, nrows = CONFIGS[name]
+        A, B, _, _ = data(name)
+        _crude[name] = orc.crude_nn(A, B, metric, eps, 1, n_scales=L)
+    return _crude[name]
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
@@ -57,7 +70,7 @@ def test_fullsize_estimate(ch, orc, name):
     A, B, At, Bt = data(name)
     out = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L)
     torch.cuda.synchronize()
-    crude = orc.crude_nn(A, B, metric, eps, 1, n_scales=L)
+    crude = oracle_crude(orc, name)
     assert np.array_equal(out["crude_scale"].cpu().numpy(), crude["scale"])
     assert np.array_equal(out["crude_nn"].cpu().numpy(), crude["nn"])
     assert np.array_equal(out["crude_D"].cpu().numpy().view(np.uint32), crude["D"].view(np.uint32))
@@ -91,6 +104,54 @@ def test_fullsize_exact_rows(ch, orc, name):
     assert np.array_equal(got_min.view(np.uint32), m32.view(np.uint32))
     np.testing.assert_allclose(got_min, m64, rtol=REL, atol=0)
     assert math.isfinite(float(chv.item()))
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_fullsize_low_precision(ch, orc, precision):
+    """The precision workload (l2, 10^6 x 10^6, d = 256, 10,000 clusters) on
+    BF16 (1) and FP8-E4M3 (2) distance tiles with the top candidates of
+    every (row, chunk of B) re-ranked in float32, against the float64
+    oracle.  Stated bounds: every re-ranked minimum is the canonical float32
+    distance to a real row of B, so it is never below the true minimum
+    (1e-5 relative); at least 99.9% (BF16) / 99% (FP8) of 1000 sampled rows
+    of the exact CH and of the 2000 draws of the estimate find the true
+    nearest row (the canonical float32 arg-min); the sampled rows' mean
+    minimum is within 1e-5 (BF16) / 1e-4 (FP8) of the float64 oracle's;
+    eta is within 1e-5 of the oracle's float64 estimate from the same
+    draws, which are precision-independent and bit-exact."""
+    name = "l2_1m_d256"
+    print(f"[case] fullsize low precision {precision} {name}", flush=True)
+    gen, kw, metric, eps, T, L, _ = CONFIGS[name]
+    A, B, At, Bt = data(name)
+    frac_exact = 0.999 if precision == 1 else 0.99
+    mean_tol = 1e-5 if precision == 1 else 1e-4
+    chv, rmin, rnn = ch.chamfer_exact(At, Bt, metric, precision=precision)
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(4).choice(A.shape[0], size=1000, replace=False))
+    rows = rows.astype(np.int32)
+    m64, _ = orc.nn_f64(A, B, metric, rows=rows)
+    m32, a32 = orc.nn_f32(A, B, metric, rows=rows)
+    got = rmin.cpu().numpy()[rows]
+    assert np.all(got >= m64 * (1 - 1e-5))
+    exact_rows = float(np.mean(got.view(np.uint32) == m32.view(np.uint32)))
+    assert exact_rows >= frac_exact, exact_rows
+    assert float(np.mean(got)) == pytest.approx(float(np.mean(m64)), rel=mean_tol)
+    assert math.isfinite(float(chv.item()))
+    # the estimate: CrudeNN, weights and draws are precision-independent
+    out = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L, precision=precision)
+    torch.cuda.synchronize()
+    crude = oracle_crude(orc, name)
+    s, w, P, W, zero = orc.weights(crude["D"])
+    idx = orc.sample(1, P, W, T)
+    assert np.array_equal(out["sample_idx"].cpu().numpy(), idx)
+    sm = out["sample_min"].cpu().numpy()
+    d64, _ = orc.nn_f64(A, B, metric, rows=idx)
+    assert np.all(sm >= d64 * (1 - 1e-5))
+    assert float(np.mean(np.abs(sm / d64 - 1) <= 1e-5)) >= frac_exact
+    eta = math.fsum(((float(W) / float(w[i])) * m for i, m in zip(idx.tolist(), d64.tolist()))) / T
+    print(f"[precision {precision}] exact rows {exact_rows:.5f}, eta rel err "
+          f"{abs(float(out['eta'].item()) / eta - 1):.2e}", flush=True)
+    assert float(out["eta"].item()) == pytest.approx(eta, rel=1e-5)
 
 
 def test_fullsize_retrieval(ch, orc):

@@ -208,3 +208,54 @@ def test_server_warm(ch):
         assert srv.stats()["graphs"] == 6
     alone = _estimate_alone(ch, dict(A=A, B=B, metric=2, eps=0.2, seed=77))
     assert got[0]["id"] == rid and got[0]["eta"] == float(alone["eta"].item())
+
+
+def test_server_matches_oracle(orc, ch):
+    """Every served result against the CPU oracle (the Chamfer-Estimate
+    figure run on the same request): eta within 1e-5 relative, the
+    fixed-point total W, exponent s and normaliser D exactly.  The requests
+    are the serving mix (d = 3 surface clouds and d = 128 clusters, l1/l2,
+    eps 0.1/0.2) at reduced sizes, plus d = 16 and d = 64 Gaussian pairs and
+    BF16 exact passes, all submitted at once to an arena that holds only a
+    few of them, so they batch and overlap."""
+    import workloads
+    stream = workloads.serving_stream(seed=77, count=28, rate_hz=500.0, n_min=300, n_max=6000)
+    reqs = []
+    for q in stream:
+        A, B = workloads.request_clouds(q)
+        reqs.append(dict(A=A, B=B, metric=q.metric, eps=q.eps, seed=q.seed, precision=0))
+    rng = np.random.default_rng(78)
+    for i in range(12):
+        d = [16, 64][i % 2]
+        n_a, n_b = (int(x) for x in rng.integers(200, 5000, size=2))
+        A = (rng.standard_normal((n_a, d)) * 2).astype(np.float32)
+        B = (rng.standard_normal((n_b, d)) * 2).astype(np.float32)
+        metric = 1 + (i % 3 != 0)
+        prec = 1 if metric == 2 and i % 4 == 1 else 0
+        reqs.append(dict(A=A, B=B, metric=metric, eps=[0.1, 0.2][i % 2], seed=900 + i,
+                         precision=prec))
+    for r in reqs:
+        r["At"] = torch.from_numpy(r["A"]).pin_memory()
+        r["Bt"] = torch.from_numpy(r["B"]).pin_memory()
+    biggest = max(ch.chamfer_workspace_bytes(r["A"].shape[0], r["B"].shape[0], r["A"].shape[1],
+                                             r["metric"], r["eps"], 0, precision=r["precision"])
+                  + 4 * r["A"].shape[1] * (r["A"].shape[0] + r["B"].shape[0]) + 4096
+                  for r in reqs)
+    print(f"[case] serving vs oracle: {len(reqs)} requests", flush=True)
+    got = {}
+    with ch.ChamferServer(4 * biggest, lanes=4) as srv:
+        ids = [srv.submit(r["At"], r["Bt"], r["metric"], r["eps"], 0, r["seed"],
+                          precision=r["precision"]) for r in reqs]
+        while len(got) < len(ids):
+            srv.progress()
+            for res in srv.results():
+                got[res["id"]] = res
+        st = srv.stats()
+    assert st["batches"] < len(reqs)
+    for rid, r in zip(ids, reqs):
+        res = got[rid]
+        assert res["status"] == 0, rid
+        ref = orc.chamfer_estimate(r["A"], r["B"], r["metric"], r["eps"], 0, r["seed"])
+        assert res["W"] == ref["W"] and res["s"] == ref["s"], rid
+        assert res["D"] == ref["D_norm"], rid
+        assert res["eta"] == pytest.approx(ref["eta"], rel=1e-5), (rid, r["A"].shape, r["metric"])
