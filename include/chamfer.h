@@ -444,9 +444,15 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
 /* Host helpers (no device work). */
 int64_t chamfer_default_samples(int64_t n_A, double eps);            /* T default */
 int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps); /* L default */
-/* The scaled Gaussian embedding matrix, Z_jk / (sqrt(2/pi) k_e), [k_e][d], into
- * host memory; the same matrix chamfer_estimate uses for `seed`. */
-int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, float *Z_host);
+/* The l2 -> l1 embedding matrix chamfer_estimate uses for `seed`, into host
+ * memory, [k_e][d] int8: Zq_jk = clamp(rint(32 g_jk), -127, 127), g_jk the
+ * standard Gaussians of Philox purpose 2, counter (j d + k, 0), by
+ * Box-Muller.  The hashed coordinates of a point x are
+ * y_j = (float)((sum_k Zq_jk u_k) 2^(e_top - 24) / (sqrt(2/pi) k_e 32)),
+ * u_k = floor(min((x_k - lo_k) 2^(24 - e_top), 2^24 - 1)), the integer sum
+ * exact: the Gaussian embedding of the appendix theorem on quantised
+ * coordinates. */
+int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, int8_t *Z_host);
 const char *chamfer_strerror(int status);
 /* The bound E of the l2 exact pass's certificate (the exact pass of
  * chamfer_exact, chamfer_nn_min and chamfer_estimate for l2 with

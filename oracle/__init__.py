@@ -40,6 +40,7 @@ _F32 = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _F64 = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _U64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 _I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I8 = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
 _VP = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _INT = ctypes.c_int
@@ -79,7 +80,7 @@ def lib():
     L.or_philox4x64.argtypes = [_U64, _U64, _U64]
     L.or_grid_tables.argtypes = [ctypes.c_uint64, _INT, _INT, _F32, _U64]
     L.or_grid_tables_rep.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _INT, _INT, _F32, _U64]
-    L.or_embedding.argtypes = [ctypes.c_uint64, _INT, _INT, _F32]
+    L.or_embedding.argtypes = [ctypes.c_uint64, _INT, _INT, _I8]
     L.or_default_scales.argtypes = [_I64, _I64, ctypes.c_double]
     L.or_default_scales.restype = _INT
     L.or_default_samples.argtypes = [_I64, ctypes.c_double]
@@ -88,7 +89,7 @@ def lib():
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_INT)]
     L.or_hash_keys.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _INT, _INT,
                                _F32, _U64, _U64]
-    L.or_hashed_coords.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _F32]
+    L.or_hashed_coords.argtypes = [_F32, _I64, _INT, _INT, _F32, _INT, _VP, _INT, _F32]
     L.or_crude_nn.argtypes = [_U64, _I64, _U64, _I64, _INT, _F32, _F32, _INT, _INT,
                               _I32, _I32, _F32]
     L.or_crude_window.argtypes = [_U64, _I64, _U64, _I64, _INT, _INT, _F32, _F32, _INT, _INT,
@@ -104,7 +105,8 @@ def lib():
     L.or_sketch_direction.argtypes = [ctypes.c_uint64, _INT, _INT, _F64]
     L.or_project.argtypes = [_F32, _I64, _INT, _F64, _F64]
     L.or_part_tables.argtypes = [ctypes.c_uint64, _INT, _F32, _U64]
-    L.or_part_keys.argtypes = [_F32, _I64, _INT, _INT, _F32, _VP, _INT, _INT, _F32, _U64, _U64]
+    L.or_part_keys.argtypes = [_F32, _I64, _INT, _INT, _F32, _INT, _VP, _INT, _INT, _F32, _U64,
+                               _U64]
     L.or_pad.argtypes = [_F32, _I64, _INT, _INT, _INT, ctypes.c_uint64, ctypes.c_float, _F32]
     _lib = L
     return L
@@ -150,11 +152,16 @@ def grid_tables(seed: int, L: int, kh: int, rep: int = 0):
 
 
 def embedding(seed: int, d: int, ke: int = DEFAULT_EMBED_DIM) -> np.ndarray:
-    """Scaled Gaussian matrix Z / (beta * ke), beta = sqrt(2/pi), [ke, d]
-    (appendix theorem embedding l2 into l1)."""
-    z = np.zeros((ke, d), np.float32)
+    """Quantised Gaussian matrix Zq = clamp(rint(32 g), -127, 127), int8
+    [ke, d] (appendix theorem embedding l2 into l1; the scale 1 / (beta ke)
+    with beta = sqrt(2/pi), and 1/32, is applied to the integer products)."""
+    z = np.zeros((ke, d), np.int8)
     lib().or_embedding(seed, d, ke, z)
     return z
+
+
+EMBED_SCALE = 32.0
+EMBED_QBITS = 24
 
 
 def default_scales(n_a: int, n_b: int, eps: float) -> int:
@@ -182,17 +189,20 @@ def calibrate(A, B):
     return lo, hi, S.value, e.value
 
 
-def hashed_coords(X, metric, lo, Zs) -> np.ndarray:
+def hashed_coords(X, metric, lo, Zs, e_top) -> np.ndarray:
     """The coordinates the grid hash sees, Y[n, kh]: x - lo for l1 and, for
-    l2, the embedding T(x - lo) of the appendix theorem embedding l2 into l1,
-    accumulated as a float32 fused multiply-add chain in ascending k."""
+    l2, the embedding T(x - lo) of the appendix theorem embedding l2 into
+    l1 in its finite-precision form: coordinates quantised to 24 bits of the
+    span 2^e_top, an exact integer product with the quantised matrix, then
+    scaled to float (see hashed_coords in the C source)."""
     X = _f32(X)
     n, d = X.shape
     kh = d if metric == 1 else Zs.shape[0]
     Y = np.zeros((n, kh), np.float32)
-    Zs = None if Zs is None else _f32(Zs)
+    Zs = None if Zs is None else np.ascontiguousarray(Zs, np.int8)
     zp = None if Zs is None else Zs.ctypes.data
-    lib().or_hashed_coords(X, n, d, metric, _f32(lo), zp, 0 if Zs is None else Zs.shape[0], Y)
+    lib().or_hashed_coords(X, n, d, metric, _f32(lo), e_top, zp,
+                           0 if Zs is None else Zs.shape[0], Y)
     return Y
 
 
@@ -201,6 +211,7 @@ def hash_keys(X, metric, lo, Zs, L, e_top, zfrac, mult) -> np.ndarray:
     X = _f32(X)
     n, d = X.shape
     keys = np.zeros((L, n), np.uint64)
+    Zs = None if Zs is None else np.ascontiguousarray(Zs, np.int8)
     ke = 0 if Zs is None else Zs.shape[0]
     zp = None if Zs is None else Zs.ctypes.data
     lib().or_hash_keys(X, n, d, metric, lo, zp, ke, L, e_top, zfrac, mult, keys)
@@ -485,14 +496,15 @@ def part_tables(seed: int, kh: int):
     return z, m
 
 
-def part_keys(X, metric, lo, Zs, e, zfrac, mult) -> np.ndarray:
+def part_keys(X, metric, lo, e_top, Zs, e, zfrac, mult) -> np.ndarray:
     """Key of every point's cell of side 2^e (see or_part_keys)."""
     X = _f32(X)
     n, d = X.shape
     keys = np.zeros(n, np.uint64)
+    Zs = None if Zs is None else np.ascontiguousarray(Zs, np.int8)
     ke = 0 if Zs is None else Zs.shape[0]
     zp = None if Zs is None else Zs.ctypes.data
-    lib().or_part_keys(X, n, d, metric, lo, zp, ke, e, zfrac, mult, keys)
+    lib().or_part_keys(X, n, d, metric, lo, e_top, zp, ke, e, zfrac, mult, keys)
     return keys
 
 
@@ -520,7 +532,7 @@ def aspect_reduce(A, B, metric, eps, seed, embed_dim=DEFAULT_EMBED_DIM):
     max_t = float(t.max()) if len(t) else 0.0
     out = reduce_bounds(A.shape[0], B.shape[0], eps, max_t, d)
     out.update(g=g, pa=pa, pb=pb, t=t, max_t=max_t, ch1=math.fsum(t.tolist()))
-    lo, _, _, _ = calibrate(A, B)
+    lo, _, _, e_top = calibrate(A, B)
     Zs = embedding(seed, d, embed_dim) if metric == L2 else None
     kh = d if metric == L1 else Zs.shape[0]
     zf, mt = part_tables(seed, kh)
@@ -528,8 +540,8 @@ def aspect_reduce(A, B, metric, eps, seed, embed_dim=DEFAULT_EMBED_DIM):
         out["keys_A"] = np.zeros(A.shape[0], np.uint64)
         out["keys_B"] = np.zeros(B.shape[0], np.uint64)
     else:
-        out["keys_A"] = part_keys(A, metric, lo, Zs, out["e_part"], zf, mt)
-        out["keys_B"] = part_keys(B, metric, lo, Zs, out["e_part"], zf, mt)
+        out["keys_A"] = part_keys(A, metric, lo, e_top, Zs, out["e_part"], zf, mt)
+        out["keys_B"] = part_keys(B, metric, lo, e_top, Zs, out["e_part"], zf, mt)
     return out
 
 

@@ -102,14 +102,24 @@ static void draw(uint64_t seed, uint64_t c0, uint64_t c1, uint32_t purpose, uint
 /* ------------------------------------------------------------------------ */
 /* Hash family at every scale (appendix lemma constructing an LSH at every  */
 /* scale): h(x)_k = ceil((x_k + z_k) / r) with z ~ U[0, r]^k.  Written in   */
-/* cell units: ceil(x_k / r + z'_k) with z'_k = z_k / r ~ U[0, 1).          */
+/* cell units with floor: floor(x_k / r + z'_k), z'_k = z_k / r ~ U[0, 1)   */
+/* (floor and ceil differ by one except on the cell boundaries, a set the   */
+/* shift hits with probability 0, so the two grids are the same family).    */
 /* For scale i and hashed coordinate k the oracle draws                    */
 /*   z'_ik = (word0 >> 40) * 2^-24            (24-bit lattice in [0, 1))     */
-/*   M_ik  = word1 | 1                         (odd 64-bit multiplier)       */
+/*   M_ik  = M1 | M2 << 32, two odd 24-bit key multipliers:                  */
+/*           M1 = (word1 & 0xffffff) | 1, M2 = ((word1 >> 32) & 0xffffff) | 1 */
 /* from the counter (k, i, GRID, rep): rep numbers the independent LSH      */
 /* structures of the repeated variant (0 for the single structure).         */
 /* zfrac and mult are [L][kh].                                               */
 /* ------------------------------------------------------------------------ */
+static uint64_t key_multipliers(uint64_t word1)
+{
+    uint64_t m1 = (word1 & 0xffffffull) | 1ull;
+    uint64_t m2 = ((word1 >> 32) & 0xffffffull) | 1ull;
+    return m1 | (m2 << 32);
+}
+
 void or_grid_tables_rep(uint64_t seed, uint64_t rep, int L, int kh, float *zfrac, uint64_t *mult)
 {
     for (int i = 0; i < L; ++i)
@@ -117,7 +127,7 @@ void or_grid_tables_rep(uint64_t seed, uint64_t rep, int L, int kh, float *zfrac
             uint64_t w[4];
             draw_rep(seed, (uint64_t)k, (uint64_t)i, PURPOSE_GRID, rep, w);
             zfrac[(size_t)i * kh + k] = ldexpf((float)(w[0] >> 40), -24);
-            mult[(size_t)i * kh + k] = w[1] | 1ull;
+            mult[(size_t)i * kh + k] = key_multipliers(w[1]);
         }
 }
 
@@ -128,23 +138,27 @@ void or_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult)
             uint64_t w[4];
             draw(seed, (uint64_t)k, (uint64_t)i, PURPOSE_GRID, w);
             zfrac[(size_t)i * kh + k] = ldexpf((float)(w[0] >> 40), -24);
-            mult[(size_t)i * kh + k] = w[1] | 1ull;
+            mult[(size_t)i * kh + k] = key_multipliers(w[1]);
         }
 }
 
 /* ------------------------------------------------------------------------ */
 /* l2 -> l1 embedding (appendix theorem on embedding l2 into l1):           */
 /* T(x)_j = (1 / (beta k)) sum_i Z_ji x_i, beta = sqrt(2/pi), Z Gaussian.   */
-/* Z_jk from Box-Muller on the counter (j*d + k, 0, EMBED):                 */
+/* Finite-precision form: the Gaussian entries are quantised to integers,  */
+/* Zq_jk = clamp(rint(32 g_jk), -127, 127), with g_jk from Box-Muller on    */
+/* the counter (j*d + k, 0, EMBED):                                          */
 /*   u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1], u2 = (w1 >> 11) 2^-53 in [0, 1)*/
 /*   g  = sqrt(-2 ln u1) cos(2 pi u2)                                        */
-/* and the stored matrix is Zs_jk = (float)(g / (beta k)).  Zs is [ke][d].  */
+/* so that the embedding of quantised coordinates is an exact integer dot   */
+/* product (hashed_coords below).  Zq is [ke][d].                            */
 /* ------------------------------------------------------------------------ */
-void or_embedding(uint64_t seed, int d, int ke, float *Zs)
+#define EMBED_SCALE 32.0 /* Zq ~ 32 g */
+#define EMBED_QBITS 24   /* coordinates quantised to 24 bits of the span */
+
+void or_embedding(uint64_t seed, int d, int ke, int8_t *Zq)
 {
     const double two_pi = 2.0 * 3.14159265358979323846;
-    const double beta = sqrt(2.0 / 3.14159265358979323846);
-    const double scale = 1.0 / (beta * (double)ke);
     for (int j = 0; j < ke; ++j)
         for (int k = 0; k < d; ++k) {
             uint64_t w[4];
@@ -152,7 +166,10 @@ void or_embedding(uint64_t seed, int d, int ke, float *Zs)
             double u1 = ldexp((double)((w[0] >> 11) + 1), -53);
             double u2 = ldexp((double)(w[1] >> 11), -53);
             double g = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
-            Zs[(size_t)j * d + k] = (float)(g * scale);
+            double q = rint(EMBED_SCALE * g);
+            if (q > 127.0) q = 127.0;
+            if (q < -127.0) q = -127.0;
+            Zq[(size_t)j * d + k] = (int8_t)q;
         }
 }
 
@@ -211,54 +228,80 @@ void or_calibrate(const float *A, int64_t nA, const float *B, int64_t nB, int d,
     *e_top_out = (S > 0.0) ? ceil_log2_double(S) : 0;
 }
 
-/* Coordinates that get hashed: l1 hashes y = x - lo (d of them); l2 hashes
- * the embedded y_j = sum_k Zs_jk (x_k - lo_k) accumulated with fmaf in
- * ascending k (ke of them). */
-static void hashed_coords(const float *x, int d, int metric, const float *lo,
-                          const float *Zs, int ke, float *y)
+/* Coordinates that get hashed.  l1: y = x - lo (d of them, float32).
+ * l2 (ke of them): the coordinates quantised to 24 bits of the span,
+ *   u_k = floor(min((x_k - lo_k) 2^(24 - e_top), 2^24 - 1))
+ * (x_k - lo_k a float32 subtraction, the scaling exact), their exact
+ * integer embedding Y_j = sum_k Zq_jk u_k, and
+ *   y_j = (float)((Y_j 2^(e_top - 24)) / (beta ke 32))
+ * with the division a multiplication by 1 / (beta ke 32) in double
+ * (Y_j 2^(e_top - 24) is exact in double, |Y_j| < 2^53), so y approximates
+ * the embedding T(x - lo) of the theorem. */
+static void hashed_coords(const float *x, int d, int metric, const float *lo, int e_top,
+                          const int8_t *Zq, int ke, float *y)
 {
     if (metric == OR_L1) {
         for (int k = 0; k < d; ++k) y[k] = x[k] - lo[k];
-    } else {
-        for (int j = 0; j < ke; ++j) {
-            float acc = 0.0f;
-            for (int k = 0; k < d; ++k) acc = fmaf(Zs[(size_t)j * d + k], x[k] - lo[k], acc);
-            y[j] = acc;
+        return;
+    }
+    const double inv = 1.0 / (sqrt(2.0 / 3.14159265358979323846) * (double)ke * EMBED_SCALE);
+    for (int j = 0; j < ke; ++j) {
+        int64_t Y = 0;
+        for (int k = 0; k < d; ++k) {
+            float v = ldexpf(x[k] - lo[k], EMBED_QBITS - e_top);
+            int64_t u = (int64_t)floorf(fminf(v, 16777215.0f));
+            Y += (int64_t)Zq[(size_t)j * d + k] * u;
         }
+        y[j] = (float)(ldexp((double)Y, e_top - EMBED_QBITS) * inv);
     }
 }
 
 /* The hashed coordinates of every point of X, Y[n][kh] (kh = d for l1,
  * ke for l2); exported so the embedding step can be checked on its own. */
-void or_hashed_coords(const float *X, int64_t n, int d, int metric, const float *lo,
-                      const float *Zs, int ke, float *Y)
+void or_hashed_coords(const float *X, int64_t n, int d, int metric, const float *lo, int e_top,
+                      const int8_t *Zq, int ke, float *Y)
 {
     int kh = metric == OR_L1 ? d : ke;
     for (int64_t p = 0; p < n; ++p)
-        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, Y + (size_t)p * kh);
+        hashed_coords(X + (size_t)p * d, d, metric, lo, e_top, Zq, ke, Y + (size_t)p * kh);
+}
+
+/* Grid cell of a shifted coordinate q = y / r + z' (float): floor(q) as a
+ * 32-bit integer, saturated at the int32 range (q is clamped first, NaN
+ * going to the upper bound), so every float maps to one cell. */
+static int32_t cell_of(float q)
+{
+    q = fminf(q, 2147483520.0f); /* the largest float below 2^31 */
+    q = fmaxf(q, -2147483648.0f);
+    return (int32_t)floorf(q);
 }
 
 /* Bucket key of point y at scale i (side 2^e):
- *   cell_k = ceilf(ldexpf(y_k, -e) + z'_ik) + 0.0f   (the +0 folds -0 into +0)
- *   key    = (sum_k bits(cell_k) * M_ik mod 2^64) >> 1
- * Two points share a bucket iff their keys are equal; distinct cells share a
- * key only by a 64-bit hash collision.  Keys fit in 63 bits. */
+ *   cell_k = cell_of(fmaf(y_k, 2^-e, z'_ik))   (y_k 2^-e is exact, so one
+ *                                              rounding, of the sum)
+ *   K1 = sum_k (cell_k mod 2^24) M1_ik mod 2^32,
+ *   K2 = sum_k (cell_k mod 2^24) M2_ik mod 2^32,
+ *   key = (K1 2^32 + K2) >> 1
+ * (cell_k mod 2^24: the low 24 bits of its two's complement).  Equal cells
+ * give equal keys.  Distinct cells whose indices differ in one coordinate
+ * by less than 2^24 never share a key (the multipliers are odd); with
+ * several differing coordinates they share one with probability about
+ * 2^-48 over the multipliers.  Keys fit in 63 bits. */
 static uint64_t bucket_key(const float *y, int kh, int e, const float *zf, const uint64_t *M)
 {
-    uint64_t acc = 0;
+    const float p = ldexpf(1.0f, -e);
+    uint32_t k1 = 0, k2 = 0;
     for (int k = 0; k < kh; ++k) {
-        float q = ldexpf(y[k], -e) + zf[k];
-        float c = ceilf(q) + 0.0f;
-        uint32_t bits;
-        memcpy(&bits, &c, 4);
-        acc += (uint64_t)bits * M[k];
+        uint32_t c = (uint32_t)cell_of(fmaf(y[k], p, zf[k])) & 0xffffffu;
+        k1 += (uint32_t)((uint64_t)c * (M[k] & 0xffffffffull));
+        k2 += (uint32_t)((uint64_t)c * (M[k] >> 32));
     }
-    return acc >> 1;
+    return (((uint64_t)k1 << 32) | (uint64_t)k2) >> 1;
 }
 
 /* keys[i * n + p] for every point p of X and scale i < L. */
 void or_hash_keys(const float *X, int64_t n, int d, int metric, const float *lo,
-                  const float *Zs, int ke, int L, int e_top, const float *zfrac,
+                  const int8_t *Zs, int ke, int L, int e_top, const float *zfrac,
                   const uint64_t *mult, uint64_t *keys)
 {
     int kh = metric == OR_L1 ? d : ke;
@@ -268,7 +311,7 @@ void or_hash_keys(const float *X, int64_t n, int d, int metric, const float *lo,
         float *y = (float *)malloc(sizeof(float) * (size_t)kh);
 #pragma omp for schedule(static)
         for (int64_t p = 0; p < n; ++p) {
-            hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
+            hashed_coords(X + (size_t)p * d, d, metric, lo, e_top, Zs, ke, y);
             for (int i = 0; i < L; ++i) {
                 int e = e_top - (L - 1 - i);
                 keys[(size_t)i * n + p] =
@@ -588,15 +631,15 @@ void or_part_tables(uint64_t seed, int kh, float *zfrac, uint64_t *mult)
  *   cell_k = ceil(ldexp((double) y_k, -e) + (double) z'_k),
  * clamped to [-2^62, 2^62] (0 when y_k is NaN), and
  *   key = (sum_k (uint64) (int64) cell_k * M_k mod 2^64) >> 1. */
-void or_part_keys(const float *X, int64_t n, int d, int metric, const float *lo,
-                  const float *Zs, int ke, int e, const float *zfrac, const uint64_t *mult,
+void or_part_keys(const float *X, int64_t n, int d, int metric, const float *lo, int e_top,
+                  const int8_t *Zs, int ke, int e, const float *zfrac, const uint64_t *mult,
                   uint64_t *keys)
 {
     int kh = metric == OR_L1 ? d : ke;
     float *y = (float *)malloc(sizeof(float) * (size_t)kh);
     const double lim = ldexp(1.0, 62);
     for (int64_t p = 0; p < n; ++p) {
-        hashed_coords(X + (size_t)p * d, d, metric, lo, Zs, ke, y);
+        hashed_coords(X + (size_t)p * d, d, metric, lo, e_top, Zs, ke, y);
         uint64_t acc = 0;
         for (int k = 0; k < kh; ++k) {
             double c = ceil(ldexp((double)y[k], -e) + (double)zfrac[k]);

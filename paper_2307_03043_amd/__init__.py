@@ -207,7 +207,7 @@ def chamfer_split_score_bound(d: int, terms: int, xn2: float, b2max: float) -> f
 
 
 def chamfer_embedding_matrix(seed: int, d: int, embed_dim: int = 32) -> np.ndarray:
-    z = np.zeros((embed_dim, d), np.float32)
+    z = np.zeros((embed_dim, d), np.int8)
     _check(lib().chamfer_embedding_matrix(seed, d, embed_dim, z.ctypes.data),
            "chamfer_embedding_matrix")
     return z

@@ -48,13 +48,15 @@ void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
     }
 }
 
-// Z_jk / (beta k_e), beta = sqrt(2/pi), Z_jk by Box-Muller from the words of
-// counter (j*d + k, 0, EMBED, 0): u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],
-// u2 = (w1 >> 11) 2^-53, g = sqrt(-2 ln u1) cos(2 pi u2).  Row-major [ke][d].
-void embedding_host(uint64_t seed, int d, int ke, float *Z) {
+// Zq_jk = clamp(rint(32 g_jk), -127, 127), g_jk by Box-Muller from the words
+// of counter (j*d + k, 0, EMBED, 0): u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],
+// u2 = (w1 >> 11) 2^-53, g = sqrt(-2 ln u1) cos(2 pi u2).  Row-major [ke][d]:
+// the quantised Gaussian matrix of the l2 -> l1 embedding (the scale
+// 1 / (beta ke 32), beta = sqrt(2/pi), is applied after the exact integer
+// product).
+void embedding_host(uint64_t seed, int d, int ke, int8_t *Z) {
     const double pi = 3.14159265358979323846;
     const double two_pi = 2.0 * pi;
-    const double scale = 1.0 / (std::sqrt(2.0 / pi) * (double)ke);
     for (int j = 0; j < ke; ++j)
         for (int k = 0; k < d; ++k) {
             uint64_t c[4] = {(uint64_t)j * (uint64_t)d + (uint64_t)k, 0, kPurposeEmbed, 0};
@@ -62,17 +64,41 @@ void embedding_host(uint64_t seed, int d, int ke, float *Z) {
             const double u1 = std::ldexp((double)((c[0] >> 11) + 1), -53);
             const double u2 = std::ldexp((double)(c[1] >> 11), -53);
             const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2);
-            Z[(size_t)j * d + k] = (float)(g * scale);
+            const double q = std::fmin(std::fmax(std::rint(32.0 * g), -127.0), 127.0);
+            Z[(size_t)j * d + k] = (int8_t)q;
         }
 }
 
-// The same, transposed to [d][ke] (the layout the hash kernels read).
-void embedding_transposed(uint64_t seed, int d, int ke, float *zt) {
-    thread_local std::vector<float> z;
+size_t embed_bytes(int d, int ke) {
+    const size_t nt = (size_t)(ke + 15) / 16, nks = (size_t)(d + 63) / 64;
+    return nt * nks * 1024 + nt * 16 * sizeof(int32_t);
+}
+
+// The matrix in the operand layout of the hash kernels' int8 matrix-core
+// embedding: for each 16-column tile t of j and 64-coordinate step s, lane
+// l (= 16 g + i) holds the 16 bytes Zq[16 t + i][64 s + 16 g + e], e < 16
+// (zero outside [ke] x [d]); then R_j = sum_k Zq_jk as int32 for the 16 nt
+// columns.  embed_bytes(d, ke) bytes.
+void embedding_packed(uint64_t seed, int d, int ke, int8_t *out) {
+    thread_local std::vector<int8_t> z;
     z.resize((size_t)ke * d);
     embedding_host(seed, d, ke, z.data());
-    for (int j = 0; j < ke; ++j)
-        for (int k = 0; k < d; ++k) zt[(size_t)k * ke + j] = z[(size_t)j * d + k];
+    const int nt = (ke + 15) / 16, nks = (d + 63) / 64;
+    for (int t = 0; t < nt; ++t)
+        for (int s = 0; s < nks; ++s)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 16; ++e) {
+                    const int j = 16 * t + (l & 15), k = 64 * s + 16 * (l >> 4) + e;
+                    out[((size_t)(t * nks + s) * 64 + l) * 16 + e] =
+                        (j < ke && k < d) ? z[(size_t)j * d + k] : (int8_t)0;
+                }
+    int32_t *r = reinterpret_cast<int32_t *>(out + (size_t)nt * nks * 1024);
+    for (int j = 0; j < 16 * nt; ++j) {
+        int32_t acc = 0;
+        if (j < ke)
+            for (int k = 0; k < d; ++k) acc += z[(size_t)j * d + k];
+        r[j] = acc;
+    }
 }
 
 }  // namespace chamfer
@@ -149,8 +175,10 @@ int make_plan(Plan &pl, int64_t nA, int64_t nB, int32_t d, int32_t metric, doubl
     pl.off_lohi = take(lohi_bytes(d));
     pl.off_zfrac = take(h * pl.L * pl.kh * sizeof(float));
     pl.off_mult = take(h * pl.L * pl.kh * sizeof(uint64_t));
-    pl.off_embed = take(metric == CHAMFER_L2 ? h * d * ke * sizeof(float) : 0);
+    pl.off_embed = take(metric == CHAMFER_L2 ? h * embed_bytes(d, ke) : 0);
     pl.off_tables = take(h * table_bytes(pl.L, lc, pl.window));
+    pl.part = hashing && pl.window == 1 && part_build_ok(lc);
+    pl.off_part = take(pl.part ? part_work_bytes(pl.L, nB, lc) : 0);
     pl.off_D = take(e_ * nA * sizeof(float));
     pl.off_nn = take(h * nA * sizeof(int32_t));
     pl.off_scale = take(h * nA * sizeof(int32_t));
@@ -214,10 +242,10 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         CH_TRY(hipStreamIsCapturing(st, &cs));
         if (cs != hipStreamCaptureStatusNone) return CHAMFER_EINVAL;
-        thread_local std::vector<float> zt;
-        zt.resize((size_t)pl.ke * pl.d);
-        embedding_transposed(seed, pl.d, pl.ke, zt.data());
-        CH_TRY(hipMemcpyAsync(at<float>(ws, pl.off_embed), zt.data(), zt.size() * sizeof(float),
+        thread_local std::vector<int8_t> zt;
+        zt.resize(embed_bytes(pl.d, pl.ke));
+        embedding_packed(seed, pl.d, pl.ke, zt.data());
+        CH_TRY(hipMemcpyAsync(at<int8_t>(ws, pl.off_embed), zt.data(), zt.size(),
                               hipMemcpyHostToDevice, st));
     }
     CH_TRY(launch_minmax(A, pl.nA, pl.d, lohi, p, st));
@@ -249,16 +277,28 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
     DevParams *p = at<DevParams>(ws, pl.off_params);
     Bucket *tables = at<Bucket>(ws, pl.off_tables);
     const uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
-    const float *emb = at<float>(ws, pl.off_embed);
+    const int8_t *emb = at<int8_t>(ws, pl.off_embed);
     float *zf = at<float>(ws, pl.off_zfrac);
     uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
+    PartWork pw{};
+    if (pl.part) part_work_bytes(pl.L, pl.nB, pl.log2cap, &pw, at<char>(ws, pl.off_part));
     for (int r = 0; r < pl.reps; ++r) {
         if (r > 0) CH_TRY(launch_grid_tables(seed, pl.L, pl.kh, zf, mt, r, st));
-        CH_TRY(launch_tables_empty(tables, pl.L, pl.log2cap, W, st));
-        if (r == 0) CH_TRY(mark(ev, 1, st));
-        CH_TRY(launch_hash(W == 1 ? 0 : 3, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi,
-                           emb, zf, mt, tables, pl.log2cap, nullptr, nullptr, nullptr, nullptr,
-                           r == 0 ? nb2 : nullptr, p, W, 0, st));
+        if (pl.part) {
+            // B's keys, then the tables built region by region in LDS (every
+            // slot written, so no emptying pass)
+            if (r == 0) CH_TRY(mark(ev, 1, st));
+            CH_TRY(launch_hash(5, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf,
+                               mt, nullptr, pl.log2cap, pw.keys, nullptr, nullptr, nullptr,
+                               r == 0 ? nb2 : nullptr, p, 1, 0, st));
+            CH_TRY(launch_part_build(pw, pl.nB, pl.L, pl.log2cap, tables, st));
+        } else {
+            CH_TRY(launch_tables_empty(tables, pl.L, pl.log2cap, W, st));
+            if (r == 0) CH_TRY(mark(ev, 1, st));
+            CH_TRY(launch_hash(W == 1 ? 0 : 3, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke,
+                               lohi, emb, zf, mt, tables, pl.log2cap, nullptr, nullptr, nullptr,
+                               nullptr, r == 0 ? nb2 : nullptr, p, W, 0, st));
+        }
         if (r == 0) CH_TRY(mark(ev, 2, st));
         const int flags = (r > 0 ? kProbeMerge : 0) | (r == pl.reps - 1 ? kProbeLast : 0);
         CH_TRY(launch_hash(W == 1 ? 1 : 4, A, pl.nA, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi,
@@ -326,8 +366,8 @@ namespace chamfer {
 
 int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t d,
                 int32_t metric, double eps, int64_t T, uint64_t seed, const chamfer_opts *opts,
-                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const float *embed_dev,
-                float *embed_host, Job *job) {
+                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const int8_t *embed_dev,
+                int8_t *embed_host, Job *job) {
     Plan pl;
     int rc = make_plan(pl, nA, nB, d, metric, eps, T, opts, true);
     if (rc) return rc;
@@ -410,7 +450,7 @@ int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t 
     J.nn_nchunk = g.nchunk;
     J.nb_nn = (int32_t)g.blocks;
     // embed_host NULL: the caller has staged this job's embedding already
-    if (metric == CHAMFER_L2 && embed_host) embedding_transposed(seed, d, pl.ke, embed_host);
+    if (metric == CHAMFER_L2 && embed_host) embedding_packed(seed, d, pl.ke, embed_host);
     return CHAMFER_OK;
 }
 
@@ -688,7 +728,7 @@ int chamfer_hash_keys(const float *A, const float *B, int64_t n_A, int64_t n_B, 
     if ((rc = hash_prologue(pl, A, B, seed, ws, st))) return rc;
     DevParams *p = at<DevParams>(ws, pl.off_params);
     const uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
-    const float *emb = at<float>(ws, pl.off_embed);
+    const int8_t *emb = at<int8_t>(ws, pl.off_embed);
     const float *zf = at<float>(ws, pl.off_zfrac);
     const uint64_t *mt = at<uint64_t>(ws, pl.off_mult);
     if (keys_A_out)
@@ -754,7 +794,7 @@ int32_t chamfer_default_scales(int64_t n_A, int64_t n_B, double eps) {
     return default_scales(n_A, n_B, eps);
 }
 
-int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, float *Z_host) {
+int chamfer_embedding_matrix(uint64_t seed, int32_t d, int32_t embed_dim, int8_t *Z_host) {
     if (d < 1 || !valid_ke(embed_dim) || Z_host == nullptr) return CHAMFER_EINVAL;
     embedding_host(seed, d, embed_dim, Z_host);
     return CHAMFER_OK;

@@ -50,8 +50,13 @@ hipError_t launch_init_params(DevParams *p, uint32_t *lohi, int d, hipStream_t s
     return hipGetLastError();
 }
 
-// Shifts z'_ik (cell units, 24-bit lattice in [0,1)) and odd multipliers
-// M_ik from Philox4x64-10, counter (k, i, GRID, 0), key (seed, 0).
+// Key multipliers from the second Philox word: two odd 24-bit values.
+__host__ __device__ inline uint64_t key_multipliers(uint64_t w1) {
+    return ((w1 & 0xffffffull) | 1ull) | ((((w1 >> 32) & 0xffffffull) | 1ull) << 32);
+}
+
+// Shifts z'_ik (cell units, 24-bit lattice in [0,1)) and key multipliers
+// M_ik from Philox4x64-10, counter (k, i, GRID, rep), key (seed, 0).
 __device__ __forceinline__ void grid_tables(uint64_t seed, int L, int kh, float *zfrac,
                                             uint64_t *mult, int rep, Blk b) {
     const int t = (int)(b.id * blockDim.x + threadIdx.x);
@@ -60,7 +65,7 @@ __device__ __forceinline__ void grid_tables(uint64_t seed, int L, int kh, float 
     uint64_t c[4] = {(uint64_t)k, (uint64_t)i, (uint64_t)kPurposeGrid, (uint64_t)rep};
     philox4x64_10(c, seed, 0);
     zfrac[t] = ldexpf((float)(uint32_t)(c[0] >> 40), -24);
-    mult[t] = c[1] | 1ull;
+    mult[t] = key_multipliers(c[1]);
 }
 
 __global__ void k_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64_t *mult,
@@ -288,6 +293,8 @@ hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t s
     return hipGetLastError();
 }
 
+// Empty W = 1 tables: `count` buckets (key EMPTY, value INT_MAX), then the
+// count fingerprint bytes that follow them (0 = empty slot).
 __device__ __forceinline__ void table_fill(Bucket *t, size_t count, Blk b) {
     const size_t stride = (size_t)b.n * blockDim.x;
     for (size_t i = (size_t)b.id * blockDim.x + threadIdx.x; i < count; i += stride) {
@@ -297,6 +304,9 @@ __device__ __forceinline__ void table_fill(Bucket *t, size_t count, Blk b) {
         b.pad = 0;
         t[i] = b;
     }
+    uint4 *fp = reinterpret_cast<uint4 *>(t + count);
+    for (size_t i = (size_t)b.id * blockDim.x + threadIdx.x; i < count / 16; i += stride)
+        fp[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __global__ void k_table_fill(Bucket *t, size_t count) { table_fill(t, count, grid_blk()); }
@@ -342,68 +352,88 @@ hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st) {
 // ------------------------------------------------------------------ keys
 
 // Key of hashed coordinates y (stride 1) at the scale of side 2^e:
-// cell_k = ceil(y_k 2^-e + z'_k) + 0 (the +0 turns -0 into +0, so equal
-// cells have equal bits), key = (sum_k bits(cell_k) M_k mod 2^64) >> 1.
-// The sum is mod 2^64, so it is split over four independent accumulators
-// (the same bits in any grouping) to shorten the dependent add chain.
-template <class PZ, class PM>
+// cell_k = floor(fma(y_k, 2^-e, z'_k)) as an int32 (y_k 2^-e is exact, so one
+// rounding, of the sum), K1 = sum_k (cell_k mod 2^24) M1_k mod 2^32, K2 the
+// same with M2_k, key = (K1 2^32 + K2) >> 1; M_k = M1_k | M2_k << 32 (odd
+// 24-bit multipliers).  Four VALU operations per coordinate: one fma, the
+// floor conversion and two 24-bit multiply-adds.  CLAMP: saturate the
+// shifted coordinate at the int32 range first (NaN to the upper bound);
+// needed only when a cell index can leave that range: more than 30 scales,
+// or sides below 2^-126 (2^-e not finite).  Sums are mod 2^32 and split
+// over two accumulator pairs to shorten the dependent chains.
+template <bool CLAMP>
+__device__ __forceinline__ uint32_t cell24(float q) {
+    if (CLAMP) q = fmaxf(fminf(q, 2147483520.0f), -2147483648.0f);
+    return (uint32_t)(int32_t)floorf(q);
+}
+
+template <bool CLAMP, class PZ, class PM>
 __device__ __forceinline__ unsigned long long bucket_key(const float *y, int kh, int e, PZ zf,
                                                          PM M) {
-    unsigned long long acc[4] = {0, 0, 0, 0};
+    const float p = ldexpf(1.0f, -e);
+    uint32_t a1 = 0, a2 = 0, b1 = 0, b2 = 0;
     int k = 0;
-    for (; k + 4 <= kh; k += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float q = ldexpf(y[k + u], -e) + zf[k + u];
-            const float c = ceilf(q) + 0.0f;
-            acc[u] += (unsigned long long)__float_as_uint(c) * M[k + u];
-        }
+    for (; k + 2 <= kh; k += 2) {
+        const uint32_t c0 = cell24<CLAMP>(fmaf(y[k], p, zf[k]));
+        const uint32_t c1 = cell24<CLAMP>(fmaf(y[k + 1], p, zf[k + 1]));
+        const unsigned long long m0 = M[k], m1 = M[k + 1];
+        a1 += __umul24(c0, (uint32_t)m0);
+        a2 += __umul24(c0, (uint32_t)(m0 >> 32));
+        b1 += __umul24(c1, (uint32_t)m1);
+        b2 += __umul24(c1, (uint32_t)(m1 >> 32));
     }
-    for (; k < kh; ++k) {
-        const float q = ldexpf(y[k], -e) + zf[k];
-        const float c = ceilf(q) + 0.0f;
-        acc[0] += (unsigned long long)__float_as_uint(c) * M[k];
+    if (k < kh) {
+        const uint32_t c0 = cell24<CLAMP>(fmaf(y[k], p, zf[k]));
+        const unsigned long long m0 = M[k];
+        a1 += __umul24(c0, (uint32_t)m0);
+        a2 += __umul24(c0, (uint32_t)(m0 >> 32));
     }
-    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) >> 1;
+    return (((unsigned long long)(a1 + b1) << 32) | (unsigned long long)(a2 + b2)) >> 1;
 }
 
 // Same, with y_k = x_k - lo_k read from HBM (l1 with d too large for LDS).
-template <class PX, class PL, class PZ, class PM>
+template <bool CLAMP, class PX, class PL, class PZ, class PM>
 __device__ __forceinline__ unsigned long long bucket_key_global(PX x, PL lohi, int kh, int e,
                                                                 PZ zf, PM M) {
-    unsigned long long acc[4] = {0, 0, 0, 0};
-    int k = 0;
-    for (; k + 4 <= kh; k += 4) {
-        float y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = x[k + u] - ordered_to_float(lohi[k + u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float q = ldexpf(y[u], -e) + zf[k + u];
-            const float c = ceilf(q) + 0.0f;
-            acc[u] += (unsigned long long)__float_as_uint(c) * M[k + u];
-        }
-    }
-    for (; k < kh; ++k) {
+    const float p = ldexpf(1.0f, -e);
+    uint32_t a1 = 0, a2 = 0;
+    for (int k = 0; k < kh; ++k) {
         const float y = x[k] - ordered_to_float(lohi[k]);
-        const float q = ldexpf(y, -e) + zf[k];
-        const float c = ceilf(q) + 0.0f;
-        acc[0] += (unsigned long long)__float_as_uint(c) * M[k];
+        const uint32_t c = cell24<CLAMP>(fmaf(y, p, zf[k]));
+        const unsigned long long m = M[k];
+        a1 += __umul24(c, (uint32_t)m);
+        a2 += __umul24(c, (uint32_t)(m >> 32));
     }
-    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) >> 1;
+    return (((unsigned long long)a1 << 32) | (unsigned long long)a2) >> 1;
 }
 
-// Home slot: the top bits of the 63-bit key (the best-mixed bits of a
-// multiply-accumulate hash).
+// Home slot: the top bits of the key times an odd 64-bit constant (the
+// golden-ratio multiplier), which carries the well-mixed low bits of the two
+// 32-bit sums into the top (the top bits of a sum of small cells times
+// 24-bit multipliers are not uniform by themselves).  The fingerprint of a
+// key is the next 8 bits of the same product, 0 mapped to 1 (0 marks an
+// empty slot in the fingerprint bytes that follow a W = 1 table).
 __device__ __forceinline__ uint64_t home_slot(unsigned long long key, int log2cap) {
-    return (uint64_t)(key >> (63 - log2cap));
+    return (uint64_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+}
+
+__device__ __forceinline__ uint32_t key_fp(unsigned long long key, int log2cap) {
+    const uint32_t f = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (56 - log2cap)) & 0xffu;
+    return f ? f : 1u;
+}
+
+// Fingerprint bytes of scale i of W = 1 tables of 2^log2cap buckets per scale.
+__device__ __forceinline__ uint8_t *table_fps(Bucket *tables, int L, int log2cap, int i) {
+    return reinterpret_cast<uint8_t *>(tables + ((size_t)L << log2cap)) + ((size_t)i << log2cap);
 }
 
 // Insert (key -> b) keeping the lowest b per key.  Linear probing; a slot's
-// key changes only from EMPTY, by CAS, so each key owns exactly one slot.
-// The slot is read first, so a key already present costs a load (and an
-// atomicMin only when b is lower than the stored value).
-__device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, int b) {
+// key changes only from EMPTY, by CAS, so each key owns exactly one slot,
+// and the lane that claims it writes the key's fingerprint byte.  The slot
+// is read first, so a key already present costs a load (and an atomicMin
+// only when b is lower than the stored value).
+__device__ void table_insert(Bucket *tab, uint8_t *fps, int log2cap, unsigned long long key,
+                             int b) {
     const uint64_t mask = (1ull << log2cap) - 1;
     uint64_t slot = home_slot(key, log2cap);
     for (;;) {
@@ -413,6 +443,7 @@ __device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, i
         if (cur == kEmptyKey) {
             const unsigned long long prev = atomicCAS(&e->key, kEmptyKey, key);
             if (prev == kEmptyKey || prev == key) {
+                if (prev == kEmptyKey) fps[slot] = (uint8_t)key_fp(key, log2cap);
                 atomicMin(&e->val, b);
                 return;
             }
@@ -427,17 +458,31 @@ __device__ void table_insert(Bucket *tab, int log2cap, unsigned long long key, i
     }
 }
 
-// Lowest b stored under key, or -1.  Runs in a later kernel than every insert.
-__device__ __forceinline__ int table_probe(const CH_RO Bucket *tab, int log2cap,
-                                           unsigned long long key) {
+// Lowest b stored under key, or -1.  Runs in a later kernel than every
+// insert.  The probe walks the fingerprint bytes, 16 per load, and reads a
+// bucket only where the fingerprint matches: a missing key (most probes
+// below a point's first colliding scale) touches only the fingerprints,
+// 1/16 of the table's bytes.
+__device__ __forceinline__ int table_probe(const CH_RO Bucket *tab, const CH_RO uint8_t *fps,
+                                           int log2cap, unsigned long long key) {
     const uint64_t mask = (1ull << log2cap) - 1;
+    const uint32_t f = key_fp(key, log2cap);
     uint64_t slot = home_slot(key, log2cap);
     for (;;) {
-        const uint4 w = ld(reinterpret_cast<const CH_RO uint4 *>(tab + slot));  // {key, val, pad}
-        const unsigned long long k = (unsigned long long)w.x | ((unsigned long long)w.y << 32);
-        if (k == key) return (int)w.z;
-        if (k == kEmptyKey) return -1;
-        slot = (slot + 1) & mask;
+        const uint64_t base = slot & ~15ull;
+        const uint4 w = ld(reinterpret_cast<const CH_RO uint4 *>(fps + base));
+        for (int q = (int)(slot - base); q < 16; ++q) {
+            const uint32_t word = q < 4 ? w.x : q < 8 ? w.y : q < 12 ? w.z : w.w;
+            const uint32_t byte = (word >> (8 * (q & 3))) & 0xffu;
+            if (byte == 0) return -1;
+            if (byte == f) {
+                const uint4 bk = ld(reinterpret_cast<const CH_RO uint4 *>(tab + base + q));
+                const unsigned long long k =
+                    (unsigned long long)bk.x | ((unsigned long long)bk.y << 32);
+                if (k == key) return (int)bk.z;
+            }
+        }
+        slot = (base + 16) & mask;
     }
 }
 
@@ -493,7 +538,7 @@ __device__ __forceinline__ int64_t wide_find(const CH_RO unsigned long long *key
 template <int METRIC>
 __device__ __forceinline__ float dist32(const float *__restrict__ a, const float *__restrict__ b,
                                         int d) {
-    const float acc = canon_acc<METRIC>(a, b, d);
+    const float acc = canon_acc<METRIC, 4>(a, b, d);
     return METRIC == CHAMFER_L1 ? acc : sqrtf(acc);
 }
 
@@ -509,8 +554,33 @@ constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2), 
 template <int BATCH, class F>
 __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t p0, int np, int d,
                                            int k0, int kc, float *dst, int ldr, F f) {
-    const int total = np * kc;
     const auto *Xr = ro(X);
+    if (kc == 64 && (d & 3) == 0 && (k0 & 3) == 0 &&
+        (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+        // 64 coordinates per row as 16 float4 loads (row r, quad c of
+        // element e: r = e / 16, c = e % 16), four per thread in one batch
+        const auto *X4 = reinterpret_cast<const CH_RO float4 *>(Xr);
+        float4 v[kTile * 16 / kThreads];
+#pragma unroll
+        for (int i = 0; i < kTile * 16 / kThreads; ++i) {
+            const int e = i * kThreads + (int)threadIdx.x, r = e >> 4, c = e & 15;
+            v[i] = r < np ? ld(X4 + (((p0 + r) * d + k0) >> 2) + c)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < kTile * 16 / kThreads; ++i) {
+            const int e = i * kThreads + (int)threadIdx.x, r = e >> 4, c = e & 15;
+            if (r < np) {
+                float *o = dst + r * ldr + 4 * c;
+                o[0] = f(v[i].x, 4 * c);
+                o[1] = f(v[i].y, 4 * c + 1);
+                o[2] = f(v[i].z, 4 * c + 2);
+                o[3] = f(v[i].w, 4 * c + 3);
+            }
+        }
+        return;
+    }
+    const int total = np * kc;
     for (int base = 0; base < total; base += BATCH * kThreads) {
         float v[BATCH];
 #pragma unroll
@@ -536,6 +606,10 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t 
 // MODE 0: insert the tile's points (B) into the L tables.
 // MODE 1: probe (A): first scale with a hit, candidate, D_a; max D_a.
 // MODE 2: write keys[L][n].
+// MODE 5: write keys[L][n] of B for the partitioned table build: a lane
+//         whose key a lower lane of its wavefront also holds writes the
+//         empty key instead (it cannot be the lowest index of its bucket),
+//         and the l2 row norms are computed as in MODE 0.
 // MODE 3: insert into window tables (W smallest b per bucket).
 // MODE 4: probe window tables: the first W distinct b over the scales, finest
 //         first (wavefront 0 walks the scales of its lane's point; the
@@ -552,12 +626,12 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t 
 template <int METRIC, int MODE, int KE, bool YG, int EC = kEmbedChunk>
 __device__ __forceinline__ void hash_tile(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
-    const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
+    const uint32_t *__restrict__ lohi, const int8_t *__restrict__ embed,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
     int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags, Blk blk) {
     extern __shared__ float smem[];
-    __shared__ float los[EC];
+    __shared__ float los[EC > kEmbedChunk ? EC : kEmbedChunk];
     __shared__ int hit_scale[kTile];
     __shared__ int hit_cand[kWaves][kTile];
     __shared__ int wave_scale[kWaves][kTile];
@@ -590,41 +664,92 @@ __device__ __forceinline__ void hash_tile(
                            [&](float v, int k) { return v - ordered_to_float(lo[k]); });
         }
     } else {
-        // y_j = sum_k Zs_jk (x_k - lo_k), fma chain in ascending k; wavefront
-        // w computes the coordinates j in [w KE/4, (w+1) KE/4) of point lane.
-        // The raw rows are staged (x - lo is formed on read, the same float
-        // subtraction); for B, wavefront 0 also accumulates |x|^2 per row for
-        // the l2 nearest-neighbour pass.
-        constexpr int JW = KE / kWaves;
-        float *xs = smem + kTile * khp;  // [kTile][EC + 1]
-        float y[JW > 0 ? JW : 1];
+        // The quantised embedding: u_k = floor(min((x_k - lo_k) 2^(24 - e_top),
+        // 2^24 - 1)), Y_j = sum_k Zq_jk u_k exactly, on the int8 matrix cores:
+        // wavefront w takes points 16 w + i of the tile (A rows: the three
+        // bytes of u offset by -128, 16 coordinates per lane), B is Zq^T from
+        // the packed table (16-column tiles of j, 64-coordinate steps), one
+        // int32 accumulator per byte; then Y_j = sum_a 2^(8a) (acc_a + 128 R_j)
+        // with R_j = sum_k Zq_jk, and y_j = (float)((Y_j 2^(e_top - 24)) inv),
+        // inv = 1 / (beta KE 32).  The raw rows are staged 64 coordinates at a
+        // time; for B, wavefront 0 also accumulates |x|^2 per row (fma chain,
+        // coordinates ascending) for the l2 nearest-neighbour pass.
+        constexpr int NT = (KE + 15) / 16;
+        constexpr int ECM = kEmbedChunk;  // one 64-coordinate MFMA step per staged chunk
+        const int nks = (d + ECM - 1) / ECM;
+        const int i16 = lane & 15, g4 = lane >> 4;
+        float *xs = smem + kTile * khp;  // [kTile][ECM + 1]
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        v4i acc[3][NT];
 #pragma unroll
-        for (int j = 0; j < JW; ++j) y[j] = 0.0f;
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[a][t] = v4i{0, 0, 0, 0};
+        const auto *zpk = reinterpret_cast<const CH_RO uint4 *>(ro(embed));
         float n2 = 0.0f;
-        const bool want_n2 = (MODE == 0 || MODE == 3) && nb2_out != nullptr && wave == 0;
-        for (int k0 = 0; k0 < d; k0 += EC) {
-            const int kc = min(EC, d - k0);
+        const bool want_n2 =
+            (MODE == 0 || MODE == 3 || MODE == 5) && nb2_out != nullptr && wave == 0;
+        for (int ks = 0; ks < nks; ++ks) {
+            const int k0 = ks * ECM;
+            const int kc = min(ECM, d - k0);
             __syncthreads();
-            stage_rows<16>(X, p0, np, d, k0, kc, xs, EC + 1,
-                           [](float v, int) { return v; });
+            stage_rows<16>(X, p0, np, d, k0, kc, xs, ECM + 1, [](float v, int) { return v; });
             if (tid < kc) los[tid] = ordered_to_float(ro(lohi)[k0 + tid]);
             __syncthreads();
-            if (active) {
+            if (want_n2 && active)
                 for (int k = 0; k < kc; ++k) {
-                    const float xraw = xs[lane * (EC + 1) + k];
-                    const float xv = xraw - los[k];
-                    const auto *zc = ro(embed_t) + (size_t)(k0 + k) * KE + wave * JW;
+                    const float xraw = xs[lane * (ECM + 1) + k];
+                    n2 = fmaf(xraw, xraw, n2);
+                }
+            // A: 16 coordinates k0 + 16 g4 + e of point 16 wave + i16, as the
+            // three bytes of u, each offset by -128 (xor 0x80); four
+            // coordinates at a time give one dword of each byte's operand
+            v4i ab[3];
+            const float *xr = xs + (16 * wave + i16) * (ECM + 1) + 16 * g4;
 #pragma unroll
-                    for (int j = 0; j < JW; ++j) y[j] = fmaf(zc[j], xv, y[j]);
-                    if (want_n2) n2 = fmaf(xraw, xraw, n2);
+            for (int q = 0; q < 4; ++q) {
+                uint32_t u[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * g4 + 4 * q + e;
+                    const float v = ldexpf(xr[4 * q + e] - los[k < kc ? k : 0], 24 - e_top);
+                    u[e] = k < kc ? (uint32_t)(int32_t)floorf(fminf(v, 16777215.0f)) : 0u;
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t sel = (uint32_t)a | ((uint32_t)(4 + a) << 8);
+                    const uint32_t lo2 = __builtin_amdgcn_perm(u[1], u[0], sel);
+                    const uint32_t hi2 = __builtin_amdgcn_perm(u[3], u[2], sel);
+                    ab[a][q] = (int)(__builtin_amdgcn_perm(hi2, lo2, 0x05040100u) ^ 0x80808080u);
                 }
             }
-        }
-        if (active) {
 #pragma unroll
-            for (int j = 0; j < JW; ++j) ys[lane * khp + wave * JW + j] = y[j];
-            if (want_n2) nb2_out[pt] = n2;
+            for (int t = 0; t < NT; ++t) {
+                const uint4 bz = ld(zpk + ((size_t)(t * nks + ks) * 64 + lane));
+                const v4i bv = v4i{(int)bz.x, (int)bz.y, (int)bz.z, (int)bz.w};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    acc[a][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ab[a], bv, acc[a][t], 0, 0, 0);
+            }
         }
+        // lane (g4, i16) holds points 16 wave + 4 g4 + r of column j = 16 t + i16
+        const auto *rsum = reinterpret_cast<const CH_RO int32_t *>(ro(embed) + (size_t)NT * nks * 1024);
+        const double inv = 1.0 / (sqrt(2.0 / 3.14159265358979323846) * (double)KE * 32.0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = 16 * t + i16;
+            const int32_t r128 = 128 * rsum[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t Y = (int64_t)(acc[0][t][r] + r128) +
+                                  ((int64_t)(acc[1][t][r] + r128) << 8) +
+                                  ((int64_t)(acc[2][t][r] + r128) << 16);
+                if (j < KE)
+                    ys[(16 * wave + 4 * g4 + r) * khp + j] =
+                        (float)(ldexp((double)Y, e_top - 24) * inv);
+            }
+        }
+        if (want_n2 && active) nb2_out[pt] = n2;
         if (want_n2) {
             uint32_t m = __float_as_uint(n2);
             for (int off = 32; off > 0; off >>= 1)
@@ -637,12 +762,17 @@ __device__ __forceinline__ void hash_tile(
 
     const float *yrow = ys + lane * khp;
     const float *xrow = X + pt * d;
+    // cell indices can leave the int32 range only with more than 30 scales
+    // or sides below 2^-126
+    const bool clamp = L > 30 || e_top - (L - 1) <= -127;
     auto key_at = [&](int i) -> unsigned long long {
         const int e = e_top - (L - 1 - i);
+        const auto zi = ro(zfrac) + (size_t)i * kh;
+        const auto mi = ro(mult) + (size_t)i * kh;
         if (METRIC == CHAMFER_L1 && YG)
-            return bucket_key_global(ro(xrow), ro(lohi), kh, e, ro(zfrac) + (size_t)i * kh,
-                                     ro(mult) + (size_t)i * kh);
-        return bucket_key(yrow, kh, e, ro(zfrac) + (size_t)i * kh, ro(mult) + (size_t)i * kh);
+            return clamp ? bucket_key_global<true>(ro(xrow), ro(lohi), kh, e, zi, mi)
+                         : bucket_key_global<false>(ro(xrow), ro(lohi), kh, e, zi, mi);
+        return clamp ? bucket_key<true>(yrow, kh, e, zi, mi) : bucket_key<false>(yrow, kh, e, zi, mi);
     };
 
     if (MODE == 0) {
@@ -665,7 +795,26 @@ __device__ __forceinline__ void hash_tile(
                 mine |= lane == leader;
             }
             mine |= ((rest >> lane) & 1ull) != 0;
-            if (mine) table_insert(tables + ((size_t)i << log2cap), log2cap, key, (int)pt);
+            if (mine)
+                table_insert(tables + ((size_t)i << log2cap), table_fps(tables, L, log2cap, i),
+                             log2cap, key, (int)pt);
+        }
+        return;
+    }
+    if (MODE == 5) {
+        constexpr int kLeaders = 4;
+        for (int i = wave; i < L; i += kWaves) {
+            const unsigned long long key = active ? key_at(i) : kEmptyKey;
+            unsigned long long rest = __ballot(active);
+            bool mine = false;
+            for (int it = 0; it < kLeaders && rest != 0; ++it) {
+                const int leader = __ffsll((long long)rest) - 1;
+                const unsigned long long lk = __shfl(key, leader);
+                rest &= ~__ballot(active && key == lk);
+                mine |= lane == leader;
+            }
+            mine |= ((rest >> lane) & 1ull) != 0;
+            if (active) keys_out[(size_t)i * n + pt] = mine ? key : kEmptyKey;
         }
         return;
     }
@@ -771,8 +920,9 @@ __device__ __forceinline__ void hash_tile(
             if (i > __hip_atomic_load(&hit_scale[lane], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WORKGROUP))
                 break;  // a finer scale already collided
-            const int v = table_probe(ro((const Bucket *)tables) + ((size_t)i << log2cap), log2cap,
-                                      key_at(i));
+            const int v = table_probe(ro((const Bucket *)tables) + ((size_t)i << log2cap),
+                                      ro((const uint8_t *)table_fps(tables, L, log2cap, i)),
+                                      log2cap, key_at(i));
             if (v >= 0) {
                 found = i;
                 cand = v;
@@ -803,11 +953,11 @@ __device__ __forceinline__ void hash_tile(
 template <int METRIC, int MODE, int KE, bool YG, int EC, int WAVES>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_hash(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
-    const uint32_t *__restrict__ lohi, const float *__restrict__ embed_t,
+    const uint32_t *__restrict__ lohi, const int8_t *__restrict__ embed,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
     int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags) {
-    hash_tile<METRIC, MODE, KE, YG, EC>(X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables,
+    hash_tile<METRIC, MODE, KE, YG, EC>(X, n, Bpts, d, L, lohi, embed, zfrac, mult, tables,
                                         log2cap, keys_out, D_out, nn_out, scale_out, nb2_out, p,
                                         nB, W, flags, grid_blk());
 }
@@ -821,44 +971,31 @@ static size_t hash_lds(int d) {
     return (size_t)kTile * ((kh | 1) + EC + 1) * sizeof(float);
 }
 
-// Tables up to this size stay in the last-level cache between the insert and
-// the probe.
-constexpr size_t kHotTableBytes = (size_t)128 << 20;
-
 template <int METRIC, int KE, bool YG>
 static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float *Bpts,
                                 int64_t nB, int d, int L, const uint32_t *lohi,
-                                const float *embed_t, const float *zfrac, const uint64_t *mult,
+                                const int8_t *embed, const float *zfrac, const uint64_t *mult,
                                 Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                                 int32_t *nn_out, int32_t *scale_out, float *nb2_out,
                                 DevParams *p, int W, int flags, hipStream_t st) {
     const unsigned blocks = (unsigned)hash_blocks(n);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
-#define CH_KARGS X, n, Bpts, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, ko, D_out, nn_out, \
+#define CH_KARGS X, n, Bpts, d, L, lohi, embed, zfrac, mult, tables, log2cap, ko, D_out, nn_out, \
                  scale_out, nb2_out, p, nB, W, flags
-    // l2 insert, and l2 probe of cache-resident tables: a 32-coordinate
-    // embedding stage holds fewer registers and LDS, so 7 workgroups fit on a
-    // CU (one resident round for 10^5 points: insert 155 -> 133 us, probe
-    // 109 -> 83 us).  A probe of larger tables is bound by their HBM lines
-    // and does better with the default (10^6 points: 1.32 vs 1.46 ms).
-    constexpr int ECS = METRIC == CHAMFER_L2 ? 32 : kEmbedChunk;
-    constexpr int WS = METRIC == CHAMFER_L2 ? 7 : 4;
-    const bool hot = table_bytes(L, log2cap, W) <= kHotTableBytes;
-    const size_t lds = hash_lds<METRIC, KE, YG>(d), lds_s = hash_lds<METRIC, KE, YG, ECS>(d);
+    // Four wavefronts per SIMD for every mode: measured against six and
+    // eight (l2, 10^5 points: probe 90, 117 and 141 us; keys and insert
+    // within noise or slower).
+    const size_t lds = hash_lds<METRIC, KE, YG>(d);
     switch (mode) {
-        case 0: k_hash<METRIC, 0, KE, YG, ECS, WS><<<blocks, kThreads, lds_s, st>>>(CH_KARGS); break;
-        case 1:
-            if (hot)
-                k_hash<METRIC, 1, KE, YG, ECS, WS><<<blocks, kThreads, lds_s, st>>>(CH_KARGS);
-            else
-                k_hash<METRIC, 1, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS);
-            break;
+        case 0: k_hash<METRIC, 0, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
+        case 1: k_hash<METRIC, 1, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
         case 2: k_hash<METRIC, 2, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
         case 3: k_hash<METRIC, 3, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
         case 4:  // retrieved b per lane after the tile
             k_hash<METRIC, 4, KE, YG, kEmbedChunk, 4>
                 <<<blocks, kThreads, lds + (size_t)kTile * W * sizeof(int), st>>>(CH_KARGS);
             break;
+        case 5: k_hash<METRIC, 5, KE, YG, kEmbedChunk, 4><<<blocks, kThreads, lds, st>>>(CH_KARGS); break;
         default: return hipErrorInvalidValue;
     }
 #undef CH_KARGS
@@ -867,7 +1004,8 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
 
 size_t table_bytes(int L, int log2cap, int W) {
     const size_t buckets = (size_t)L << log2cap;
-    return W <= 1 ? buckets * sizeof(Bucket) : buckets * (sizeof(uint64_t) + (size_t)W * 4);
+    // W = 1: buckets, then a fingerprint byte per bucket
+    return W <= 1 ? buckets * (sizeof(Bucket) + 1) : buckets * (sizeof(uint64_t) + (size_t)W * 4);
 }
 
 hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStream_t st) {
@@ -885,13 +1023,13 @@ hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStr
 
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
-                       const float *embed_t, const float *zfrac, const uint64_t *mult,
+                       const int8_t *embed, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
                        int W, int flags, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (W < 1 || W > kMaxWindow) return hipErrorInvalidValue;
-#define CH_ARGS mode, X, n, Bpts, nB, d, L, lohi, embed_t, zfrac, mult, tables, log2cap, keys_out, \
+#define CH_ARGS mode, X, n, Bpts, nB, d, L, lohi, embed, zfrac, mult, tables, log2cap, keys_out, \
                 D_out, nn_out, scale_out, nb2_out, p, W, flags, st
     if (metric == CHAMFER_L1) {
         // the window probe also keeps W ints per lane in LDS
@@ -907,6 +1045,339 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
         default: return hipErrorInvalidValue;
     }
 #undef CH_ARGS
+}
+
+// ------------------------------------------------------ partitioned build
+// The W = 1 tables of the direct path, built without global atomics.  A
+// table of 2^c slots is cut into regions of S = 2^min(c, 12) slots, and a
+// key's region is the top bits of its home slot.  From B's keys (hash mode
+// 5, a wavefront's duplicate keys dropped): per scale, each block of
+// kPartBlock keys counts its keys per region (k_part_hist), one workgroup
+// per scale turns the counts into offsets (k_part_scan), the blocks write
+// their (key, b) pairs grouped by region (k_part_scatter, runs of a region
+// contiguous), and one workgroup per (scale, region) inserts the region's
+// pairs into a table in LDS -- linear probing from the home slot, lowest b
+// per key, LDS atomics only -- and writes all S slots out
+// (k_region_build).  The LDS build never wraps: a pair whose probe reaches
+// the region's end is kept aside and inserted afterwards with the global
+// insert (k_spill_insert), which continues into the next region like any
+// linear probe; the probe then finds every key as after the global insert.
+// A region holds at most S keys against about S / 2 expected (tables are
+// at most half full), so on hashed keys the spill is empty in practice.
+
+constexpr int kRegionBits = 11;
+constexpr int kPartBlock = 4096;   // keys per histogram / scatter workgroup
+constexpr int kMaxRegions = 1024;  // regions per scale the scan and scatter hold in LDS
+
+__host__ __device__ inline int region_bits(int log2cap) {
+    return log2cap < kRegionBits ? log2cap : kRegionBits;
+}
+
+__host__ __device__ inline int64_t part_regions(int log2cap) {
+    return (int64_t)1 << (log2cap - region_bits(log2cap));
+}
+int64_t part_blocks(int64_t nB) { return (nB + kPartBlock - 1) / kPartBlock; }
+bool part_build_ok(int log2cap) { return part_regions(log2cap) <= kMaxRegions; }
+
+size_t part_work_bytes(int L, int64_t nB, int log2cap, PartWork *w, char *base) {
+    const int64_t R = part_regions(log2cap), nblk = part_blocks(nB);
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t b_keys = al((size_t)L * nB * sizeof(uint64_t));
+    const size_t b_offs = al((size_t)L * nblk * R * sizeof(uint32_t));
+    const size_t b_bins = al((size_t)L * R * 3 * sizeof(uint32_t));
+    const size_t b_ent = al((size_t)L * nB * sizeof(uint4));
+    if (w) {
+        w->keys = reinterpret_cast<uint64_t *>(base);
+        w->offs = reinterpret_cast<uint32_t *>(base + b_keys);
+        w->bins = reinterpret_cast<uint32_t *>(base + b_keys + b_offs);
+        w->entries = reinterpret_cast<uint4 *>(base + b_keys + b_offs + b_bins);
+        w->spilled = reinterpret_cast<uint32_t *>(base + b_keys + b_offs + b_bins + b_ent);
+    }
+    return b_keys + b_offs + b_bins + b_ent + 256;
+}
+
+__device__ __forceinline__ uint32_t key_region(unsigned long long key, int log2cap) {
+    return (uint32_t)(home_slot(key, log2cap) >> region_bits(log2cap));
+}
+
+// In-place exclusive prefix sum of v[0..R) (R <= 1024) by a workgroup of
+// 256 threads; returns the total.  Each thread sums up to four consecutive
+// values, the 256 partial sums are scanned in LDS, then written back.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, int R, uint32_t *tmp) {
+    const int t = threadIdx.x;
+    const int per = (R + 255) / 256;
+    uint32_t loc[4] = {0, 0, 0, 0};
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < per && t * per + q < R) {
+            loc[q] = v[t * per + q];
+            sum += loc[q];
+        }
+    tmp[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t x = t >= off ? tmp[t - off] : 0u;
+        __syncthreads();
+        tmp[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = tmp[t] - sum;  // exclusive prefix of this thread's group
+    const uint32_t total = tmp[255];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < per && t * per + q < R) {
+            v[t * per + q] = run;
+            run += loc[q];
+        }
+    __syncthreads();
+    return total;
+}
+
+// Counts per (scale i, block j, region): offs[(i nblk + j) R + g].
+__global__ __launch_bounds__(256) void k_part_hist(const uint64_t *__restrict__ keys, int64_t nB,
+                                                   int log2cap, int64_t nblk, uint32_t *offs) {
+    extern __shared__ uint32_t cnt[];
+    const int R = (int)part_regions(log2cap);
+    const int64_t i = blockIdx.x / nblk, j = blockIdx.x - i * nblk;
+    for (int g = threadIdx.x; g < R; g += 256) cnt[g] = 0;
+    __syncthreads();
+    const CH_RO uint64_t *kr = ro(keys) + i * nB;
+#pragma unroll 4
+    for (int t = 0; t < kPartBlock / 256; ++t) {
+        const int64_t e = j * kPartBlock + t * 256 + threadIdx.x;
+        if (e < nB) {
+            const unsigned long long key = kr[e];
+            if (key != kEmptyKey) atomicAdd(&cnt[key_region(key, log2cap)], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *o = offs + (size_t)(i * nblk + j) * R;
+    for (int g = threadIdx.x; g < R; g += 256) o[g] = cnt[g];
+}
+
+// Per scale: offs becomes the exclusive prefix over blocks of each region's
+// counts; bins[(i R + g) 3 + {0, 1, 2}] = the region's first entry (in the
+// scale's [nB] span of entries), its count, and 0 (spill count); the spill
+// flag is cleared.
+__global__ __launch_bounds__(256) void k_part_scan(int64_t nB, int log2cap, int64_t nblk,
+                                                   uint32_t *offs, uint32_t *bins,
+                                                   uint32_t *spilled) {
+    extern __shared__ uint32_t tot[];  // [R], then [256] scan scratch
+    const int R = (int)part_regions(log2cap);
+    const int64_t i = blockIdx.x;
+    if (i == 0 && threadIdx.x == 0) *spilled = 0;  // read after the region builds
+    for (int g = threadIdx.x; g < R; g += 256) {
+        uint32_t run = 0;
+        uint32_t *o = offs + (size_t)i * nblk * R + g;
+        int64_t j = 0;
+        for (; j + 4 <= nblk; j += 4) {
+            const uint32_t c0 = o[(j + 0) * R], c1 = o[(j + 1) * R];
+            const uint32_t c2 = o[(j + 2) * R], c3 = o[(j + 3) * R];
+            o[(j + 0) * R] = run;
+            o[(j + 1) * R] = run + c0;
+            o[(j + 2) * R] = run + c0 + c1;
+            o[(j + 3) * R] = run + c0 + c1 + c2;
+            run += c0 + c1 + c2 + c3;
+        }
+        for (; j < nblk; ++j) {
+            const uint32_t c = o[j * R];
+            o[j * R] = run;
+            run += c;
+        }
+        tot[g] = run;
+        bins[((size_t)i * R + g) * 3 + 1] = run;
+        bins[((size_t)i * R + g) * 3 + 2] = 0;
+    }
+    __syncthreads();
+    block_exclusive_scan(tot, R, tot + R);
+    for (int g = threadIdx.x; g < R; g += 256) bins[((size_t)i * R + g) * 3 + 0] = tot[g];
+}
+
+// The block's (key, b) pairs grouped by region: counted in LDS, placed in
+// LDS in region order, then written so that consecutive threads write
+// consecutive entries of a region's run.
+__global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict__ keys,
+                                                      int64_t nB, int log2cap, int64_t nblk,
+                                                      const uint32_t *__restrict__ offs,
+                                                      const uint32_t *__restrict__ bins,
+                                                      uint4 *entries) {
+    extern __shared__ uint32_t sm[];
+    const int R = (int)part_regions(log2cap);
+    uint32_t *cnt = sm;               // [R] counts, then the block's region starts
+    uint32_t *fill = sm + R;          // [R + 256] scan scratch, then positions per region
+    auto *sk = reinterpret_cast<unsigned long long *>(sm + 2 * R + 256);  // [kPartBlock]
+    int32_t *sb = reinterpret_cast<int32_t *>(sk + kPartBlock);                      // [kPartBlock]
+    __shared__ uint32_t total;
+    const int64_t i = blockIdx.x / nblk, j = blockIdx.x - i * nblk;
+    for (int g = threadIdx.x; g < R; g += 256) cnt[g] = 0;
+    __syncthreads();
+    constexpr int kPer = kPartBlock / 256;
+    unsigned long long k[kPer];
+    const CH_RO uint64_t *kr = ro(keys) + i * nB;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int64_t e = j * kPartBlock + t * 256 + threadIdx.x;
+        k[t] = e < nB ? kr[e] : kEmptyKey;
+        if (k[t] != kEmptyKey) atomicAdd(&cnt[key_region(k[t], log2cap)], 1u);
+    }
+    __syncthreads();
+    const uint32_t tsum = block_exclusive_scan(cnt, R, fill);  // fill: scan scratch
+    for (int g = threadIdx.x; g < R; g += 256) fill[g] = cnt[g];
+    if (threadIdx.x == 0) total = tsum;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        if (k[t] == kEmptyKey) continue;
+        const uint32_t pos = atomicAdd(&fill[key_region(k[t], log2cap)], 1u);
+        sk[pos] = k[t];
+        sb[pos] = (int32_t)(j * kPartBlock + t * 256 + threadIdx.x);
+    }
+    __syncthreads();
+    const uint32_t n = total;
+    const uint32_t *o = offs + (size_t)(i * nblk + j) * R;
+    const uint32_t *bn = bins + (size_t)i * R * 3;
+    for (uint32_t pos = threadIdx.x; pos < n; pos += 256) {
+        const unsigned long long key = sk[pos];
+        const uint32_t g = key_region(key, log2cap);
+        const size_t dst = (size_t)i * nB + bn[g * 3] + o[g] + (pos - cnt[g]);
+        entries[dst] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)sb[pos], 0u);
+    }
+}
+
+// One workgroup per (scale, region): the region's pairs into an LDS table of
+// S slots (lowest b per key), then all S slots written to the table.  Pairs
+// whose probe reaches the region's end are compacted to the front of the
+// region's run of entries, counted in bins[.. + 2] and flagged in *spilled.
+// Up to kRegionPrefetch pairs per
+// thread are read before any is inserted (one round of loads).
+constexpr int kRegionPrefetch = 8;
+
+__global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB, int L,
+                                                      int log2cap, Bucket *tables, uint32_t *bins,
+                                                      uint32_t *spilled) {
+    extern __shared__ unsigned long long tk[];  // [S] keys, then [S] values
+    const int qb = region_bits(log2cap);
+    const int S = 1 << qb;
+    int32_t *tv = reinterpret_cast<int32_t *>(tk + S);
+    __shared__ uint32_t nspill;
+    const int64_t R = part_regions(log2cap);
+    const int64_t i = blockIdx.x / R, g = blockIdx.x - i * R;
+    const uint32_t start = bins[(i * R + g) * 3], count = bins[(i * R + g) * 3 + 1];
+    for (int s = threadIdx.x; s < S; s += 256) {
+        tk[s] = kEmptyKey;
+        tv[s] = INT_MAX;
+    }
+    if (threadIdx.x == 0) nspill = 0;
+    uint4 *run = entries + (size_t)i * nB + start;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = 0; base < count; base += 256 * kRegionPrefetch) {
+        uint4 e[kRegionPrefetch];
+#pragma unroll
+        for (int q = 0; q < kRegionPrefetch; ++q) {
+            const uint32_t at = base + q * 256 + threadIdx.x;
+            e[q] = at < count ? run[at] : make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
+        }
+        __syncthreads();  // the table is initialised; every pair read before spills overwrite
+#pragma unroll
+        for (int q = 0; q < kRegionPrefetch; ++q) {
+            const unsigned long long key = (unsigned long long)e[q].x |
+                                           ((unsigned long long)e[q].y << 32);
+            const bool valid = key != kEmptyKey;
+            int b = (int)e[q].z;
+            // the lowest lane's key: its lanes fold their b into it (a key
+            // repeated across wavefronts at coarse scales goes in once per
+            // wavefront); the others insert on their own
+            const unsigned long long lk = __shfl(key, __ffsll((long long)__ballot(valid)) - 1);
+            const bool same = valid && key == lk;
+            int mb = same ? b : INT_MAX;
+            for (int off = 32; off > 0; off >>= 1) mb = min(mb, __shfl_xor(mb, off));
+            const bool leader = same && (__ffsll((long long)__ballot(same)) - 1) == lane;
+            if (leader) b = mb;
+            if (!valid || (same && !leader)) continue;
+            int s = (int)(home_slot(key, log2cap) & (uint64_t)(S - 1));
+            bool done = false;
+            for (; s < S; ++s) {
+                unsigned long long cur = tk[s];
+                if (cur == kEmptyKey) cur = atomicCAS(&tk[s], kEmptyKey, key);
+                if (cur == kEmptyKey || cur == key) {
+                    atomicMin(&tv[s], b);
+                    done = true;
+                    break;
+                }
+            }
+            if (!done) {
+                const uint32_t r = atomicAdd(&nspill, 1u);
+                run[r] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)b, 0u);
+            }
+        }
+        __syncthreads();
+    }
+    Bucket *out = tables + ((size_t)i << log2cap) + ((size_t)g << qb);
+    uint8_t *ofp = table_fps(tables, L, log2cap, (int)i) + ((size_t)g << qb);
+    for (int s = threadIdx.x; s < S; s += 256) {
+        Bucket bk;
+        bk.key = tk[s];
+        bk.val = tv[s];
+        bk.pad = 0;
+        out[s] = bk;
+    }
+    for (int s4 = threadIdx.x; s4 < S / 4; s4 += 256) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned long long k = tk[4 * s4 + q];
+            w |= (k == kEmptyKey ? 0u : key_fp(k, log2cap)) << (8 * q);
+        }
+        reinterpret_cast<uint32_t *>(ofp)[s4] = w;
+    }
+    if (threadIdx.x == 0) {
+        bins[(i * R + g) * 3 + 2] = nspill;
+        if (nspill) atomicOr(spilled, 1u);
+    }
+}
+
+// The pairs the LDS builds kept aside, inserted with the global insert; a
+// single flag word says whether there are any.
+__global__ __launch_bounds__(256) void k_spill_insert(const uint32_t *__restrict__ bins,
+                                                      const uint4 *__restrict__ entries,
+                                                      int64_t nB, int L, int log2cap,
+                                                      Bucket *tables, const uint32_t *spilled) {
+    if (*spilled == 0) return;
+    const int64_t R = part_regions(log2cap);
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < (int64_t)L * R; r += nw) {
+        const uint32_t ns = bins[r * 3 + 2];
+        if (ns == 0) continue;
+        const int64_t i = r / R;
+        const uint4 *run = entries + (size_t)i * nB + bins[r * 3];
+        for (uint32_t e = lane; e < ns; e += 64) {
+            const uint4 v = run[e];
+            table_insert(tables + ((size_t)i << log2cap), table_fps(tables, L, log2cap, (int)i),
+                         log2cap, (unsigned long long)v.x | ((unsigned long long)v.y << 32),
+                         (int)v.z);
+        }
+    }
+}
+
+hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, Bucket *tables,
+                             hipStream_t st) {
+    if (nB <= 0 || L <= 0) return hipSuccess;
+    if (!part_build_ok(log2cap)) return hipErrorInvalidValue;
+    const int64_t R = part_regions(log2cap), nblk = part_blocks(nB);
+    const int S = 1 << region_bits(log2cap);
+    k_part_hist<<<(unsigned)(L * nblk), 256, (size_t)R * sizeof(uint32_t), st>>>(
+        w.keys, nB, log2cap, nblk, w.offs);
+    k_part_scan<<<(unsigned)L, 256, ((size_t)R + 256) * sizeof(uint32_t), st>>>(
+        nB, log2cap, nblk, w.offs, w.bins, w.spilled);
+    const size_t lds_sc = (2 * (size_t)R + 256) * sizeof(uint32_t) + (size_t)kPartBlock * 12;
+    k_part_scatter<<<(unsigned)(L * nblk), 256, lds_sc, st>>>(w.keys, nB, log2cap, nblk, w.offs,
+                                                              w.bins, w.entries);
+    k_region_build<<<(unsigned)(L * R), 256, (size_t)S * 12, st>>>(w.entries, nB, L, log2cap,
+                                                                   tables, w.bins, w.spilled);
+    k_spill_insert<<<256, 256, 0, st>>>(w.bins, w.entries, nB, L, log2cap, tables, w.spilled);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- batched

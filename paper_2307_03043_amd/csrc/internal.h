@@ -100,9 +100,10 @@ struct Plan {
     int32_t d, metric, L, ke, kh, q, precision, window, reps, sampling;
     uint64_t seed;
     int log2cap;  // per-scale table capacity is 2^log2cap
+    bool part;    // B's tables come from the partitioned build (W = 1)
     // byte offsets into the workspace
     size_t off_params, off_lohi, off_zfrac, off_mult, off_embed, off_tables, off_D,
-        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit, off_xsplit, off_xn2, off_srec,
+        off_nn, off_scale, off_blocksums, off_P, off_idx, off_best, off_partial, off_nb2, off_bsplit, off_xsplit, off_xn2, off_srec, off_part,
         off_bq, off_xq, off_lpf, total;
 };
 
@@ -152,7 +153,7 @@ struct Job {
     uint32_t *lohi;
     float *zfrac;
     uint64_t *mult;
-    const float *embed;
+    const int8_t *embed;
     Bucket *tables;
     int64_t table_count;
     float *D;
@@ -326,16 +327,34 @@ hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t s
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st);
 // mode 0: insert B into the tables (l2: also |b|^2 into nb2_out and
 // p->b2max_bits when nb2_out is set); 1: probe A (CrudeNN); 2: write keys;
+// 5: write B's keys for launch_part_build (duplicates within a wavefront
+// dropped; |b|^2 as mode 0);
 // 3 / 4: insert / probe with a window of W points per bucket (the tables
 // are then keys [L][cap] followed by members [L][cap][W]).  flags: kProbe*.
 hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, int64_t nB,
                        int d, int metric, int L, int ke, const uint32_t *lohi,
-                       const float *embed_t, const float *zfrac, const uint64_t *mult,
+                       const int8_t *embed, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
                        int W, int flags, hipStream_t st);
 // Bytes of the tables of L scales of 2^log2cap buckets with window W.
 size_t table_bytes(int L, int log2cap, int W);
+// The partitioned build of the W = 1 tables (no global atomics): keys of B
+// from launch_hash mode 5 into w.keys, then launch_part_build.  Usable when
+// part_build_ok(log2cap) (at most 4096 regions of 4096 slots per scale).
+struct PartWork {
+    uint64_t *keys;    // [L][nB] (the empty key for a dropped duplicate)
+    uint32_t *offs;    // [L][blocks][regions]
+    uint32_t *bins;    // [L][regions][3]: first entry, count, spilled
+    uint4 *entries;    // [L][nB] (key lo, key hi, b, 0) grouped by region
+    uint32_t *spilled; // [1] some region kept pairs aside for the global insert
+};
+bool part_build_ok(int log2cap);
+// Workspace bytes of the build; with w, also lays the regions out from base.
+size_t part_work_bytes(int L, int64_t nB, int log2cap, PartWork *w = nullptr,
+                       char *base = nullptr);
+hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, Bucket *tables,
+                             hipStream_t st);
 // Empty tables (window W).
 hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStream_t st);
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
@@ -444,19 +463,22 @@ hipError_t launch_batch_final(const Batch *bt, int metric, hipStream_t st);
 
 // Host side of batching (api.hip): validate a request and fill its job with
 // the layout of chamfer_estimate in workspace ws; for l2, embed_host
-// receives the transposed embedding ([d][ke] floats) that the caller must
-// place at embed_dev before the batch runs.
+// receives the packed embedding (embedding_packed, embed_bytes(d, ke)) that
+// the caller must place at embed_dev before the batch runs.
 int job_prepare(const float *A, const float *B, int64_t nA, int64_t nB, int32_t d,
                 int32_t metric, double eps, int64_t T, uint64_t seed, const chamfer_opts *opts,
-                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const float *embed_dev,
-                float *embed_host, Job *job);
+                void *ws, size_t ws_bytes, double *eta, chamfer_aux aux, const int8_t *embed_dev,
+                int8_t *embed_host, Job *job);
 // Block counts of every stage of a job.
 void job_stage_blocks(const Job &job, int64_t out[kBsCount]);
 
-// Host Philox4x64-10 (counter c, key (k0, k1); output in c) and the l2 -> l1
-// embedding matrix, transposed to [d][ke].
+// Host Philox4x64-10 (counter c, key (k0, k1); output in c), the quantised
+// l2 -> l1 embedding matrix ([ke][d] int8) and its packed operand layout for
+// the hash kernels (embed_bytes(d, ke) bytes).
 void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1);
-void embedding_transposed(uint64_t seed, int d, int ke, float *zt);
+void embedding_host(uint64_t seed, int d, int ke, int8_t *Z);
+size_t embed_bytes(int d, int ke);
+void embedding_packed(uint64_t seed, int d, int ke, int8_t *out);
 
 // chamfer_estimate / chamfer_workspace_bytes with opts->reduction set.
 size_t reduced_workspace_bytes(int64_t n_A, int64_t n_B, int32_t d, int32_t metric, double eps,

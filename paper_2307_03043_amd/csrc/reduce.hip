@@ -112,7 +112,7 @@ int rplan(RPlan &rp, int64_t nA, int64_t nB, int32_t d, int32_t metric,
     rp.off_partial = take(kNearBlocks * sizeof(double));
     rp.off_params = take(sizeof(DevParams));
     rp.off_lohi = take(lohi_bytes(d));
-    rp.off_embed = take(metric == CHAMFER_L2 ? (size_t)d * ke * sizeof(float) : 0);
+    rp.off_embed = take(metric == CHAMFER_L2 ? (size_t)d * ke : 0);
     rp.off_zp = take((size_t)rp.kh * sizeof(float));
     rp.off_mp = take((size_t)rp.kh * sizeof(uint64_t));
     rp.off_keysA = take((size_t)nA * sizeof(uint64_t));
@@ -332,11 +332,13 @@ __device__ __forceinline__ uint64_t part_cell_term(float y, int e, float z, uint
 template <int METRIC, int KE>
 __global__ __launch_bounds__(kThreads) void k_part_keys(
     const float *__restrict__ X, int64_t n, int d, const uint32_t *__restrict__ lohi,
-    const float *__restrict__ zt, const float *__restrict__ zp, const uint64_t *__restrict__ mp,
-    const chamfer_reduction *info, uint64_t *__restrict__ keys) {
+    const int8_t *__restrict__ zt, const float *__restrict__ zp, const uint64_t *__restrict__ mp,
+    const chamfer_reduction *info, const DevParams *pr, uint64_t *__restrict__ keys) {
     __shared__ float tile[kThreads][kProjCols + 1];
     const bool degenerate = info->degenerate != 0;
     const int e = info->e_part;
+    const int e_top = pr->e_top;
+    const double inv = 1.0 / (sqrt(2.0 / 3.14159265358979323846) * (double)KE * 32.0);
     for (int64_t r0 = (int64_t)blockIdx.x * kThreads; r0 < n; r0 += (int64_t)gridDim.x * kThreads) {
         const int rows = n - r0 < kThreads ? (int)(n - r0) : kThreads;
         if (degenerate) {
@@ -344,9 +346,10 @@ __global__ __launch_bounds__(kThreads) void k_part_keys(
             continue;
         }
         uint64_t acc = 0;
-        float emb[KE > 0 ? KE : 1];
+        // l2: the exact integer embedding of the quantised coordinates
+        int64_t emb[KE > 0 ? KE : 1];
 #pragma unroll
-        for (int k = 0; k < (KE > 0 ? KE : 1); ++k) emb[k] = 0.0f;
+        for (int k = 0; k < (KE > 0 ? KE : 1); ++k) emb[k] = 0;
         for (int c0 = 0; c0 < d; c0 += kProjCols) {
             const int cols = d - c0 < kProjCols ? d - c0 : kProjCols;
             __syncthreads();
@@ -358,9 +361,11 @@ __global__ __launch_bounds__(kThreads) void k_part_keys(
                     if (METRIC == CHAMFER_L1) {
                         acc += part_cell_term(y, e, zp[c0 + c], mp[c0 + c]);
                     } else {
-                        const float *zrow = zt + (size_t)(c0 + c) * KE;
+                        const int64_t u =
+                            (int64_t)floorf(fminf(ldexpf(y, 24 - e_top), 16777215.0f));
+                        const int8_t *zrow = zt + (size_t)(c0 + c) * KE;
 #pragma unroll
-                        for (int k = 0; k < KE; ++k) emb[k] = fmaf(zrow[k], y, emb[k]);
+                        for (int k = 0; k < KE; ++k) emb[k] += (int64_t)zrow[k] * u;
                     }
                 }
             }
@@ -368,7 +373,10 @@ __global__ __launch_bounds__(kThreads) void k_part_keys(
         if ((int)threadIdx.x < rows) {
             if (METRIC == CHAMFER_L2) {
 #pragma unroll
-                for (int k = 0; k < KE; ++k) acc += part_cell_term(emb[k], e, zp[k], mp[k]);
+                for (int k = 0; k < KE; ++k) {
+                    const float yk = (float)(ldexp((double)emb[k], e_top - 24) * inv);
+                    acc += part_cell_term(yk, e, zp[k], mp[k]);
+                }
             }
             keys[r0 + threadIdx.x] = acc >> 1;
         }
@@ -376,32 +384,21 @@ __global__ __launch_bounds__(kThreads) void k_part_keys(
 }
 
 hipError_t launch_part_keys(const float *X, int64_t n, int d, int metric, int ke,
-                            const uint32_t *lohi, const float *zt, const float *zp,
-                            const uint64_t *mp, const chamfer_reduction *info, uint64_t *keys,
-                            unsigned grid, hipStream_t st) {
+                            const uint32_t *lohi, const int8_t *zt, const float *zp,
+                            const uint64_t *mp, const chamfer_reduction *info,
+                            const DevParams *pr, uint64_t *keys, unsigned grid, hipStream_t st) {
+#define CH_PK_ARGS X, n, d, lohi, zt, zp, mp, info, pr, keys
     if (metric == CHAMFER_L1) {
-        k_part_keys<CHAMFER_L1, 0><<<grid, kThreads, 0, st>>>(X, n, d, lohi, zt, zp, mp, info,
-                                                              keys);
+        k_part_keys<CHAMFER_L1, 0><<<grid, kThreads, 0, st>>>(CH_PK_ARGS);
     } else {
         switch (ke) {
-            case 8:
-                k_part_keys<CHAMFER_L2, 8><<<grid, kThreads, 0, st>>>(X, n, d, lohi, zt, zp, mp,
-                                                                      info, keys);
-                break;
-            case 16:
-                k_part_keys<CHAMFER_L2, 16><<<grid, kThreads, 0, st>>>(X, n, d, lohi, zt, zp, mp,
-                                                                       info, keys);
-                break;
-            case 32:
-                k_part_keys<CHAMFER_L2, 32><<<grid, kThreads, 0, st>>>(X, n, d, lohi, zt, zp, mp,
-                                                                       info, keys);
-                break;
-            default:
-                k_part_keys<CHAMFER_L2, 64><<<grid, kThreads, 0, st>>>(X, n, d, lohi, zt, zp, mp,
-                                                                       info, keys);
-                break;
+            case 8: k_part_keys<CHAMFER_L2, 8><<<grid, kThreads, 0, st>>>(CH_PK_ARGS); break;
+            case 16: k_part_keys<CHAMFER_L2, 16><<<grid, kThreads, 0, st>>>(CH_PK_ARGS); break;
+            case 32: k_part_keys<CHAMFER_L2, 32><<<grid, kThreads, 0, st>>>(CH_PK_ARGS); break;
+            default: k_part_keys<CHAMFER_L2, 64><<<grid, kThreads, 0, st>>>(CH_PK_ARGS); break;
         }
     }
+#undef CH_PK_ARGS
     return hipGetLastError();
 }
 
@@ -497,14 +494,15 @@ int run_reduce(const RPlan &rp, const float *A, const float *B, double eps, uint
     double *partial = at<double>(ws, rp.off_partial);
     DevParams *p = at<DevParams>(ws, rp.off_params);
     uint32_t *lohi = at<uint32_t>(ws, rp.off_lohi);
-    float *zt = at<float>(ws, rp.off_embed);
+    int8_t *zt = at<int8_t>(ws, rp.off_embed);
     float *zp = at<float>(ws, rp.off_zp);
     uint64_t *mp = at<uint64_t>(ws, rp.off_mp);
 
     // host draws: g, the partition grid and (l2) the embedding, one upload
     // each (pageable copies, read before the call returns)
     thread_local std::vector<double> hg;
-    thread_local std::vector<float> hz, hzt;
+    thread_local std::vector<float> hz;
+    thread_local std::vector<int8_t> hzq, hzt;
     thread_local std::vector<uint64_t> hm;
     hg.resize(d);
     sketch_direction(seed, d, rp.metric, hg.data());
@@ -515,9 +513,13 @@ int run_reduce(const RPlan &rp, const float *A, const float *B, double eps, uint
     CH_TRY(hipMemcpyAsync(zp, hz.data(), hz.size() * sizeof(float), hipMemcpyHostToDevice, st));
     CH_TRY(hipMemcpyAsync(mp, hm.data(), hm.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     if (rp.metric == CHAMFER_L2) {
+        // the quantised matrix transposed to [d][ke] (a row per coordinate)
+        hzq.resize((size_t)d * rp.ke);
         hzt.resize((size_t)d * rp.ke);
-        embedding_transposed(seed, d, rp.ke, hzt.data());
-        CH_TRY(hipMemcpyAsync(zt, hzt.data(), hzt.size() * sizeof(float), hipMemcpyHostToDevice,
+        embedding_host(seed, d, rp.ke, hzq.data());
+        for (int j = 0; j < rp.ke; ++j)
+            for (int k = 0; k < d; ++k) hzt[(size_t)k * rp.ke + j] = hzq[(size_t)j * d + k];
+        CH_TRY(hipMemcpyAsync(zt, hzt.data(), hzt.size(), hipMemcpyHostToDevice,
                               st));
     }
 
@@ -548,9 +550,9 @@ int run_reduce(const RPlan &rp, const float *A, const float *B, double eps, uint
     CH_TRY(launch_minmax(A, rp.nA, d, lohi, p, st));
     CH_TRY(launch_minmax(B, rp.nB, d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, d, p, st));
-    CH_TRY(launch_part_keys(A, rp.nA, d, rp.metric, rp.ke, lohi, zt, zp, mp, info, keysA,
+    CH_TRY(launch_part_keys(A, rp.nA, d, rp.metric, rp.ke, lohi, zt, zp, mp, info, p, keysA,
                             grid_for(rp.nA), st));
-    CH_TRY(launch_part_keys(B, rp.nB, d, rp.metric, rp.ke, lohi, zt, zp, mp, info, keysB,
+    CH_TRY(launch_part_keys(B, rp.nB, d, rp.metric, rp.ke, lohi, zt, zp, mp, info, p, keysB,
                             grid_for(rp.nB), st));
     k_one_part<<<grid_for(rp.nA + rp.nB), kThreads, 0, st>>>(keysA, rp.nA, keysB, rp.nB, info);
     CH_TRY(hipGetLastError());

@@ -68,7 +68,7 @@ int layout(Layout &lo, int64_t n_A, const int64_t *offsets, int32_t m, int32_t d
     std::memset(&lo, 0, sizeof(lo));
     lo.batch = up(sizeof(Batch));
     // every job has the same seed and d, hence one embedding matrix (l2)
-    lo.embed = metric == CHAMFER_L2 ? up((size_t)d * ke * sizeof(float)) : 0;
+    lo.embed = metric == CHAMFER_L2 ? up(embed_bytes(d, ke)) : 0;
     lo.eta = up((size_t)2 * m * sizeof(double));
     lo.est = up((size_t)4 * m * sizeof(double));  // estimates, then [3] per candidate
     lo.per_job_ws = up(maxws);
@@ -186,12 +186,12 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
     // B_i -> A)
     Staging stg;
     stg.st = st;
-    std::vector<float> emb;  // read by the copy below before the stream drains
+    std::vector<int8_t> emb;  // read by the copy below before the stream drains
     if (metric == CHAMFER_L2) {
-        emb.resize((size_t)d * ke);
-        embedding_transposed(seed, d, ke, emb.data());
-        CH_TRY(hipMemcpyAsync(base + lo.off_embed, emb.data(), emb.size() * sizeof(float),
-                              hipMemcpyHostToDevice, st));
+        emb.resize(embed_bytes(d, ke));
+        embedding_packed(seed, d, ke, emb.data());
+        CH_TRY(hipMemcpyAsync(base + lo.off_embed, emb.data(), emb.size(), hipMemcpyHostToDevice,
+                              st));
     }
     for (int b = 0; b < 2; ++b) {
         stg.buf[b].resize(lo.batch);  // the batch descriptor
@@ -214,7 +214,7 @@ int chamfer_retrieve(const float *A, int64_t n_A, const float *Bs, const int64_t
             rc = job_prepare(fwd ? A : B, fwd ? B : A, fwd ? n_A : nB, fwd ? nB : n_A, d, metric,
                              eps, T, seed, opts, base + lo.off_jobs + (size_t)s * lo.per_job_ws,
                              lo.per_job_ws, eta + j, aux,
-                             reinterpret_cast<const float *>(base + lo.off_embed), nullptr,
+                             reinterpret_cast<const int8_t *>(base + lo.off_embed), nullptr,
                              &bh->job[s]);
             if (rc) return rc;
         }

@@ -258,8 +258,8 @@ int launch_lane(chamfer_server *s, Lane &ln, const ClassKey &key) {
         aux.status = &od->status;
         int rc = job_prepare(A, B, r.n_A, r.n_B, r.d, r.metric, r.eps, r.T, r.seed, &r.opts, ws,
                              m.job.ws_bytes, &od->eta, aux,
-                             reinterpret_cast<const float *>(ln.dev + eoff),
-                             reinterpret_cast<float *>(ln.host + eoff), &bh->job[j]);
+                             reinterpret_cast<const int8_t *>(ln.dev + eoff),
+                             reinterpret_cast<int8_t *>(ln.host + eoff), &bh->job[j]);
         if (rc != CHAMFER_OK) {
             s->done.push_back(result_of(m.job, rc, ln.admit_s));
             s->arena->release(m.off, m.job.footprint);
@@ -482,7 +482,7 @@ int chamfer_server_submit(chamfer_server *s, const chamfer_request *req, uint64_
     if (pd.footprint == 0) return CHAMFER_EINVAL;
     if (pd.footprint > s->arena->size()) return CHAMFER_EWORKSPACE;  // can never be admitted
     pd.key = class_of(pd.req);
-    pd.embed_bytes = pd.key.metric == CHAMFER_L2 ? round_up((size_t)pd.key.d * pd.key.ke * 4) : 0;
+    pd.embed_bytes = pd.key.metric == CHAMFER_L2 ? round_up(embed_bytes(pd.key.d, pd.key.ke)) : 0;
     pd.id = s->next_id++;
     pd.submit_s = now_s();
     if (id_out) *id_out = pd.id;
