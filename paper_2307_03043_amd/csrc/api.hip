@@ -248,8 +248,7 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
         CH_TRY(hipMemcpyAsync(at<int8_t>(ws, pl.off_embed), zt.data(), zt.size(),
                               hipMemcpyHostToDevice, st));
     }
-    CH_TRY(launch_minmax(A, pl.nA, pl.d, lohi, p, st));
-    CH_TRY(launch_minmax(B, pl.nB, pl.d, lohi, p, st));
+    CH_TRY(launch_minmax_pair(A, pl.nA, B, pl.nB, pl.d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, pl.d, p, st));
     return CHAMFER_OK;
 }
@@ -575,8 +574,7 @@ int chamfer_exact(const float *A, const float *B, int64_t n_A, int64_t n_B, int3
     auto *best = at<unsigned long long>(ws, pl.off_best);
     double *partial = at<double>(ws, pl.off_partial);
     CH_TRY(launch_init_params(p, lohi, d, st));
-    CH_TRY(launch_minmax(A, n_A, d, lohi, p, st));
-    CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
+    CH_TRY(launch_minmax_pair(A, n_A, B, n_B, d, lohi, p, st));
     CH_TRY(launch_calib_final(lohi, d, p, st));
     CH_TRY(launch_fill_u64(best, n_A, ~0ull, st));
     float *nb2 = nullptr;
@@ -665,8 +663,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
         uint32_t *lohi = at<uint32_t>(ws, pl.off_lohi);
         CH_TRY(mark(ev, 0, st));
         CH_TRY(launch_init_params(p, lohi, d, st));
-        CH_TRY(launch_minmax(A, n_A, d, lohi, p, st));
-        CH_TRY(launch_minmax(B, n_B, d, lohi, p, st));
+        CH_TRY(launch_minmax_pair(A, n_A, B, n_B, d, lohi, p, st));
         CH_TRY(launch_calib_final(lohi, d, p, st));
         CH_TRY(mark(ev, 1, st));
         if (bsplit) CH_TRY(launch_rownorm(B, n_B, d, nb2, p, st));

@@ -194,6 +194,19 @@ __global__ __launch_bounds__(256) void k_minmax4(const float4 *__restrict__ X4, 
     minmax4(X4, total4, d, stride4, lohi, p, grid_blk());
 }
 
+// Both point sets in one launch: blocks [0, nbA) take A, the rest B.
+__global__ __launch_bounds__(256) void k_minmax4_pair(const float4 *__restrict__ A4,
+                                                      int64_t totalA4, int64_t strideA4,
+                                                      int64_t nbA, const float4 *__restrict__ B4,
+                                                      int64_t totalB4, int64_t strideB4, int d,
+                                                      uint32_t *lohi, DevParams *p) {
+    const int64_t b = blockIdx.x;
+    if (b < nbA)
+        minmax4(A4, totalA4, d, strideA4, lohi, p, Blk{b, nbA});
+    else
+        minmax4(B4, totalB4, d, strideB4, lohi, p, Blk{b - nbA, (int64_t)gridDim.x - nbA});
+}
+
 bool minmax_vec4(const float *X, int d) {
     return (d & 3) == 0 && d <= 2048 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
 }
@@ -234,6 +247,21 @@ hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevPa
     minmax_geom(n, d, false, &blocks, &stride);
     const size_t lds = d <= 2048 ? 2 * (size_t)d * sizeof(uint32_t) : 0;
     k_minmax<<<(unsigned)blocks, 256, lds, st>>>(X, total, d, stride, lohi, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax_pair(const float *A, int64_t nA, const float *B, int64_t nB, int d,
+                              uint32_t *lohi, DevParams *p, hipStream_t st) {
+    if (nA <= 0 || !minmax_vec4(A, d) || !minmax_vec4(B, d)) {
+        hipError_t e = nA > 0 ? launch_minmax(A, nA, d, lohi, p, st) : hipSuccess;
+        return e != hipSuccess ? e : launch_minmax(B, nB, d, lohi, p, st);
+    }
+    int64_t nbA, sA, nbB, sB;
+    minmax_geom(nA, d, true, &nbA, &sA);
+    minmax_geom(nB, d, true, &nbB, &sB);
+    k_minmax4_pair<<<(unsigned)(nbA + nbB), 256, 2 * (size_t)d * sizeof(uint32_t), st>>>(
+        reinterpret_cast<const float4 *>(A), nA * (int64_t)d / 4, sA, nbA,
+        reinterpret_cast<const float4 *>(B), nB * (int64_t)d / 4, sB, d, lohi, p);
     return hipGetLastError();
 }
 

@@ -323,6 +323,10 @@ hipError_t launch_grid_tables(uint64_t seed, int L, int kh, float *zfrac, uint64
                               int rep, hipStream_t st);
 hipError_t launch_minmax(const float *X, int64_t n, int d, uint32_t *lohi, DevParams *p,
                          hipStream_t st);
+// The same over A and then B in one launch (two launches when either set
+// is not 16-byte aligned with d a multiple of 4).
+hipError_t launch_minmax_pair(const float *A, int64_t nA, const float *B, int64_t nB, int d,
+                              uint32_t *lohi, DevParams *p, hipStream_t st);
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st);
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st);
 // mode 0: insert B into the tables (l2: also |b|^2 into nb2_out and

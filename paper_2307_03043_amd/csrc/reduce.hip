@@ -14,8 +14,6 @@
 // The estimate with the reduction reads the partition on the host once and
 // either runs the plain estimate (one part, degenerate, or a part of A
 // without points of B) or sums the estimates of the gathered parts.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -27,6 +25,12 @@
 using namespace chamfer;
 
 namespace {
+
+// Keys per block of the radix sort of B's projections (below).
+constexpr int kSortItems = 8;
+constexpr int kSortBlock = 256 * kSortItems;
+
+int64_t sort_blocks(int64_t n) { return (n + kSortBlock - 1) / kSortBlock; }
 
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -92,10 +96,8 @@ int rplan(RPlan &rp, int64_t nA, int64_t nB, int32_t d, int32_t metric,
     rp.lb = ceil_log2_i64(nB);
     rp.ln = ceil_log2_i64(n);
     rp.m = pad_dims(nA, nB, d);
-    // radix sort temporary storage: histograms and look-back state, well
-    // under one byte per key plus a constant (checked against the sort's own
-    // query at run time)
-    rp.sort_bytes = up((size_t)nB + (16u << 20));
+    // radix sort: a 256-bin count per block of keys, per pass
+    rp.sort_bytes = up((size_t)256 * sort_blocks(nB) * sizeof(uint32_t));
     size_t o2 = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o2;
@@ -216,6 +218,139 @@ __global__ __launch_bounds__(kThreads) void k_project(const float *__restrict__ 
         }
         if ((int)threadIdx.x < rows) out[r0 + threadIdx.x] = acc;
     }
+}
+
+// ------------------------------------------------------------- radix sort
+// B's projections in ascending order: an LSD radix sort of their
+// order-preserving 64-bit codes (sign bit flipped for non-negative doubles,
+// every bit for negative ones), eight passes of 8-bit digits.  A pass counts
+// the digits of each block of kSortBlock codes into 256 bins (k_sort_hist),
+// one workgroup turns the [digit][block] counts into exclusive offsets
+// (k_sort_scan), and each block writes its codes to their places
+// (k_sort_scatter).  The scatter is stable: codes of one block keep their
+// order -- a wavefront ranks equal digits by ballots over the eight digit
+// bits, the wavefronts of a round and the rounds of a block are ordered
+// through per-digit counters in LDS -- so each pass keeps the order of the
+// previous ones among equal digits, and the eight passes sort.
+__device__ __forceinline__ unsigned long long dbl_code(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+__device__ __forceinline__ double code_dbl(unsigned long long c) {
+    const unsigned long long u = (c >> 63) ? (c & ~(1ull << 63)) : ~c;
+    return __longlong_as_double((long long)u);
+}
+
+__global__ __launch_bounds__(256) void k_sort_encode(double *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) reinterpret_cast<unsigned long long *>(p)[i] = dbl_code(p[i]);
+}
+
+__global__ __launch_bounds__(256) void k_sort_decode(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) reinterpret_cast<double *>(p)[i] = code_dbl(p[i]);
+}
+
+// cnt[digit * nblk + block] = how many codes of the block have that digit.
+__global__ __launch_bounds__(256) void k_sort_hist(const unsigned long long *__restrict__ keys,
+                                                   int64_t n, int shift, int64_t nblk,
+                                                   uint32_t *cnt) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b = blockIdx.x;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t e = b * kSortBlock + it * 256 + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    cnt[(int64_t)threadIdx.x * nblk + b] = h[threadIdx.x];
+}
+
+// Exclusive prefix sum in place over the total = 256 nblk counts (digit
+// major): each of 1024 threads sums a contiguous run, the run sums are
+// scanned in LDS, then each run is rewritten as offsets.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *cnt, int64_t total) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (total + 1023) / 1024;
+    const int64_t b0 = min(total, t * per), b1 = min(total, b0 + per);
+    uint32_t sum = 0;
+    for (int64_t i = b0; i < b1; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int64_t i = b0; i < b1; ++i) {
+        const uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const unsigned long long *__restrict__ in,
+                                                      unsigned long long *__restrict__ out,
+                                                      int64_t n, int shift, int64_t nblk,
+                                                      const uint32_t *__restrict__ off) {
+    __shared__ uint32_t base[256];    // next place of each digit for this block
+    __shared__ uint32_t wc[4][256];   // per-wavefront digit counts of the round
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t b = blockIdx.x;
+    base[t] = off[(int64_t)t * nblk + b];
+    for (int q = 0; q < 4; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t e = b * kSortBlock + it * 256 + t;
+        const bool valid = e < n;
+        const unsigned long long key = valid ? in[e] : 0ull;
+        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const unsigned long long bb = __ballot((dg >> bit) & 1u);
+            m &= ((dg >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[dg] + rank;
+            for (int q = 0; q < w; ++q) pos += wc[q][dg];
+            out[pos] = key;
+        }
+        __syncthreads();
+        base[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        for (int q = 0; q < 4; ++q) wc[q][t] = 0;
+        __syncthreads();
+    }
+}
+
+// Sorts p[0..n) (doubles) ascending; tmp holds n doubles, cnt 256
+// sort_blocks(n) counts.  The sorted values end in p.
+hipError_t sort_doubles(double *p, double *tmp, int64_t n, uint32_t *cnt, hipStream_t st) {
+    if (n <= 1) return hipSuccess;
+    const int64_t nblk = sort_blocks(n);
+    const unsigned g256 = (unsigned)((n + 255) / 256);
+    auto *a = reinterpret_cast<unsigned long long *>(p);
+    auto *b = reinterpret_cast<unsigned long long *>(tmp);
+    k_sort_encode<<<g256, 256, 0, st>>>(p, n);
+    for (int shift = 0; shift < 64; shift += 8) {
+        k_sort_hist<<<(unsigned)nblk, 256, 0, st>>>(a, n, shift, nblk, cnt);
+        k_sort_scan<<<1, 1024, 0, st>>>(cnt, 256 * nblk);
+        k_sort_scatter<<<(unsigned)nblk, 256, 0, st>>>(a, b, n, shift, nblk, cnt);
+        std::swap(a, b);
+    }
+    // eight passes: the sorted codes are back in p
+    k_sort_decode<<<g256, 256, 0, st>>>(a, n);
+    return hipGetLastError();
 }
 
 // t_a = min(succ - p_a, p_a - pred) over B's sorted projections; per block
@@ -528,13 +663,8 @@ int run_reduce(const RPlan &rp, const float *A, const float *B, double eps, uint
     k_project<<<grid_for(rp.nA, 8192), kThreads, 0, st>>>(A, rp.nA, d, g, pa);
     k_project<<<grid_for(rp.nB, 8192), kThreads, 0, st>>>(B, rp.nB, d, g, pb);
     CH_TRY(hipGetLastError());
-    size_t need = 0;
-    hipcub::DoubleBuffer<double> keys(pb, alt);
-    CH_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, need, keys, (int)rp.nB, 0, 64, st));
-    if (need > rp.sort_bytes) return CHAMFER_EWORKSPACE;
-    CH_TRY(hipcub::DeviceRadixSort::SortKeys(at<void>(ws, rp.off_sort), need, keys, (int)rp.nB,
-                                             0, 64, st));
-    const double *pbs = keys.Current();
+    CH_TRY(sort_doubles(pb, alt, rp.nB, at<uint32_t>(ws, rp.off_sort), st));
+    const double *pbs = pb;
     const unsigned nb = grid_for(rp.nA, kNearBlocks);
     k_nearest1d<<<nb, kThreads, 0, st>>>(pa, rp.nA, pbs, rp.nB, t_out, partial, scr);
     // 4: bounds; q0 = eps / (2 n m) in double, scaled by 2^(e_M - k_hi) on
