@@ -248,8 +248,9 @@ __device__ __forceinline__ void nnmin_l2_split(
     constexpr int LDR = RB + 16;                 // padded LDS row (bytes)
     constexpr int NV = kSplitTileRows * RB / 16;  // 16-byte units per tile
     constexpr int PER_T = (NV + 255) / 256;
-    __shared__ __attribute__((aligned(16))) uint8_t tile[kSplitTileRows * LDR];
-    __shared__ __attribute__((aligned(16))) float tn2[kSplitTileRows];  // -|b|^2 / 2
+    constexpr int NBUF = DP <= 128 ? 2 : 1;  // LDS tile buffers (three workgroups per CU)
+    __shared__ __attribute__((aligned(16))) uint8_t tile[NBUF * kSplitTileRows * LDR];
+    __shared__ __attribute__((aligned(16))) float tn2[NBUF * kSplitTileRows];  // -|b|^2 / 2
 
     if (p->status != CHAMFER_OK) return;
     const int tid = threadIdx.x;
@@ -297,123 +298,164 @@ __device__ __forceinline__ void nnmin_l2_split(
 
     // Register prefetch of one tile: thread tid takes the 16-byte unit
     // u = tid % UPR of the rows tid / UPR + i RPI (i < PER_T), and threads
-    // below kSplitTileRows take -|b|^2 / 2 of one row (-inf past the chunk).
+    // below kSplitTileRows take |b|^2 of one row.  Rows past the chunk are
+    // read at its last row, so every load is in bounds and unconditional
+    // (no register defaults that would make the loop wait on the loads in
+    // flight); store() writes them as zero rows with -|b|^2 / 2 = -inf.
     constexpr int UPR = RB / 16;  // 16-byte units per split row
     constexpr int RPI = 256 / UPR;
     static_assert(RPI * PER_T == kSplitTileRows, "one tile per 256 threads and PER_T passes");
     const int r0 = tid / UPR, u0 = tid - (tid / UPR) * UPR;
+    // Tiles are addressed by their first row t relative to b0 (a chunk has
+    // fewer than 2^31 rows).
+    const int len = (int)(b1 - b0);
+    const CH_RO uint4 *cbase = reinterpret_cast<const CH_RO uint4 *>(ro(Bs)) + b0 * UPR + u0;
+    const CH_RO float *cn2 = ro(nb2) + b0;
     uint4 pf[PER_T];
-    float pn2 = -INFINITY;
-    auto fetch = [&](int64_t t0) {
-        const CH_RO uint4 *src =
-            reinterpret_cast<const CH_RO uint4 *>(ro(Bs) + (size_t)(t0 + r0) * (2 * DP)) + u0;
-        if (t0 + kSplitTileRows <= b1) {  // whole tile (uniform)
+    float pn2 = 0.0f;
+    auto fetch = [&](int t) {
+        if (tid < kSplitTileRows) pn2 = cn2[min(t + tid, len - 1)];
+        if (t + kSplitTileRows <= len) {  // whole tile (uniform)
+            const CH_RO uint4 *src = cbase + (size_t)(t + r0) * UPR;
 #pragma unroll
-            for (int i = 0; i < PER_T; ++i) pf[i] = ld(src + (size_t)i * RPI * UPR);
+            for (int i = 0; i < PER_T; ++i) pf[i] = ld(src + i * RPI * UPR);
         } else {
 #pragma unroll
             for (int i = 0; i < PER_T; ++i)
-                pf[i] = t0 + r0 + i * RPI < b1 ? ld(src + (size_t)i * RPI * UPR)
-                                               : make_uint4(0u, 0u, 0u, 0u);
+                pf[i] = ld(cbase + (size_t)min(t + r0 + i * RPI, len - 1) * UPR);
+        }
+    };
+    auto store = [&](int buf, int t) {
+        uint8_t *tb = tile + buf * (kSplitTileRows * LDR);
+        if (t + kSplitTileRows <= len) {
+#pragma unroll
+            for (int i = 0; i < PER_T; ++i)
+                *reinterpret_cast<uint4 *>(&tb[(r0 + i * RPI) * LDR + u0 * 16]) = pf[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < PER_T; ++i)
+                *reinterpret_cast<uint4 *>(&tb[(r0 + i * RPI) * LDR + u0 * 16]) =
+                    t + r0 + i * RPI < len ? pf[i] : make_uint4(0u, 0u, 0u, 0u);
         }
         if (tid < kSplitTileRows)
-            pn2 = (t0 + tid < b1) ? -0.5f * ro(nb2)[t0 + tid] : -INFINITY;
+            tn2[buf * kSplitTileRows + tid] = t + tid < len ? -0.5f * pn2 : -INFINITY;
     };
-
-    int64_t t0 = b0;
-    fetch(t0);
-    for (;;) {
-        __syncthreads();  // the previous tile is no longer being read
+    // MFMA scores of the tile in buffer buf (rows b0 + t...) and the
+    // running best / second-best per lane and query
+    auto compute = [&](int buf, int t) {
+        if (!wave_active) return;
+        const uint8_t *tb = tile + buf * (kSplitTileRows * LDR);
+        const int32_t rbase = (int32_t)b0 + t + 4 * g;
+        const float *tnb = tn2 + buf * kSplitTileRows;
+        // TERMS = 3: every product into hi; TERMS = 4: the small ones into lo
+        constexpr int NL = TERMS == 4 ? kSplitMB : 1;
+        v4f hi[kSplitMB][NB], lo[NL][NB];
 #pragma unroll
-        for (int i = 0; i < PER_T; ++i)
-            *reinterpret_cast<uint4 *>(&tile[(r0 + i * RPI) * LDR + u0 * 16]) = pf[i];
-        if (tid < kSplitTileRows) tn2[tid] = pn2;
-        __syncthreads();
-        const int64_t next = t0 + kSplitTileRows;
-        if (next < b1) fetch(next);
-
-        if (wave_active) {
-            // TERMS = 3: every product into hi; TERMS = 4: the small ones into lo
-            constexpr int NL = TERMS == 4 ? kSplitMB : 1;
-            v4f hi[kSplitMB][NB], lo[NL][NB];
+        for (int m = 0; m < kSplitMB; ++m) {
+            const v4f h0 = *reinterpret_cast<const v4f *>(&tnb[16 * m + 4 * g]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) hi[m][nb] = h0;
+        }
+#pragma unroll
+        for (int m = 0; m < NL; ++m)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) lo[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v8bf ah[kSplitMB], am[kSplitMB];
 #pragma unroll
             for (int m = 0; m < kSplitMB; ++m) {
-                const v4f h0 = *reinterpret_cast<const v4f *>(&tn2[16 * m + 4 * g]);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) hi[m][nb] = h0;
+                const uint8_t *ap = &tb[(16 * m + j) * LDR + (g * KQ + 8 * s) * 2];
+                ah[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap));
+                am[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap + 2 * DP));
             }
 #pragma unroll
-            for (int m = 0; m < NL; ++m)
+            for (int nb = 0; nb < NB; ++nb) {
+                const v8bf xh = __builtin_bit_cast(v8bf, qh[nb][s]);
+                const v8bf xm = __builtin_bit_cast(v8bf, qm[nb][s]);
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) lo[m][nb] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int m = 0; m < kSplitMB; ++m)
+                    hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xh, hi[m][nb],
+                                                                        0, 0, 0);
+                if constexpr (TERMS == 4) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                v8bf ah[kSplitMB], am[kSplitMB];
-#pragma unroll
-                for (int m = 0; m < kSplitMB; ++m) {
-                    const uint8_t *ap = &tile[(16 * m + j) * LDR + (g * KQ + 8 * s) * 2];
-                    ah[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap));
-                    am[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(ap + 2 * DP));
-                }
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const v8bf xh = __builtin_bit_cast(v8bf, qh[nb][s]);
-                    const v8bf xm = __builtin_bit_cast(v8bf, qm[nb][s]);
+                    for (int m = 0; m < kSplitMB; ++m) {
+                        lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
+                                                                            lo[m][nb], 0, 0, 0);
+                        lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
+                                                                            lo[m][nb], 0, 0, 0);
+                        lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xm,
+                                                                            lo[m][nb], 0, 0, 0);
+                    }
+                } else {
 #pragma unroll
                     for (int m = 0; m < kSplitMB; ++m)
-                        hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xh, hi[m][nb],
-                                                                            0, 0, 0);
-                    if constexpr (TERMS == 4) {
+                        hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
+                                                                            hi[m][nb], 0, 0, 0);
 #pragma unroll
-                        for (int m = 0; m < kSplitMB; ++m) {
-                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
-                                                                                lo[m][nb], 0, 0, 0);
-                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
-                                                                                lo[m][nb], 0, 0, 0);
-                            lo[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xm,
-                                                                                lo[m][nb], 0, 0, 0);
-                        }
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < kSplitMB; ++m)
-                            hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], xm,
-                                                                                hi[m][nb], 0, 0, 0);
-#pragma unroll
-                        for (int m = 0; m < kSplitMB; ++m)
-                            hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
-                                                                                hi[m][nb], 0, 0, 0);
-                    }
+                    for (int m = 0; m < kSplitMB; ++m)
+                        hi[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[m], xh,
+                                                                            hi[m][nb], 0, 0, 0);
                 }
             }
-            // Lane (g, j) holds rows 16m + 4g + r of the tile for query j,
-            // taken in pairs (r, r + 1): the pair's larger value (the lower
-            // row on a tie) against the best, and the second largest of
-            // {best, pair} = med3 against the second.
-#pragma unroll
-            for (int m = 0; m < kSplitMB; ++m)
-#pragma unroll
-                for (int r = 0; r < 4; r += 2) {
-                    const int32_t row0 = (int32_t)(t0 + 16 * m + 4 * g + r);
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        float v0 = hi[m][nb][r], v1 = hi[m][nb][r + 1];
-                        if constexpr (TERMS == 4) {
-                            v0 += lo[m][nb][r];
-                            v1 += lo[m][nb][r + 1];
-                        }
-                        const float bv = bestv[nb];
-                        const bool up = v1 > v0;
-                        const float pm = up ? v1 : v0;
-                        second[nb] = fmaxf(second[nb], __builtin_amdgcn_fmed3f(bv, v0, v1));
-                        const bool gt = pm > bv;
-                        bestv[nb] = gt ? pm : bv;
-                        bidx[nb] = gt ? row0 + (int32_t)up : bidx[nb];
-                    }
-                }
         }
-        t0 = next;
-        if (t0 >= b1) break;
+        // Lane (g, j) holds rows 16m + 4g + r of the tile for query j,
+        // taken in pairs (r, r + 1): the pair's larger value (the lower
+        // row on a tie) against the best, and the second largest of
+        // {best, pair} = med3 against the second.
+#pragma unroll
+        for (int m = 0; m < kSplitMB; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; r += 2) {
+                const int32_t row0 = rbase + 16 * m + r;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    float v0 = hi[m][nb][r], v1 = hi[m][nb][r + 1];
+                    if constexpr (TERMS == 4) {
+                        v0 += lo[m][nb][r];
+                        v1 += lo[m][nb][r + 1];
+                    }
+                    const float bv = bestv[nb];
+                    const bool up = v1 > v0;
+                    const float pm = up ? v1 : v0;
+                    second[nb] = fmaxf(second[nb], __builtin_amdgcn_fmed3f(bv, v0, v1));
+                    const bool gt = pm > bv;
+                    bestv[nb] = gt ? pm : bv;
+                    bidx[nb] = gt ? row0 + (int32_t)up : bidx[nb];
+                }
+            }
+    };
+
+    // One barrier per tile with two buffers: tile i + 1 is written to the
+    // buffer that tile i - 1 occupied, which every wavefront finished
+    // reading before the barrier that ended step i - 1.  With one buffer
+    // (d_pad = 256: LDS) the tile is written between two barriers.
+    int t = 0, buf = 0;
+    fetch(t);
+    if constexpr (NBUF == 2) {
+        store(0, t);
+        __syncthreads();
     }
+    for (; t + kSplitTileRows < len; t += kSplitTileRows) {
+        if constexpr (NBUF == 1) {
+            __syncthreads();  // the previous tile is no longer being read
+            store(0, t);
+            __syncthreads();
+        }
+        fetch(t + kSplitTileRows);
+        compute(buf, t);
+        if constexpr (NBUF == 2) {
+            buf ^= 1;
+            store(buf, t + kSplitTileRows);
+            __syncthreads();
+        }
+    }
+    if constexpr (NBUF == 1) {
+        __syncthreads();
+        store(0, t);
+        __syncthreads();
+    }
+    compute(buf, t);
     if (!wave_active) return;
 
     if constexpr (DEFER) {
