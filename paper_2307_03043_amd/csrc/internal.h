@@ -253,14 +253,29 @@ __device__ __forceinline__ float canon_acc(const float *__restrict__ a,
         const auto *b4 = reinterpret_cast<const CH_RO float4 *>(ro(b));
         const int d4 = d >> 2;
         constexpr int kBatch = BATCH;
-        for (int k0 = 0; k0 < d4; k0 += kBatch) {
+        int k0 = 0;
+        for (; k0 + kBatch <= d4; k0 += kBatch) {  // whole batches: no guards
             float4 u[kBatch], v[kBatch];
 #pragma unroll
-            for (int i = 0; i < kBatch; ++i)
-                if (k0 + i < d4) {
-                    u[i] = ld(a4 + k0 + i);
-                    v[i] = ld(b4 + k0 + i);
-                }
+            for (int i = 0; i < kBatch; ++i) {
+                u[i] = ld(a4 + k0 + i);
+                v[i] = ld(b4 + k0 + i);
+            }
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                step(u[i].x, v[i].x);
+                step(u[i].y, v[i].y);
+                step(u[i].z, v[i].z);
+                step(u[i].w, v[i].w);
+            }
+        }
+        if (k0 < d4) {  // the last, partial batch: loads clamped in bounds
+            float4 u[kBatch], v[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                u[i] = ld(a4 + min(k0 + i, d4 - 1));
+                v[i] = ld(b4 + min(k0 + i, d4 - 1));
+            }
 #pragma unroll
             for (int i = 0; i < kBatch; ++i)
                 if (k0 + i < d4) {

@@ -50,8 +50,8 @@
 // exact rescan.
 //
 // Deferred form (the estimator's draws): the pass only records, per (query,
-// chunk), the chunk's largest v, its row and the second largest v of the
-// whole chunk; k_split_resolve then takes each query in one wavefront,
+// chunk), the chunk's largest v, its row, the second largest v of the whole
+// chunk and the chunk's index; k_split_resolve then takes each query in one wavefront,
 // bounds its minimum from above over all chunks, evaluates the canonical
 // distance of only those chunk candidates whose lower bound reaches that
 // bound (one per query on most data, instead of four per chunk), and lists
@@ -477,8 +477,8 @@ __device__ __forceinline__ void nnmin_l2_split(
             }
             const int64_t qi = qbase + nb * 16 + j;
             if (g == 0 && qi < nx)
-                rec[(size_t)qi * nchunk + cb] =
-                    make_uint4(__float_as_uint(v1), (uint32_t)i1, __float_as_uint(v2), 0u);
+                rec[(size_t)qi * nchunk + cb] = make_uint4(
+                    __float_as_uint(v1), (uint32_t)i1, __float_as_uint(v2), (uint32_t)cb);
         }
         return;
     }
@@ -565,25 +565,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // smallest (value, row) found.
 // K > 0: the query's records are read once into K registers per lane
 // (nchunk <= 64 K), so the three passes over them wait on one round of
-// loads; K = 0 reads them from memory in each pass.
+// loads; the candidates of (2) and the chunks to rescan of (3) are first
+// listed in LDS and then evaluated in one loop each, which keeps a single
+// copy of the canonical distance in the kernel (unrolled over the K
+// records it would not fit the instruction cache).  K = 0 reads the
+// records from memory in each pass.
 template <int K>
 __global__ __launch_bounds__(256) void k_split_resolve(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
     const float *__restrict__ xn2, const float *__restrict__ B, int64_t nB, int d, int DP,
     int64_t chunk, int nchunk, const uint4 *__restrict__ rec, uint2 *__restrict__ redo,
     unsigned long long *best, DevParams *p) {
+    __shared__ int lists[4][K > 0 ? 64 * K : 1];
     if (p->status != CHAMFER_OK) return;
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= nx) return;  // uniform over the wavefront
+    int *list = lists[threadIdx.x >> 6];
+    const unsigned long long below = (1ull << lane) - 1;
     const CH_RO uint4 *r = ro(rec) + (size_t)q * nchunk;
-    // records past nchunk read as empty chunks (v = v2 = -inf)
+    // records past nchunk read as empty chunks (v = v2 = -inf); a record
+    // is (v, row, v2, chunk), and all four words stay in use, so no load's
+    // destination is reused while it is in flight
     const uint4 none = make_uint4(0xff800000u, 0u, 0xff800000u, 0u);
     uint4 w[K > 0 ? K : 1];
     if constexpr (K > 0) {
+        // every load in bounds and unconditional, so they are all in flight
+        // together; the records past nchunk are replaced afterwards
+#pragma unroll
+        for (int i = 0; i < K; ++i) w[i] = ld(r + min(i * 64 + lane, nchunk - 1));
 #pragma unroll
         for (int i = 0; i < K; ++i)
-            w[i] = i * 64 + lane < nchunk ? ld(r + i * 64 + lane) : none;
+            if (i * 64 + lane >= nchunk) w[i] = none;
     }
     auto rec_at = [&](int i) -> uint4 {
         if constexpr (K > 0) return w[i];
@@ -598,6 +611,9 @@ __global__ __launch_bounds__(256) void k_split_resolve(
         split_score_bound(d, DP, 3, xn, (double)__uint_as_float(p->b2max_bits));
     const double xlo = xn * (1.0 - rho), xhi = xn * (1.0 + 2.0 * rho);
     const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
+    auto dist = [&](int64_t b) {
+        return pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + b * d, d), b);
+    };
 
     double ub = INFINITY;
 #pragma unroll kUnroll
@@ -607,46 +623,66 @@ __global__ __launch_bounds__(256) void k_split_resolve(
     }
     for (int off = 32; off > 0; off >>= 1) ub = fmin(ub, __shfl_xor(ub, off));
 
-    unsigned long long m = ~0ull;
-#pragma unroll kUnroll
-    for (int i = 0; i < iters; ++i) {
-        const uint4 c = rec_at(i);
+    auto is_cand = [&](uint4 c) {
         const float v = __uint_as_float(c.x);
-        if (v > -INFINITY && !((1.0 - rho) * (-2.0 * (double)v - E + xlo) > ub))
-            m = min(m, pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + (int64_t)c.y * d, d), c.y));
+        return v > -INFINITY && !((1.0 - rho) * (-2.0 * (double)v - E + xlo) > ub);
+    };
+    unsigned long long m = ~0ull;
+    if constexpr (K > 0) {
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const uint4 c = w[i];
+            const bool cand = is_cand(c);
+            const unsigned long long mk = __ballot(cand);
+            if (cand) list[n + __popcll(mk & below)] = (int)c.y;
+            n += __popcll(mk);
+        }
+        for (int t = lane; t < n; t += 64) m = min(m, dist(list[t]));
+    } else {
+        for (int i = 0; i < iters; ++i) {
+            const uint4 c = rec_at(i);
+            if (is_cand(c)) m = min(m, dist(c.y));
+        }
     }
     for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
     const double thr = (double)unpack_sp(m);
 
+    // chunks whose other rows are not settled: rescanned below (redo null)
+    // or listed for k_split_redo
+    auto rescan = [&](int64_t c) {
+        const int64_t b0 = c * chunk, b1 = min(nB, b0 + chunk);
+        for (int64_t b = b0 + lane; b < b1; b += 64) m = min(m, dist(b));
+    };
+    int nf = 0;
 #pragma unroll kUnroll
     for (int i = 0; i < iters; ++i) {
-        const int c0 = i * 64;
-        const float v2 = __uint_as_float(rec_at(i).z);
+        const uint4 c = rec_at(i);
+        const float v2 = __uint_as_float(c.z);
         const bool flag =
-            c0 + lane < nchunk && !((1.0 - rho) * (-2.0 * (double)v2 - E + xlo) > thr);
+            i * 64 + lane < nchunk && !((1.0 - rho) * (-2.0 * (double)v2 - E + xlo) > thr);
         unsigned long long mask = __ballot(flag);
         if (mask == 0) continue;
+        if (lane == 0) atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
         if (redo == nullptr) {
-            if (lane == 0) atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
-            while (mask) {
-                const int64_t c = c0 + __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
-                const int64_t b0 = c * chunk, b1 = min(nB, b0 + chunk);
-                for (int64_t b = b0 + lane; b < b1; b += 64)
-                    m = min(m, pack_sp(canon_acc<CHAMFER_L2, 16>(x, B + b * d, d), b));
+            if constexpr (K > 0) {
+                if (flag) list[nf + __popcll(mask & below)] = (int)c.w;
+                nf += __popcll(mask);
+            } else {
+                while (mask) {
+                    const int jj = __ffsll((long long)mask) - 1;
+                    mask &= mask - 1;
+                    rescan(i * 64 + jj);
+                }
             }
             continue;
         }
         uint32_t base = 0;
-        if (lane == 0) {
-            base = atomicAdd(&p->nredo, (uint32_t)__popcll(mask));
-            atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
-        }
+        if (lane == 0) base = atomicAdd(&p->nredo, (uint32_t)__popcll(mask));
         base = __shfl(base, 0);
-        if (flag)
-            redo[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1))] =
-                make_uint2((uint32_t)q, (uint32_t)(c0 + lane));
+        if (flag) redo[base + (uint32_t)__popcll(mask & below)] = make_uint2((uint32_t)q, c.w);
     }
+    for (int f = 0; f < nf; ++f) rescan(list[f]);
     if (redo == nullptr)
         for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
     if (lane == 0) best[q] = m;
