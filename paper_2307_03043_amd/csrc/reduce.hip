@@ -97,7 +97,7 @@ int rplan(RPlan &rp, int64_t nA, int64_t nB, int32_t d, int32_t metric,
     rp.ln = ceil_log2_i64(n);
     rp.m = pad_dims(nA, nB, d);
     // radix sort: a 256-bin count per block of keys, per pass
-    rp.sort_bytes = up((size_t)256 * sort_blocks(nB) * sizeof(uint32_t));
+    rp.sort_bytes = up((size_t)256 * (sort_blocks(nB) + 1) * sizeof(uint32_t));
     size_t o2 = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o2;
@@ -225,9 +225,10 @@ __global__ __launch_bounds__(kThreads) void k_project(const float *__restrict__ 
 // order-preserving 64-bit codes (sign bit flipped for non-negative doubles,
 // every bit for negative ones), eight passes of 8-bit digits.  A pass counts
 // the digits of each block of kSortBlock codes into 256 bins (k_sort_hist),
-// one workgroup turns the [digit][block] counts into exclusive offsets
-// (k_sort_scan), and each block writes its codes to their places
-// (k_sort_scatter).  The scatter is stable: codes of one block keep their
+// one workgroup per digit turns its row of the [digit][block] counts into
+// exclusive offsets within the digit and the digit's total
+// (k_sort_rowscan), and each block adds the digits' exclusive totals and
+// writes its codes to their places (k_sort_scatter).  The scatter is stable: codes of one block keep their
 // order -- a wavefront ranks equal digits by ballots over the eight digit
 // bits, the wavefronts of a round and the rounds of a block are ordered
 // through per-digit counters in LDS -- so each pass keeps the order of the
@@ -269,41 +270,61 @@ __global__ __launch_bounds__(256) void k_sort_hist(const unsigned long long *__r
     cnt[(int64_t)threadIdx.x * nblk + b] = h[threadIdx.x];
 }
 
-// Exclusive prefix sum in place over the total = 256 nblk counts (digit
-// major): each of 1024 threads sums a contiguous run, the run sums are
-// scanned in LDS, then each run is rewritten as offsets.
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *cnt, int64_t total) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (total + 1023) / 1024;
-    const int64_t b0 = min(total, t * per), b1 = min(total, b0 + per);
-    uint32_t sum = 0;
-    for (int64_t i = b0; i < b1; ++i) sum += cnt[i];
-    part[t] = sum;
+// Exclusive scan of one value per thread of a 256-thread workgroup: the
+// thread's exclusive prefix, and the sum of all 256 in *all.  ws: 4 words
+// of LDS.  Every thread must call it (two barriers).
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t c, uint32_t *ws, uint32_t *all) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t x = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) ws[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t x = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
+    uint32_t pre = 0, sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t v = ws[q];
+        pre += q < w ? v : 0u;
+        sum += v;
     }
-    uint32_t run = part[t] - sum;
-    for (int64_t i = b0; i < b1; ++i) {
-        const uint32_t c = cnt[i];
-        cnt[i] = run;
-        run += c;
+    __syncthreads();  // ws is free again
+    *all = sum;
+    return pre + x - c;
+}
+
+// Workgroup d: the counts cnt[d nblk + b] of digit d in place as exclusive
+// offsets over the blocks b (256 blocks per step, coalesced), and the
+// digit's total in tot[d].
+__global__ __launch_bounds__(256) void k_sort_rowscan(uint32_t *cnt, int64_t nblk, uint32_t *tot) {
+    __shared__ uint32_t ws[4];
+    uint32_t *row = cnt + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int64_t i0 = 0; i0 < nblk; i0 += 256) {
+        const int64_t i = i0 + threadIdx.x;
+        const uint32_t c = i < nblk ? row[i] : 0u;
+        uint32_t all;
+        const uint32_t pre = block_excl_scan256(c, ws, &all);
+        if (i < nblk) row[i] = carry + pre;
+        carry += all;
     }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(256) void k_sort_scatter(const unsigned long long *__restrict__ in,
                                                       unsigned long long *__restrict__ out,
                                                       int64_t n, int shift, int64_t nblk,
-                                                      const uint32_t *__restrict__ off) {
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint32_t *__restrict__ tot) {
     __shared__ uint32_t base[256];    // next place of each digit for this block
     __shared__ uint32_t wc[4][256];   // per-wavefront digit counts of the round
+    __shared__ uint32_t ws[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t b = blockIdx.x;
-    base[t] = off[(int64_t)t * nblk + b];
+    uint32_t all;
+    base[t] = off[(int64_t)t * nblk + b] + block_excl_scan256(tot[t], ws, &all);
     for (int q = 0; q < 4; ++q) wc[q][t] = 0;
     __syncthreads();
     const unsigned long long below = (1ull << lane) - 1;
@@ -334,7 +355,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const unsigned long long *
 }
 
 // Sorts p[0..n) (doubles) ascending; tmp holds n doubles, cnt 256
-// sort_blocks(n) counts.  The sorted values end in p.
+// (sort_blocks(n) + 1) counts (the last 256: the digits' totals).  The
+// sorted values end in p.
 hipError_t sort_doubles(double *p, double *tmp, int64_t n, uint32_t *cnt, hipStream_t st) {
     if (n <= 1) return hipSuccess;
     const int64_t nblk = sort_blocks(n);
@@ -344,8 +366,9 @@ hipError_t sort_doubles(double *p, double *tmp, int64_t n, uint32_t *cnt, hipStr
     k_sort_encode<<<g256, 256, 0, st>>>(p, n);
     for (int shift = 0; shift < 64; shift += 8) {
         k_sort_hist<<<(unsigned)nblk, 256, 0, st>>>(a, n, shift, nblk, cnt);
-        k_sort_scan<<<1, 1024, 0, st>>>(cnt, 256 * nblk);
-        k_sort_scatter<<<(unsigned)nblk, 256, 0, st>>>(a, b, n, shift, nblk, cnt);
+        k_sort_rowscan<<<256, 256, 0, st>>>(cnt, nblk, cnt + 256 * nblk);
+        k_sort_scatter<<<(unsigned)nblk, 256, 0, st>>>(a, b, n, shift, nblk, cnt,
+                                                     cnt + 256 * nblk);
         std::swap(a, b);
     }
     // eight passes: the sorted codes are back in p
