@@ -677,8 +677,8 @@ def target_point(args, ch, torch, workloads):
             "brute_force_ms": bt * 1e3, "speedup": bt / dt,
             "rel_err": abs(eta - exact) / exact, "eta": eta, "CH": exact,
             "stages_ms": stages,
-            "roofline": {"kernel": "exact pass over the T draws (split tables, matrix-core "
-                                   "record kernel, resolve, rescans)",
+            "roofline": {"kernel": "exact pass over the T draws (the draws' split table, "
+                                   "matrix-core record kernel, resolve, rescans)",
                          "bound": work["bound"], "achieved": achieved, "peak": work["peak"],
                          "unit": work["unit"], "frac": achieved / work["peak"],
                          "kernel_ms": kms}}
@@ -815,8 +815,9 @@ def main():
     lam = float(aux["D"].item())
 
     # roofline of the exact pass over the draws (stage 4 -> 5: for l2 the
-    # split tables, the record pass on the matrix cores and the per-draw
-    # resolve kernel)
+    # draws' split table, the record pass on the matrix cores and the
+    # per-draw resolve kernel; B's split table is written by the kernel that
+    # hashes B, in the bucket_B stage)
     work = algorithmic_sample_pass(metric, T, n_b, d)
     kernel_ms = stages_ms["exact_pass"]
     achieved = work["ops"] / (kernel_ms * 1e-3) / 1e12
@@ -826,8 +827,9 @@ def main():
                 "traffic": measured_traffic(args.workload, kernel_ms), "kernel_ms": kernel_ms,
                 "algorithmic": work["note"]}
     if "products" in work:
-        roofline["kernel"] = ("k_split_rows + k_nnmin_l2_split record pass + k_split_resolve "
-                              "(exact pass over the T draws)")
+        roofline["kernel"] = ("k_split_rows of the draws + k_nnmin_l2_split record pass + "
+                              "k_split_resolve (exact pass over the T draws; B's split table "
+                              "is written while B is hashed, in bucket_B)")
         roofline["mfma_dtype"] = "bf16"
         roofline["frac_of_split_ceiling"] = achieved * work["products"] / work["peak"]
 

@@ -119,10 +119,11 @@ typedef struct chamfer_aux {
      * 1 calibration and tables done, 2 B bucketed, 3 CrudeNN done (D_a),
      * 4 weights and draws done, 5 exact pass over the draws done, 6 end.
      * Stage 4->5 is the nearest-neighbour pass over the draws: for l2 with
-     * 12 <= d <= 256 the BF16 split tables of B and of the draws, the
-     * matrix-core record kernel, the per-draw resolve kernel and, when B's
-     * chunks are longer than 512 rows, the rescan kernel; otherwise one
-     * vector-ALU kernel. */
+     * 12 <= d <= 256 the BF16 split table of the draws, the matrix-core
+     * record kernel, the per-draw resolve kernel and, when B's chunks are
+     * longer than 512 rows, the rescan kernel (B's split table is written
+     * in stage 1->2 by the kernel that hashes B, or in stage 4->5 for the
+     * uniform-sampling baseline); otherwise one vector-ALU kernel. */
     void **stage_events;
 } chamfer_aux;
 

@@ -268,7 +268,10 @@ hipError_t mark(void **ev, int i, hipStream_t st) {
 // l2 exact pass).
 int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
                int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,
-               float *nb2 = nullptr) {
+               float *nb2 = nullptr, uint16_t *bsplit = nullptr) {
+    // bsplit (l2 only, may be null): B's split table for the exact pass,
+    // written by the kernel that hashes B (B is read once for both)
+    const int sdp = bsplit ? split_dpad(pl.d) : 0;
     CH_TRY(mark(ev, 0, st));
     const int W = pl.window;
     int rc = hash_prologue(pl, A, B, seed, ws, st);
@@ -289,14 +292,16 @@ int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, fl
             if (r == 0) CH_TRY(mark(ev, 1, st));
             CH_TRY(launch_hash(5, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke, lohi, emb, zf,
                                mt, nullptr, pl.log2cap, pw.keys, nullptr, nullptr, nullptr,
-                               r == 0 ? nb2 : nullptr, p, 1, 0, st));
+                               r == 0 ? nb2 : nullptr, p, 1, 0, st, r == 0 ? bsplit : nullptr,
+                               sdp));
             CH_TRY(launch_part_build(pw, pl.nB, pl.L, pl.log2cap, tables, st));
         } else {
             CH_TRY(launch_tables_empty(tables, pl.L, pl.log2cap, W, st));
             if (r == 0) CH_TRY(mark(ev, 1, st));
             CH_TRY(launch_hash(W == 1 ? 0 : 3, B, pl.nB, B, pl.nB, pl.d, pl.metric, pl.L, pl.ke,
                                lohi, emb, zf, mt, tables, pl.log2cap, nullptr, nullptr, nullptr,
-                               nullptr, r == 0 ? nb2 : nullptr, p, W, 0, st));
+                               nullptr, r == 0 ? nb2 : nullptr, p, W, 0, st,
+                               r == 0 ? bsplit : nullptr, sdp));
         }
         if (r == 0) CH_TRY(mark(ev, 2, st));
         const int flags = (r > 0 ? kProbeMerge : 0) | (r == pl.reps - 1 ? kProbeLast : 0);
@@ -672,7 +677,7 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
         CH_TRY(mark(ev, 3, st));
     } else {
         int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
-        if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2))) return rc;
+        if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2, bsplit))) return rc;
     }
     uint64_t *P = at<uint64_t>(ws, pl.off_P);
     int32_t *idx = at<int32_t>(ws, pl.off_idx);
@@ -680,11 +685,11 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
     CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
     CH_TRY(mark(ev, 4, st));
-    // the split tables of B and of the draws (part of the exact pass),
-    // written after the hash tables are done with (they would evict them
-    // from the last-level cache) and just before their reader
+    // the split table of the draws (part of the exact pass); B's was written
+    // while B was hashed, except for the uniform baseline, which does not
+    // hash B
     if (bsplit) {
-        CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
+        if (pl.sampling == CHAMFER_UNIFORM) CH_TRY(launch_split_rows(B, n_B, d, bsplit, p, st));
         CH_TRY(launch_split_queries(A, idx, pl.T, d, at<uint16_t>(ws, pl.off_xsplit),
                                     at<float>(ws, pl.off_xn2), p, st));
     }

@@ -651,13 +651,49 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t 
 // first hit (or once another wavefront has hit at a finer scale); the first
 // colliding scale is the smallest over the four.
 // EC: coordinates of x staged per pass of the l2 embedding.
+// B's split table for the l2 exact pass, written from the staged rows while B
+// is hashed (B is read once): row r of the table holds h = bf16(x_k) for
+// k < split_dp, then m = bf16(x_k - h) (zero past d), as the separate split
+// pass writes them.  Coordinates [k0, k0 + kc) of the tile's np points are
+// staged at xs[point * ld + k - k0]; the last chunk also writes the padding
+// [k0 + kc, split_dp).  Thread t takes 16 consecutive coordinates of point
+// t / 4 per 64-coordinate step.
+__device__ __forceinline__ void split_staged(const float *xs, int ld, int64_t p0, int np, int k0,
+                                             int kc, bool last, int split_dp, uint16_t *out) {
+    const int pp = threadIdx.x >> 2;
+    if (pp >= np) return;
+    uint16_t *row = out + (size_t)(p0 + pp) * (2 * split_dp);
+    const int kend = last ? split_dp : k0 + kc;
+    for (int c = k0 + (threadIdx.x & 3) * 16; c < kend; c += 64) {
+        uint32_t hw[8], mw[8];
+#pragma unroll
+        for (int e = 0; e < 16; e += 2) {
+            const int a = c + e - k0;
+            const float v0 = a < kc ? xs[pp * ld + a] : 0.0f;
+            const float v1 = a + 1 < kc ? xs[pp * ld + a + 1] : 0.0f;
+            uint32_t h0, m0, h1, m1;
+            split2(v0, h0, m0);
+            split2(v1, h1, m1);
+            hw[e / 2] = h0 | (h1 << 16);
+            mw[e / 2] = m0 | (m1 << 16);
+        }
+        uint4 *hd = reinterpret_cast<uint4 *>(row + c);
+        uint4 *md = reinterpret_cast<uint4 *>(row + split_dp + c);
+        hd[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        hd[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+        md[0] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
+        md[1] = make_uint4(mw[4], mw[5], mw[6], mw[7]);
+    }
+}
+
 template <int METRIC, int MODE, int KE, bool YG, int EC = kEmbedChunk>
 __device__ __forceinline__ void hash_tile(
     const float *__restrict__ X, int64_t n, const float *__restrict__ Bpts, int d, int L,
     const uint32_t *__restrict__ lohi, const int8_t *__restrict__ embed,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags, Blk blk) {
+    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags, Blk blk,
+    uint16_t *split_out = nullptr, int split_dp = 0) {
     extern __shared__ float smem[];
     __shared__ float los[EC > kEmbedChunk ? EC : kEmbedChunk];
     __shared__ int hit_scale[kTile];
@@ -729,6 +765,8 @@ __device__ __forceinline__ void hash_tile(
                     const float xraw = xs[lane * (ECM + 1) + k];
                     n2 = fmaf(xraw, xraw, n2);
                 }
+            if ((MODE == 0 || MODE == 3 || MODE == 5) && split_out != nullptr)
+                split_staged(xs, ECM + 1, p0, np, k0, kc, ks == nks - 1, split_dp, split_out);
             // A: 16 coordinates k0 + 16 g4 + e of point 16 wave + i16, as the
             // three bytes of u, each offset by -128 (xor 0x80); four
             // coordinates at a time give one dword of each byte's operand
@@ -984,10 +1022,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WAVES)
     const uint32_t *__restrict__ lohi, const int8_t *__restrict__ embed,
     const float *__restrict__ zfrac, const uint64_t *__restrict__ mult, Bucket *tables,
     int log2cap, unsigned long long *keys_out, float *D_out, int32_t *nn_out,
-    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags) {
+    int32_t *scale_out, float *nb2_out, DevParams *p, int64_t nB, int W, int flags,
+    uint16_t *split_out, int split_dp) {
     hash_tile<METRIC, MODE, KE, YG, EC>(X, n, Bpts, d, L, lohi, embed, zfrac, mult, tables,
                                         log2cap, keys_out, D_out, nn_out, scale_out, nb2_out, p,
-                                        nB, W, flags, grid_blk());
+                                        nB, W, flags, grid_blk(), split_out, split_dp);
 }
 
 int64_t hash_blocks(int64_t n) { return (n + kTile - 1) / kTile; }
@@ -1005,11 +1044,12 @@ static hipError_t launch_hash_t(int mode, const float *X, int64_t n, const float
                                 const int8_t *embed, const float *zfrac, const uint64_t *mult,
                                 Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                                 int32_t *nn_out, int32_t *scale_out, float *nb2_out,
-                                DevParams *p, int W, int flags, hipStream_t st) {
+                                DevParams *p, int W, int flags, hipStream_t st,
+                                uint16_t *split_out, int split_dp) {
     const unsigned blocks = (unsigned)hash_blocks(n);
     auto *ko = reinterpret_cast<unsigned long long *>(keys_out);
 #define CH_KARGS X, n, Bpts, d, L, lohi, embed, zfrac, mult, tables, log2cap, ko, D_out, nn_out, \
-                 scale_out, nb2_out, p, nB, W, flags
+                 scale_out, nb2_out, p, nB, W, flags, split_out, split_dp
     // Four wavefronts per SIMD for every mode: measured against six and
     // eight (l2, 10^5 points: probe 90, 117 and 141 us; keys and insert
     // within noise or slower).
@@ -1054,11 +1094,17 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
                        const int8_t *embed, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
-                       int W, int flags, hipStream_t st) {
+                       int W, int flags, hipStream_t st, uint16_t *split_out, int split_dp) {
     if (n <= 0) return hipSuccess;
     if (W < 1 || W > kMaxWindow) return hipErrorInvalidValue;
+    // the split table is written from the l2 embedding's staged rows (B's
+    // hashing modes only; split_dp a multiple of 64 at or above d, or 32)
+    if (split_out != nullptr &&
+        (metric != CHAMFER_L2 || !(mode == 0 || mode == 3 || mode == 5) || split_dp < d ||
+         (split_dp % 64 != 0 && split_dp != 32)))
+        return hipErrorInvalidValue;
 #define CH_ARGS mode, X, n, Bpts, nB, d, L, lohi, embed, zfrac, mult, tables, log2cap, keys_out, \
-                D_out, nn_out, scale_out, nb2_out, p, W, flags, st
+                D_out, nn_out, scale_out, nb2_out, p, W, flags, st, split_out, split_dp
     if (metric == CHAMFER_L1) {
         // the window probe also keeps W ints per lane in LDS
         const int room = mode == 4 ? kMaxLdsL1Dim - W : kMaxLdsL1Dim;

@@ -231,6 +231,25 @@ __device__ __forceinline__ uint4 ld(const CH_RO uint4 *p) {
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// Padded dimension of the split tables of the l2 exact pass (12 <= d <= 256).
+__host__ __device__ inline int split_dpad(int d) {
+    return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
+}
+
+// BF16 bits of f, round to nearest even (f finite or infinite).
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// The two-term split of the l2 exact pass: (h, m) of v as BF16 bit patterns,
+// h = bf16(v), m = bf16(v - h) (v - h is exact in float32).
+__device__ __forceinline__ void split2(float v, uint32_t &h, uint32_t &m) {
+    h = bf16_rne_bits(v);
+    m = bf16_rne_bits(v - __uint_as_float(h << 16));
+}
+
 // Canonical float32 distance accumulator between rows a and b: k ascending,
 // one rounding per operation; l1: acc + |a_k - b_k|, l2: fma(t, t, acc) with
 // t = a_k - b_k (the caller takes the square root for l2).  Loads are issued
@@ -355,7 +374,8 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
                        const int8_t *embed, const float *zfrac, const uint64_t *mult,
                        Bucket *tables, int log2cap, uint64_t *keys_out, float *D_out,
                        int32_t *nn_out, int32_t *scale_out, float *nb2_out, DevParams *p,
-                       int W, int flags, hipStream_t st);
+                       int W, int flags, hipStream_t st, uint16_t *split_out = nullptr,
+                       int split_dp = 0);
 // Bytes of the tables of L scales of 2^log2cap buckets with window W.
 size_t table_bytes(int L, int log2cap, int W);
 // The partitioned build of the W = 1 tables (no global atomics): keys of B

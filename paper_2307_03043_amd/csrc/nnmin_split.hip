@@ -84,10 +84,6 @@ constexpr int64_t split_target(int dp) { return dp <= 64 ? 2304 : dp <= 128 ? 46
 // exact rescans, each reading the whole chunk) are frequent.
 constexpr int64_t kSplitManyQueries = 16384;
 
-__host__ __device__ inline int split_dpad(int d) {
-    return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
-}
-
 // Certificate constants of a launch and the bound E of one query (see the
 // header): |computed score - (|b|^2 - 2 x.b)| <= E for every row b, given
 // the float32 |x|^2 of the query and the float32 maximum of |b|^2 over B.
@@ -115,18 +111,6 @@ __host__ __device__ inline double split_score_bound(int d, int dp, int terms, do
 }
 
 size_t split_table_bytes(int64_t nB, int d) { return (size_t)nB * split_dpad(d) * 4; }
-
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-
-// (h, m) of v as BF16 bit patterns.
-__device__ __forceinline__ void split2(float v, uint32_t &h, uint32_t &m) {
-    h = bf16_rne_bits(v);
-    m = bf16_rne_bits(v - __uint_as_float(h << 16));
-}
 
 __device__ __forceinline__ unsigned long long pack_sp(float v, int64_t b) {
     return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(uint32_t)b;
