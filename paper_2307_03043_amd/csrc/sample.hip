@@ -145,15 +145,28 @@ hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums
 // Draw l: word 0 of Philox4x64-10 at counter (l, attempt, SAMPLE, 0), key
 // (seed, 0); Lemire: m = x W, reject while (m mod 2^64) < (2^64 - W) mod W,
 // u = m >> 64; idx = min{a : P_a > u}.  Also resets the nearest-neighbour
-// slot of the draw.
+// slot of the draw.  The search first finds, in LDS, the first of kFences
+// evenly spaced fences P[(i + 1) S - 1] (S = ceil(n_A / kFences), the last
+// one P[n_A - 1] = W > u) above u, then searches the S entries it closes in
+// memory: the same index with log2 S dependent loads instead of log2 n_A.
+// Every thread of the workgroup must call it (one barrier).
+constexpr int kFences = 1024;
+
 __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *__restrict__ P,
                                        int64_t nA, int64_t T, int32_t *idx,
                                        unsigned long long *best, const DevParams *p, Blk blk) {
+    __shared__ unsigned long long fence[kFences];
     const int64_t l = blk.id * blockDim.x + threadIdx.x;
+    const uint64_t W = p->W;
+    const bool ok = p->status == CHAMFER_OK && W != 0;  // uniform
+    const int64_t S = (nA + kFences - 1) / kFences;
+    if (ok)
+        for (int i = threadIdx.x; i < kFences; i += blockDim.x)
+            fence[i] = ro(P)[min((int64_t)(i + 1) * S - 1, nA - 1)];
+    __syncthreads();
     if (l >= T) return;
     best[l] = ~0ull;
-    const uint64_t W = p->W;
-    if (p->status != CHAMFER_OK || W == 0) {
+    if (!ok) {
         idx[l] = 0;
         return;
     }
@@ -169,7 +182,16 @@ __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *
         }
         break;
     }
-    int64_t a = 0, b = nA - 1;
+    int f0 = 0, f1 = kFences - 1;
+    while (f0 < f1) {
+        const int mid = (f0 + f1) >> 1;
+        if (fence[mid] > u)
+            f1 = mid;
+        else
+            f0 = mid + 1;
+    }
+    // P[f0 S - 1] <= u < P[min((f0 + 1) S, n_A) - 1]
+    int64_t a = (int64_t)f0 * S, b = min((int64_t)(f0 + 1) * S - 1, nA - 1);
     while (a < b) {
         const int64_t mid = a + ((b - a) >> 1);
         if (ro(P)[mid] > u)
@@ -210,6 +232,9 @@ __device__ __forceinline__ void estimate_final(const unsigned long long *__restr
     double acc = 0.0;
     // kG terms per thread per round: their loads (best, idx, then D[idx])
     // are issued together, then the terms are added in index order
+    // (all loads in bounds and unconditional, so each group of them is in
+    // flight together: positions past T read draw T - 1, whose idx is a row
+    // of A like every draw's)
     constexpr int kG = 8;
     for (int64_t l0 = t; l0 < T; l0 += 256 * kG) {
         unsigned long long bv[kG];
@@ -217,15 +242,12 @@ __device__ __forceinline__ void estimate_final(const unsigned long long *__restr
         float dv[kG];
 #pragma unroll
         for (int g = 0; g < kG; ++g) {
-            const int64_t l = l0 + (int64_t)g * 256;
-            bv[g] = l < T ? ro(best)[l] : 0ull;
-            ix[g] = l < T ? ro(idx)[l] : 0;
+            const int64_t l = min(l0 + (int64_t)g * 256, T - 1);
+            bv[g] = ro(best)[l];
+            ix[g] = ro(idx)[l];
         }
 #pragma unroll
-        for (int g = 0; g < kG; ++g) {
-            const int64_t l = l0 + (int64_t)g * 256;
-            dv[g] = (l < T && status == CHAMFER_OK && W != 0) ? ro(D)[ix[g]] : 0.0f;
-        }
+        for (int g = 0; g < kG; ++g) dv[g] = ro(D)[ix[g]];
 #pragma unroll
         for (int g = 0; g < kG; ++g) {
             const int64_t l = l0 + (int64_t)g * 256;
