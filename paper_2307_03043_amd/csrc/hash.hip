@@ -1268,6 +1268,80 @@ __global__ __launch_bounds__(256) void k_part_scan(int64_t nB, int log2cap, int6
     for (int g = threadIdx.x; g < R; g += 256) bins[((size_t)i * R + g) * 3 + 0] = tot[g];
 }
 
+// The same for large partitions (many blocks and regions), in two launches:
+// k_part_scan_rows takes 64 regions of one scale per workgroup, each
+// wavefront a contiguous quarter of the blocks (loads coalesced over the
+// regions, eight in flight per lane), and writes the regions' totals;
+// k_part_base scans the totals of each scale into the regions' first
+// entries and clears the spill flag.
+__global__ __launch_bounds__(256) void k_part_scan_rows(int log2cap, int64_t nblk,
+                                                        uint32_t *offs, uint32_t *bins) {
+    __shared__ uint32_t part[4][64];
+    const int R = (int)part_regions(log2cap);
+    const int gpb = (R + 63) / 64;  // workgroups per scale
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = blockIdx.x / gpb;
+    const int g = (int)(blockIdx.x % gpb) * 64 + lane;
+    const bool live = g < R;
+    const int64_t q = (nblk + 3) / 4;
+    const int64_t j0 = min(nblk, w * q), j1 = min(nblk, j0 + q);
+    uint32_t *o = offs + (size_t)i * nblk * R + g;
+    uint32_t sum = 0;
+    if (live) {
+        int64_t j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) c[e] = o[(j + e) * R];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sum += c[e];
+        }
+        for (; j < j1; ++j) sum += o[j * R];
+    }
+    part[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, tot = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t x = part[v][lane];
+        run += v < w ? x : 0u;
+        tot += x;
+    }
+    if (!live) return;
+    int64_t j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c[e] = o[(j + e) * R];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            o[(j + e) * R] = run;
+            run += c[e];
+        }
+    }
+    for (; j < j1; ++j) {
+        const uint32_t c = o[j * R];
+        o[j * R] = run;
+        run += c;
+    }
+    if (w == 0) {
+        bins[((size_t)i * R + g) * 3 + 1] = tot;
+        bins[((size_t)i * R + g) * 3 + 2] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_part_base(int log2cap, uint32_t *bins,
+                                                   uint32_t *spilled) {
+    __shared__ uint32_t tot[kMaxRegions + 256];
+    const int R = (int)part_regions(log2cap);
+    const int64_t i = blockIdx.x;
+    if (i == 0 && threadIdx.x == 0) *spilled = 0;  // read after the region builds
+    for (int g = threadIdx.x; g < R; g += 256) tot[g] = bins[((size_t)i * R + g) * 3 + 1];
+    __syncthreads();
+    block_exclusive_scan(tot, R, tot + R);
+    for (int g = threadIdx.x; g < R; g += 256) bins[((size_t)i * R + g) * 3 + 0] = tot[g];
+}
+
 // The block's (key, b) pairs grouped by region: counted in LDS, placed in
 // LDS in region order, then written so that consecutive threads write
 // consecutive entries of a region's run.
@@ -1435,6 +1509,11 @@ __global__ __launch_bounds__(256) void k_spill_insert(const uint32_t *__restrict
     }
 }
 
+// Largest count table (blocks x regions) of one scale that one workgroup
+// scans (10^5 points: 25 x 128); above it the two-launch scan (10^6 points,
+// 245 x 1024: 88 us in one workgroup per scale).
+constexpr int64_t kPartScanOneGroup = 16384;
+
 hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, Bucket *tables,
                              hipStream_t st) {
     if (nB <= 0 || L <= 0) return hipSuccess;
@@ -1443,8 +1522,14 @@ hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, 
     const int S = 1 << region_bits(log2cap);
     k_part_hist<<<(unsigned)(L * nblk), 256, (size_t)R * sizeof(uint32_t), st>>>(
         w.keys, nB, log2cap, nblk, w.offs);
-    k_part_scan<<<(unsigned)L, 256, ((size_t)R + 256) * sizeof(uint32_t), st>>>(
-        nB, log2cap, nblk, w.offs, w.bins, w.spilled);
+    if (nblk * R <= kPartScanOneGroup) {
+        k_part_scan<<<(unsigned)L, 256, ((size_t)R + 256) * sizeof(uint32_t), st>>>(
+            nB, log2cap, nblk, w.offs, w.bins, w.spilled);
+    } else {
+        k_part_scan_rows<<<(unsigned)(L * ((R + 63) / 64)), 256, 0, st>>>(log2cap, nblk, w.offs,
+                                                                         w.bins);
+        k_part_base<<<(unsigned)L, 256, 0, st>>>(log2cap, w.bins, w.spilled);
+    }
     const size_t lds_sc = (2 * (size_t)R + 256) * sizeof(uint32_t) + (size_t)kPartBlock * 12;
     k_part_scatter<<<(unsigned)(L * nblk), 256, lds_sc, st>>>(w.keys, nB, log2cap, nblk, w.offs,
                                                               w.bins, w.entries);
