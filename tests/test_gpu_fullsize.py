@@ -203,3 +203,30 @@ def test_fullsize_reduction(ch, orc, name):
     plain = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L, with_aux=False)["eta"]
     red = ch.chamfer_estimate(At, Bt, metric, eps, T, 1, n_scales=L, reduction=1)["eta"]
     assert float(plain.item()) == float(red.item())
+
+
+def test_global_insert_tables_with_split(ch, orc):
+    """Above 2^20 points of B the tables are built by the global insert
+    (the partitioned build's regions would exceed its limit) and the same
+    kernel writes B's split table for the exact pass: CrudeNN bits, the
+    draws and their canonical minima against the oracle (l2, |A| = 2000,
+    |B| = 2^20 + 7, d = 16)."""
+    print("[case] global-insert tables with the split table", flush=True)
+    rng = np.random.default_rng(21)
+    centres = rng.uniform(-10, 10, (64, 16))
+    n_b = (1 << 20) + 7
+    B = (centres[rng.integers(0, 64, n_b)] + rng.standard_normal((n_b, 16))).astype(np.float32)
+    A = (centres[rng.integers(0, 64, 2000)] + rng.standard_normal((2000, 16))).astype(np.float32)
+    out = ch.chamfer_estimate(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), 2, 0.2,
+                              300, 5)
+    torch.cuda.synchronize()
+    ref = orc.chamfer_estimate(A, B, 2, 0.2, 300, 5)
+    c = ref["crude"]
+    assert np.array_equal(out["crude_D"].cpu().numpy().view(np.uint32), c["D"].view(np.uint32))
+    assert np.array_equal(out["crude_nn"].cpu().numpy(), c["nn"])
+    assert np.array_equal(out["crude_scale"].cpu().numpy(), c["scale"])
+    assert np.array_equal(out["sample_idx"].cpu().numpy(), ref["idx"])
+    m32, a32 = orc.nn_f32(A, B, 2, rows=ref["idx"])
+    assert np.array_equal(out["sample_nn"].cpu().numpy(), a32)
+    assert np.array_equal(out["sample_min"].cpu().numpy().view(np.uint32), m32.view(np.uint32))
+    assert float(out["eta"].item()) == pytest.approx(ref["eta"], rel=REL)
