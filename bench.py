@@ -731,13 +731,23 @@ def main():
     import torch
 
     if args.copy_probe:
+        # a plain device copy: calibrates the traffic counters, and its rate
+        # (bytes read + written per second) is the HBM bandwidth this box
+        # reaches with a library kernel
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(args.steps):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n * 4, "copies": args.steps}))
+        ms = e0.elapsed_time(e1) / max(args.steps, 1)
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": args.steps, "ms_per_copy": ms,
+                          "hbm_tb_per_s": 2 * n * 4 / (ms * 1e-3) / 1e12}))
         return
 
     import paper_2307_03043_amd as ch
