@@ -3,13 +3,16 @@
 // multipliers, the open-addressing bucket tables of B, and the probe of A
 // that yields the first colliding scale, the candidate b and D_a.
 //
-// Layout: one wavefront (64 lanes) per tile of 64 consecutive points.  The
-// tile's hashed coordinates are staged in LDS with an odd row stride, so the
+// Layout: one workgroup of four wavefronts per tile of 64 consecutive
+// points, one point per lane; the wavefronts split the scales.  The tile's
+// hashed coordinates are staged in LDS with an odd row stride, so the
 // per-lane reads of row p, coordinate k hit 64 distinct banks.  Shifts and
 // multipliers are indexed only by the (wave-uniform) scale and coordinate,
-// so they are read through the scalar cache.  Keys are never written to HBM
-// on the estimator path: B's keys go straight into the tables and A's keys
-// are recomputed scale by scale until the first hit.
+// so they are read through the scalar cache.  B's keys are written once,
+// [L][n_B], and its tables built from them region by region in LDS (the
+// partitioned build below; the serving path and the window tables insert
+// directly); A's keys are never written: they are recomputed scale by
+// scale until the first hit.
 #include <climits>
 
 #include "internal.h"

@@ -412,8 +412,9 @@ hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const f
                         hipStream_t st);
 // The l2 exact pass on the BF16 matrix cores (12 <= d <= 256) with a two-term
 // split of every coordinate: launch_rownorm (or the hash of B) fills nb2 and
-// p->b2max_bits, launch_split_rows the split table of B (split_table_bytes),
-// then launch_nnmin_split returns the canonical float32 minima.
+// p->b2max_bits, launch_split_rows (or the hash of B) the split table of B
+// (split_table_bytes), then launch_nnmin_split returns the canonical float32
+// minima.
 bool mfma_supported(int d, int metric);
 hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevParams *p,
                           hipStream_t st);
