@@ -579,56 +579,71 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kEmbedChunk = 64;  // coordinates of x - lo staged per pass (l2), by default
 
 // Copy rows [np][kc] of the tile (row stride d, from column k0) into LDS
-// rows of stride ldr as f(value, k): each thread issues a batch of loads
-// before it stores any of them, so a tile costs a few memory round trips
-// instead of one per element.
-template <int BATCH, class F>
+// rows of stride ldr, less lo_k (the ordered-int lower corner) when lo is
+// given: each thread issues a batch of loads before it stores any of them,
+// so a tile costs a few memory round trips instead of one per element.  The
+// loads are in bounds and unconditional (rows past np and elements past the
+// tile read its last element, and are not stored), so the batch is in flight
+// at once; in the float4 form a thread always takes the same quad of
+// columns, whose lo it loads once, first.
+template <int BATCH>
 __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t p0, int np, int d,
-                                           int k0, int kc, float *dst, int ldr, F f) {
+                                           int k0, int kc, float *dst, int ldr,
+                                           const uint32_t *__restrict__ lo) {
     const auto *Xr = ro(X);
     if (kc == 64 && (d & 3) == 0 && (k0 & 3) == 0 &&
         (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
         // 64 coordinates per row as 16 float4 loads (row r, quad c of
-        // element e: r = e / 16, c = e % 16), four per thread in one batch
+        // element e: r = e / 16, c = e % 16 = thread % 16), four per thread
+        // in one batch
         const auto *X4 = reinterpret_cast<const CH_RO float4 *>(Xr);
+        constexpr int kRowsPerPass = kThreads / 16;
+        const int c = (int)threadIdx.x & 15, r0 = (int)threadIdx.x >> 4;
+        // without lo the quad is read from X itself and not used
+        const bool sub = lo != nullptr;
+        const auto *lr = sub ? ro(lo) + k0 + 4 * c : ro(reinterpret_cast<const uint32_t *>(X));
+        const uint32_t l0 = lr[0], l1 = lr[1], l2 = lr[2], l3 = lr[3];
         float4 v[kTile * 16 / kThreads];
 #pragma unroll
         for (int i = 0; i < kTile * 16 / kThreads; ++i) {
-            const int e = i * kThreads + (int)threadIdx.x, r = e >> 4, c = e & 15;
-            v[i] = r < np ? ld(X4 + (((p0 + r) * d + k0) >> 2) + c)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int r = min(i * kRowsPerPass + r0, np - 1);
+            v[i] = ld(X4 + (((p0 + r) * d + k0) >> 2) + c);
         }
+        const float4 off = sub ? make_float4(ordered_to_float(l0), ordered_to_float(l1),
+                                             ordered_to_float(l2), ordered_to_float(l3))
+                               : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
         for (int i = 0; i < kTile * 16 / kThreads; ++i) {
-            const int e = i * kThreads + (int)threadIdx.x, r = e >> 4, c = e & 15;
+            const int r = i * kRowsPerPass + r0;
             if (r < np) {
                 float *o = dst + r * ldr + 4 * c;
-                o[0] = f(v[i].x, 4 * c);
-                o[1] = f(v[i].y, 4 * c + 1);
-                o[2] = f(v[i].z, 4 * c + 2);
-                o[3] = f(v[i].w, 4 * c + 3);
+                o[0] = v[i].x - off.x;
+                o[1] = v[i].y - off.y;
+                o[2] = v[i].z - off.z;
+                o[3] = v[i].w - off.w;
             }
         }
         return;
     }
     const int total = np * kc;
+    const bool sub = lo != nullptr;
+    const auto *lr = sub ? ro(lo) + k0 : ro(reinterpret_cast<const uint32_t *>(X));
     for (int base = 0; base < total; base += BATCH * kThreads) {
         float v[BATCH];
+        uint32_t o[BATCH];
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
-            const int e = base + i * kThreads + (int)threadIdx.x;
-            v[i] = 0.0f;
-            if (e < total) {
-                const int r = e / kc, k = e - r * kc;
-                v[i] = Xr[(p0 + r) * d + k0 + k];
-            }
+            const int e = min(base + i * kThreads + (int)threadIdx.x, total - 1);
+            const int r = e / kc, k = e - r * kc;
+            v[i] = Xr[(p0 + r) * d + k0 + k];
+            o[i] = lr[sub ? k : 0];
         }
 #pragma unroll
         for (int i = 0; i < BATCH; ++i) {
             const int e = base + i * kThreads + (int)threadIdx.x;
             if (e < total) {
                 const int r = e / kc, k = e - r * kc;
-                dst[r * ldr + k] = f(v[i], k);
+                dst[r * ldr + k] = v[i] - (sub ? ordered_to_float(o[i]) : 0.0f);
             }
         }
     }
@@ -726,9 +741,7 @@ __device__ __forceinline__ void hash_tile(
 
     if (METRIC == CHAMFER_L1) {
         if (!YG) {
-            const auto *lo = ro(lohi);
-            stage_rows<16>(X, p0, np, d, 0, d, ys, khp,
-                           [&](float v, int k) { return v - ordered_to_float(lo[k]); });
+            stage_rows<16>(X, p0, np, d, 0, d, ys, khp, lohi);
         }
     } else {
         // The quantised embedding: u_k = floor(min((x_k - lo_k) 2^(24 - e_top),
@@ -760,7 +773,7 @@ __device__ __forceinline__ void hash_tile(
             const int k0 = ks * ECM;
             const int kc = min(ECM, d - k0);
             __syncthreads();
-            stage_rows<16>(X, p0, np, d, k0, kc, xs, ECM + 1, [](float v, int) { return v; });
+            stage_rows<16>(X, p0, np, d, k0, kc, xs, ECM + 1, nullptr);
             if (tid < kc) los[tid] = ordered_to_float(ro(lohi)[k0 + tid]);
             __syncthreads();
             if (want_n2 && active)
@@ -1220,14 +1233,16 @@ __global__ __launch_bounds__(256) void k_part_hist(const uint64_t *__restrict__ 
     for (int g = threadIdx.x; g < R; g += 256) cnt[g] = 0;
     __syncthreads();
     const CH_RO uint64_t *kr = ro(keys) + i * nB;
-#pragma unroll 4
-    for (int t = 0; t < kPartBlock / 256; ++t) {
-        const int64_t e = j * kPartBlock + t * 256 + threadIdx.x;
-        if (e < nB) {
-            const unsigned long long key = kr[e];
-            if (key != kEmptyKey) atomicAdd(&cnt[key_region(key, log2cap)], 1u);
-        }
-    }
+    // all of the thread's keys are loaded (in bounds, unconditionally, so
+    // the loads are in flight together) before any is counted
+    constexpr int kPer = kPartBlock / 256;
+    unsigned long long k[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) k[t] = kr[min(j * kPartBlock + t * 256 + threadIdx.x, nB - 1)];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t)
+        if (j * kPartBlock + t * 256 + threadIdx.x < nB && k[t] != kEmptyKey)
+            atomicAdd(&cnt[key_region(k[t], log2cap)], 1u);
     __syncthreads();
     uint32_t *o = offs + (size_t)(i * nblk + j) * R;
     for (int g = threadIdx.x; g < R; g += 256) o[g] = cnt[g];
@@ -1366,10 +1381,13 @@ __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict
     constexpr int kPer = kPartBlock / 256;
     unsigned long long k[kPer];
     const CH_RO uint64_t *kr = ro(keys) + i * nB;
+    // loads first (in bounds, unconditional: in flight together), then the
+    // counts; keys past n_B become the empty key
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) k[t] = kr[min(j * kPartBlock + t * 256 + threadIdx.x, nB - 1)];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int64_t e = j * kPartBlock + t * 256 + threadIdx.x;
-        k[t] = e < nB ? kr[e] : kEmptyKey;
+        if (j * kPartBlock + t * 256 + threadIdx.x >= nB) k[t] = kEmptyKey;
         if (k[t] != kEmptyKey) atomicAdd(&cnt[key_region(k[t], log2cap)], 1u);
     }
     __syncthreads();
