@@ -230,3 +230,24 @@ def test_global_insert_tables_with_split(ch, orc):
     assert np.array_equal(out["sample_nn"].cpu().numpy(), a32)
     assert np.array_equal(out["sample_min"].cpu().numpy().view(np.uint32), m32.view(np.uint32))
     assert float(out["eta"].item()) == pytest.approx(ref["eta"], rel=REL)
+
+
+@pytest.mark.parametrize("metric,d", [(2, 100), (1, 40)])
+def test_probe_tile_distance_ragged(ch, orc, metric, d):
+    """Probe grids of 5000 tiles or more compute each point's candidate
+    distance with the whole workgroup (64-coordinate chunks through LDS);
+    a ragged last tile (37 points) and chunk widths that are not 64 (d = 100:
+    64 + 36; d = 40) against the oracle's CrudeNN bits."""
+    print(f"[case] probe tile distance metric={metric} d={d}", flush=True)
+    rng = np.random.default_rng(30 + d)
+    centres = rng.uniform(-20, 20, (200, d))
+    n_a, n_b = 5000 * 64 + 37, 20_000
+    A = (centres[rng.integers(0, 200, n_a)] + rng.standard_normal((n_a, d))).astype(np.float32)
+    B = (centres[rng.integers(0, 200, n_b)] + rng.standard_normal((n_b, d))).astype(np.float32)
+    out = ch.chamfer_estimate(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), metric,
+                              0.2, 300, 3, n_scales=18)
+    torch.cuda.synchronize()
+    c = orc.crude_nn(A, B, metric, 0.2, 3, n_scales=18)
+    assert np.array_equal(out["crude_scale"].cpu().numpy(), c["scale"])
+    assert np.array_equal(out["crude_nn"].cpu().numpy(), c["nn"])
+    assert np.array_equal(out["crude_D"].cpu().numpy().view(np.uint32), c["D"].view(np.uint32))
