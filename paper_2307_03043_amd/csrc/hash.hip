@@ -1588,6 +1588,9 @@ __global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB
         }
         __syncthreads();
     }
+    // an empty region skips the loop: the fingerprints below read slots that
+    // other threads initialised
+    __syncthreads();
     Bucket *out = tables + ((size_t)i << log2cap) + ((size_t)g << qb);
     uint8_t *ofp = table_fps(tables, L, log2cap, (int)i) + ((size_t)g << qb);
     for (int s = threadIdx.x; s < S; s += 256) {
