@@ -236,15 +236,23 @@ int hash_prologue(const Plan &pl, const float *A, const float *B, uint64_t seed,
                         at<uint64_t>(ws, pl.off_mult), nullptr, 0, st));
     if (pl.metric == CHAMFER_L2) {
         // The embedding matrix is drawn on the host (it needs log and cos in
-        // double precision) and uploaded transposed, [d][ke], from a buffer
-        // the next call overwrites: a captured copy would replay from it, so
-        // a capturing stream is refused.
+        // double precision) and uploaded in the hash kernels' operand layout
+        // from a buffer a later call may overwrite: a captured copy would
+        // replay from it, so a capturing stream is refused.  The buffer keeps
+        // the last (seed, d, k_e)'s matrix, which repeated calls reuse.
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         CH_TRY(hipStreamIsCapturing(st, &cs));
         if (cs != hipStreamCaptureStatusNone) return CHAMFER_EINVAL;
         thread_local std::vector<int8_t> zt;
-        zt.resize(embed_bytes(pl.d, pl.ke));
-        embedding_packed(seed, pl.d, pl.ke, zt.data());
+        thread_local uint64_t zt_seed = 0;
+        thread_local int zt_d = -1, zt_ke = -1;
+        if (zt_d != pl.d || zt_ke != pl.ke || zt_seed != seed) {
+            zt.resize(embed_bytes(pl.d, pl.ke));
+            embedding_packed(seed, pl.d, pl.ke, zt.data());
+            zt_seed = seed;
+            zt_d = pl.d;
+            zt_ke = pl.ke;
+        }
         CH_TRY(hipMemcpyAsync(at<int8_t>(ws, pl.off_embed), zt.data(), zt.size(),
                               hipMemcpyHostToDevice, st));
     }
