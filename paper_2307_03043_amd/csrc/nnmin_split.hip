@@ -554,6 +554,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // copy of the canonical distance in the kernel (unrolled over the K
 // records it would not fit the instruction cache).  K = 0 reads the
 // records from memory in each pass.
+// The rescans queued by a workgroup's four wavefronts (rq[0 .. *nrq), draw
+// slot << 24 | chunk): every wavefront takes pieces of 64 rows in turn and
+// merges the canonical minimum of each piece into slot_min of its draw.
+// xoff: this wavefront's draw row offset (row * d), or -1 without a draw.
+// Every wavefront of the workgroup calls it (two barriers); slot_min holds
+// the merged minima when it returns.
+__device__ __forceinline__ void resolve_rescans(const float *__restrict__ X,
+                                                const float *__restrict__ B, int64_t nB, int d,
+                                                int64_t chunk, const uint32_t *rq, const int *nrq,
+                                                unsigned long long *slot_min, int64_t *slot_x,
+                                                int wv, int lane, int64_t xoff) {
+    if (lane == 0) slot_x[wv] = xoff < 0 ? 0 : xoff;
+    __syncthreads();  // the queue, the row offsets and the minima are initialised
+    const int64_t P = (chunk + 63) / 64;
+    const int64_t total = (int64_t)*nrq * P;
+    for (int64_t id = wv; id < total; id += 4) {
+        const uint32_t e = rq[id / P];
+        const int ws = (int)(e >> 24);
+        const int64_t c = (int64_t)(e & 0xffffffu);
+        const int64_t b1 = min(nB, c * chunk + chunk);
+        const int64_t b = c * chunk + (id % P) * 64 + lane;
+        unsigned long long mm = ~0ull;
+        if (b < b1) mm = pack_sp(canon_acc<CHAMFER_L2, 16>(X + slot_x[ws], B + b * d, d), b);
+        for (int off = 32; off > 0; off >>= 1) mm = min(mm, (unsigned long long)__shfl_xor(mm, off));
+        if (lane == 0 && mm != ~0ull) atomicMin(&slot_min[ws], mm);
+    }
+    __syncthreads();  // every piece merged
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_split_resolve(
     const float *__restrict__ X, const int32_t *__restrict__ rows, int64_t nx,
@@ -561,11 +590,28 @@ __global__ __launch_bounds__(256) void k_split_resolve(
     int64_t chunk, int nchunk, const uint4 *__restrict__ rec, uint2 *__restrict__ redo,
     unsigned long long *best, DevParams *p) {
     __shared__ int lists[4][K > 0 ? 64 * K : 1];
+    // K > 0 without a redo list: the flagged chunks of the workgroup's four
+    // draws (draw slot << 24 | chunk) are rescanned by all four wavefronts,
+    // in pieces of 64 rows, their minima merged per draw in LDS
+    __shared__ uint32_t rq[K > 0 ? 4 * 64 * K : 1];
+    __shared__ int nrq;
+    __shared__ unsigned long long slot_min[4];
+    __shared__ int64_t slot_x[4];
     if (p->status != CHAMFER_OK) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nx) return;  // uniform over the wavefront
-    int *list = lists[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wv;
+    const bool coop = K > 0 && redo == nullptr;  // uniform over the grid
+    if (coop) {
+        if (threadIdx.x == 0) nrq = 0;
+        if (lane == 0) slot_min[wv] = ~0ull;
+        __syncthreads();
+    }
+    if (q >= nx) {  // uniform over the wavefront
+        if (!coop) return;
+        resolve_rescans(X, B, nB, d, chunk, rq, &nrq, slot_min, slot_x, wv, lane, -1);
+        return;
+    }
+    int *list = lists[wv];
     const unsigned long long below = (1ull << lane) - 1;
     const CH_RO uint4 *r = ro(rec) + (size_t)q * nchunk;
     // records past nchunk read as empty chunks (v = v2 = -inf); a record
@@ -650,8 +696,10 @@ __global__ __launch_bounds__(256) void k_split_resolve(
         if (lane == 0) atomicAdd(&p->fallbacks, (uint32_t)__popcll(mask));
         if (redo == nullptr) {
             if constexpr (K > 0) {
-                if (flag) list[nf + __popcll(mask & below)] = (int)c.w;
-                nf += __popcll(mask);
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&nrq, (uint32_t)__popcll(mask));
+                base = __shfl(base, 0);
+                if (flag) rq[base + (uint32_t)__popcll(mask & below)] = ((uint32_t)wv << 24) | c.w;
             } else {
                 while (mask) {
                     const int jj = __ffsll((long long)mask) - 1;
@@ -666,9 +714,14 @@ __global__ __launch_bounds__(256) void k_split_resolve(
         base = __shfl(base, 0);
         if (flag) redo[base + (uint32_t)__popcll(mask & below)] = make_uint2((uint32_t)q, c.w);
     }
-    for (int f = 0; f < nf; ++f) rescan(list[f]);
-    if (redo == nullptr)
+    (void)nf;
+    if (coop) {
+        const int64_t xr = rows ? (int64_t)ro(rows)[q] : q;
+        resolve_rescans(X, B, nB, d, chunk, rq, &nrq, slot_min, slot_x, wv, lane, xr * d);
+        m = min(m, slot_min[wv]);
+    } else if (redo == nullptr) {
         for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned long long)__shfl_xor(m, off));
+    }
     if (lane == 0) best[q] = m;
 }
 
