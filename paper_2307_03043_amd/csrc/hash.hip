@@ -650,8 +650,10 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int64_t 
 }
 
 // Probe grids of at least this many tiles compute the candidate distances
-// with tile_dist (l2, d = 128, measured: gather faster by 10% at 1563 tiles
-// and 4% at 3907; tile_dist faster by 1% at 6250 tiles and 4% at 15625).
+// with all four wavefronts (l2, d = 128, tile_dist against the gather by
+// wavefront 0: gather faster by 10% at 1563 tiles and 4% at 3907, tile_dist
+// faster by 1% at 6250 tiles and 4% at 15625; quad_dist 2% faster again at
+// 15625, and 8% for l1 at d = 64).
 constexpr int64_t kCoopDistTiles = 5000;
 
 // Canonical float32 distance of each point of the tile to its candidate row
@@ -736,6 +738,64 @@ __device__ __forceinline__ float tile_dist(const float *__restrict__ X, int64_t 
             if (wave == 0 && lane < np)
                 for (int k = 0; k < kc; ++k) term(tb[lane * ldt + k]);
             __syncthreads();
+        }
+    }
+    return METRIC == CHAMFER_L1 ? acc : sqrtf(acc);
+}
+
+// Canonical float32 distance of the tile's point pp to B's row c with four
+// lanes: lane 4 j + s holds quarter s of both rows (coordinates
+// [s S, (s + 1) S), S = ceil(d / 4) <= kQuadCols, all loaded in one batch)
+// and continues the sum of quarter s - 1, which moves one lane up between
+// quarters, so the terms are added in coordinate order as dist32 adds them.
+// The distance is returned in lane 4 j + 3.  All 64 lanes must call it.
+constexpr int kQuadCols = 32;
+template <int METRIC>
+__device__ __forceinline__ float quad_dist(const float *__restrict__ X, int64_t p0, int pp, int d,
+                                           const float *__restrict__ Bpts, int c) {
+    const int lane = threadIdx.x & 63, s = lane & 3;
+    const int S = (d + 3) >> 2;
+    const int k0 = s * S, k1 = min(d, k0 + S);
+    const auto *xr = ro(X) + (p0 + pp) * d;
+    const auto *br = ro(Bpts) + (int64_t)c * d;
+    float t[kQuadCols];
+    if ((S & 3) == 0 && (d & 3) == 0 &&
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Bpts)) & 15) == 0) {
+        // quarters of whole 16-byte quads (d a multiple of 16)
+        float4 xv[kQuadCols / 4], bv[kQuadCols / 4];
+#pragma unroll
+        for (int i = 0; i < kQuadCols / 4; ++i) {
+            const int k = min(k0 + 4 * i, d - 4);
+            xv[i] = ld(reinterpret_cast<const CH_RO float4 *>(xr + k));
+            bv[i] = ld(reinterpret_cast<const CH_RO float4 *>(br + k));
+        }
+#pragma unroll
+        for (int i = 0; i < kQuadCols / 4; ++i) {
+            t[4 * i] = xv[i].x - bv[i].x;
+            t[4 * i + 1] = xv[i].y - bv[i].y;
+            t[4 * i + 2] = xv[i].z - bv[i].z;
+            t[4 * i + 3] = xv[i].w - bv[i].w;
+        }
+    } else {
+        float xv[kQuadCols], bv[kQuadCols];
+#pragma unroll
+        for (int i = 0; i < kQuadCols; ++i) {
+            const int k = min(k0 + i, d - 1);
+            xv[i] = xr[k];
+            bv[i] = br[k];
+        }
+#pragma unroll
+        for (int i = 0; i < kQuadCols; ++i) t[i] = xv[i] - bv[i];
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float prev = __shfl_up(acc, 1, 4);  // quarter q - 1's sum, in the lane below
+        if (s == q) {
+            acc = q == 0 ? 0.0f : prev;
+#pragma unroll
+            for (int i = 0; i < kQuadCols; ++i)
+                if (k0 + i < k1) acc = METRIC == CHAMFER_L1 ? acc + fabsf(t[i]) : fmaf(t[i], t[i], acc);
         }
     }
     return METRIC == CHAMFER_L1 ? acc : sqrtf(acc);
@@ -999,28 +1059,33 @@ __device__ __forceinline__ void hash_tile(
     }
     // keep the better of (D, c, s) and the stored result of an earlier
     // structure; then store, and reduce max D on the last structure
-    auto finish = [&](float D, int c, int s) {
-        if (active) {
+    // store (D, c, s) for point ptx of the tile's points when act; with
+    // wave_max, the wavefront's max of the stored D goes to p->max_d_bits
+    // (kProbeLast).  Returns the stored D.
+    auto finish_at = [&](int64_t ptx, bool act, float D, int c, int s, bool wave_max) {
+        if (act) {
             if (flags & kProbeMerge) {
-                const float Dp = D_out[pt];
-                const int cp = nn_out[pt];
+                const float Dp = D_out[ptx];
+                const int cp = nn_out[ptx];
                 if (Dp < D || (Dp == D && cp < c)) {
                     D = Dp;
                     c = cp;
                 }
-                if (scale_out) s = min(s, scale_out[pt]);
+                if (scale_out) s = min(s, scale_out[ptx]);
             }
-            D_out[pt] = D;
-            nn_out[pt] = c;
-            if (scale_out) scale_out[pt] = s;
+            D_out[ptx] = D;
+            nn_out[ptx] = c;
+            if (scale_out) scale_out[ptx] = s;
         }
-        if (flags & kProbeLast) {
+        if (wave_max && (flags & kProbeLast)) {
             // wavefront max of D (D >= 0, so its bits order as floats)
-            uint32_t m = active ? __float_as_uint(D) : 0u;
+            uint32_t m = act ? __float_as_uint(D) : 0u;
             for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
             if (lane == 0) atomicMax(&p->max_d_bits, m);
         }
+        return D;
     };
+    auto finish = [&](float D, int c, int s) { finish_at(pt, active, D, c, s, true); };
     if (MODE == 3) {
         unsigned long long *wkeys = reinterpret_cast<unsigned long long *>(tables);
         int *wmem = reinterpret_cast<int *>(wkeys + ((size_t)L << log2cap));
@@ -1108,6 +1173,37 @@ __device__ __forceinline__ void hash_tile(
     wave_scale[wave][lane] = found;
     hit_cand[wave][lane] = cand;
     __syncthreads();
+    // Small grids (about one round of resident workgroups) finish sooner when
+    // wavefront 0 gathers both rows itself and the other three leave at once;
+    // large ones are faster with all four wavefronts on the distances: four
+    // lanes per point (quad_dist, d <= 128) or coalesced chunks (tile_dist).
+    const bool coop = !(METRIC == CHAMFER_L1 && YG) && (n + kTile - 1) / kTile >= kCoopDistTiles;
+    if (coop && d <= 4 * kQuadCols) {
+        // wavefront w: points 16 w + j, four lanes each
+        const int pq = 16 * wave + (lane >> 2);
+        int sq = L, cq = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            if (wave_scale[w][pq] < sq) {
+                sq = wave_scale[w][pq];
+                cq = hit_cand[w][pq];
+            }
+        const bool aq = (lane & 3) == 3 && pq < np;
+        const float Dq = finish_at(p0 + pq, aq,
+                                   quad_dist<METRIC>(X, p0, min(pq, np - 1), d, Bpts, cq), cq, sq,
+                                   false);
+        if (flags & kProbeLast) {  // one atomic per tile: the wavefronts' maxima meet in LDS
+            uint32_t m = aq ? __float_as_uint(Dq) : 0u;
+            for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+            if (lane == 0) hit_scale[wave] = (int)m;
+            __syncthreads();
+            if (tid == 0)
+                atomicMax(&p->max_d_bits,
+                          max(max((uint32_t)hit_scale[0], (uint32_t)hit_scale[1]),
+                              max((uint32_t)hit_scale[2], (uint32_t)hit_scale[3])));
+        }
+        return;
+    }
     // the finest colliding scale over the four wavefronts (every wavefront
     // computes it for its lane's point; wavefront 0 keeps it)
     int best_s = L, best_c = 0;
@@ -1119,10 +1215,6 @@ __device__ __forceinline__ void hash_tile(
                 best_c = hit_cand[w][lane];
             }
     }
-    // Small grids (about one round of resident workgroups) finish sooner when
-    // wavefront 0 gathers both rows itself and the other three leave at once;
-    // large ones move fewer lines with the coalesced workgroup form.
-    const bool coop = !(METRIC == CHAMFER_L1 && YG) && (n + kTile - 1) / kTile >= kCoopDistTiles;
     if (!coop) {
         if (wave != 0) return;
         finish(active ? dist32<METRIC>(xrow, Bpts + (size_t)best_c * d, d) : 0.0f, best_c,
