@@ -272,7 +272,7 @@ hipError_t mark(void **ev, int i, hipStream_t st) {
 // structures (reps) the tables are rebuilt for each structure r (grid stream
 // word r) and each probe keeps the better of its candidate and the stored
 // one; with a window W the tables hold W points per bucket.
-// nb2 given: the hash of B also fills |b|^2 and p->b2max_bits (inputs of the
+// nb2 given: the hash of B also fills |b|^2 and p->b2max_rep (inputs of the
 // l2 exact pass).
 int crude_core(const Plan &pl, const float *A, const float *B, uint64_t seed, float *D,
                int32_t *nn, int32_t *scale, void *ws, hipStream_t st, void **ev = nullptr,

@@ -28,14 +28,14 @@ __device__ __forceinline__ void init_params(DevParams *p, uint32_t *lohi, int d,
         p->e_top = 0;
         p->s = 0;
         p->all_zero = 0;
-        p->max_d_bits = 0;
         p->nonfinite = 0;
         p->W = 0;
         p->S = 0.0;
-        p->b2max_bits = 0;
         p->fallbacks = 0;
         p->nredo = 0;
     }
+    for (int64_t k = t; k < 2 * kMaxRepl; k += b.n * blockDim.x)
+        (k < kMaxRepl ? p->max_d_rep : p->b2max_rep)[(k % kMaxRepl) * kReplStride] = 0u;
     if (lohi != nullptr)
         for (int64_t k = t; k < (int64_t)kLohiReps * 2 * d; k += b.n * blockDim.x)
             lohi[k] = (k % (2 * d)) < d ? 0xffffffffu : 0u;  // running min / max (ordered)
@@ -988,7 +988,7 @@ __device__ __forceinline__ void hash_tile(
             uint32_t m = __float_as_uint(n2);
             for (int off = 32; off > 0; off >>= 1)
                 m = max(m, (uint32_t)__shfl_xor((int)m, off));
-            if (lane == 0) atomicMax(&p->b2max_bits, m);
+            if (lane == 0) rep_max(p->b2max_rep, blk.id, m);
         }
     }
     if (MODE == 1 && wave == 0) hit_scale[lane] = L;
@@ -1060,7 +1060,7 @@ __device__ __forceinline__ void hash_tile(
     // keep the better of (D, c, s) and the stored result of an earlier
     // structure; then store, and reduce max D on the last structure
     // store (D, c, s) for point ptx of the tile's points when act; with
-    // wave_max, the wavefront's max of the stored D goes to p->max_d_bits
+    // wave_max, the wavefront's max of the stored D goes to p->max_d_rep
     // (kProbeLast).  Returns the stored D.
     auto finish_at = [&](int64_t ptx, bool act, float D, int c, int s, bool wave_max) {
         if (act) {
@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void hash_tile(
             // wavefront max of D (D >= 0, so its bits order as floats)
             uint32_t m = act ? __float_as_uint(D) : 0u;
             for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-            if (lane == 0) atomicMax(&p->max_d_bits, m);
+            if (lane == 0) rep_max(p->max_d_rep, blk.id, m);
         }
         return D;
     };
@@ -1198,9 +1198,9 @@ __device__ __forceinline__ void hash_tile(
             if (lane == 0) hit_scale[wave] = (int)m;
             __syncthreads();
             if (tid == 0)
-                atomicMax(&p->max_d_bits,
-                          max(max((uint32_t)hit_scale[0], (uint32_t)hit_scale[1]),
-                              max((uint32_t)hit_scale[2], (uint32_t)hit_scale[3])));
+                rep_max(p->max_d_rep, blk.id,
+                        max(max((uint32_t)hit_scale[0], (uint32_t)hit_scale[1]),
+                            max((uint32_t)hit_scale[2], (uint32_t)hit_scale[3])));
         }
         return;
     }

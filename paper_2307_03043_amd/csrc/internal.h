@@ -30,6 +30,9 @@ constexpr int kMaxReps = 64;            // k of the multi-probe CrudeNN
 constexpr int kProbeMerge = 1;  // keep the better of this and the previous structure's result
 constexpr int kProbeLast = 2;   // last structure: also reduce max D_a
 
+constexpr int kMaxRepl = 64;     // replicas of the per-workgroup maxima (one per lane)
+constexpr int kReplStride = 32;  // uint32 words between replicas: one 128-byte line each
+
 // Device-resident parameters of one call; written by the kernels, read by
 // later kernels of the same call (no host round trip).
 struct DevParams {
@@ -37,16 +40,32 @@ struct DevParams {
     int32_t e_top;       // top grid scale exponent
     int32_t s;           // fixed-point exponent of the weights
     int32_t all_zero;    // every D_a == 0
-    uint32_t max_d_bits; // bits of max_a D_a (D_a >= 0, so bits order as floats)
     uint32_t nonfinite;  // an input coordinate is NaN or Inf
     uint64_t W;          // fixed-point total
     double S;            // sum_k (hi_k - lo_k)
-    uint32_t b2max_bits; // bits of max_b |b|^2 (float32, >= 0)
     uint32_t fallbacks;  // (query, chunk) pairs rescanned exactly by the MFMA pass
     uint32_t nredo;      // (query, chunk) pairs listed for the deferred pass's rescan
-    uint32_t pad32;
+    uint32_t pad32[2];
     uint64_t pad[1];
+    // The maxima of D_a and |b|^2 reduced over thousands of workgroups: each
+    // workgroup's atomicMax goes to replica (id mod kMaxRepl), one 128-byte
+    // line each, since atomics queued on one address serialise at its cache
+    // channel; readers take the max over the replicas (rep_fold).
+    uint32_t max_d_rep[kMaxRepl * kReplStride];
+    uint32_t b2max_rep[kMaxRepl * kReplStride];
 };
+
+__device__ __forceinline__ void rep_max(uint32_t *rep, int64_t id, uint32_t m) {
+    atomicMax(&rep[(id % kMaxRepl) * kReplStride], m);
+}
+
+// Max over the replicas (unsigned: the bits of non-negative floats order as
+// the floats); a whole wavefront calls it, lane r reading replica r.
+__device__ __forceinline__ uint32_t rep_fold(const uint32_t *rep) {
+    uint32_t m = rep[(threadIdx.x & 63) * kReplStride];
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    return m;
+}
 
 // One bucket of a scale's open-addressing table: key -> lowest b index.
 struct alignas(16) Bucket {
@@ -364,7 +383,7 @@ hipError_t launch_minmax_pair(const float *A, int64_t nA, const float *B, int64_
 hipError_t launch_calib_final(uint32_t *lohi, int d, DevParams *p, hipStream_t st);
 hipError_t launch_table_fill(Bucket *tables, size_t count, hipStream_t st);
 // mode 0: insert B into the tables (l2: also |b|^2 into nb2_out and
-// p->b2max_bits when nb2_out is set); 1: probe A (CrudeNN); 2: write keys;
+// p->b2max_rep when nb2_out is set); 1: probe A (CrudeNN); 2: write keys;
 // 5: write B's keys for launch_part_build (duplicates within a wavefront
 // dropped; |b|^2 as mode 0);
 // 3 / 4: insert / probe with a window of W points per bucket (the tables
@@ -412,7 +431,7 @@ hipError_t launch_nnmin(const float *X, const int32_t *rows, int64_t nx, const f
                         hipStream_t st);
 // The l2 exact pass on the BF16 matrix cores (12 <= d <= 256) with a two-term
 // split of every coordinate: launch_rownorm (or the hash of B) fills nb2 and
-// p->b2max_bits, launch_split_rows (or the hash of B) the split table of B
+// p->b2max_rep, launch_split_rows (or the hash of B) the split table of B
 // (split_table_bytes), then launch_nnmin_split returns the canonical float32
 // minima.
 bool mfma_supported(int d, int metric);

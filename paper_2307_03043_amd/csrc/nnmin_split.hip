@@ -181,7 +181,7 @@ hipError_t launch_split_queries(const float *X, const int32_t *rows, int64_t nx,
 }
 
 // |b|^2 per row (float32 fma chain in ascending k) and its maximum over B
-// (p->b2max_bits); one thread per row with 16-byte loads.
+// (p->b2max_rep); one thread per row with 16-byte loads.
 __global__ __launch_bounds__(256) void k_rownorm(const float *__restrict__ B, int64_t nB, int d,
                                                  float *nb2, DevParams *p) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_rownorm(const float *__restrict__ B, in
     }
     uint32_t m = __float_as_uint(v);
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&p->b2max_bits, m);
+    if ((threadIdx.x & 63) == 0) rep_max(p->b2max_rep, blockIdx.x, m);
 }
 
 hipError_t launch_rownorm(const float *B, int64_t nB, int d, float *nb2, DevParams *p,
@@ -469,7 +469,7 @@ __device__ __forceinline__ void nnmin_l2_split(
 
     // ---- re-rank and certificate, per block of 16 queries ----
     const double rho = split_rho(d);
-    const double b2max = (double)__uint_as_float(p->b2max_bits);
+    const double b2max = (double)__uint_as_float(rep_fold(p->b2max_rep));
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int64_t qi = qbase + nb * 16 + j;
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256) void k_split_resolve(
     const double rho = split_rho(d);
     const double xn = (double)ro(xn2)[q];
     const double E =
-        split_score_bound(d, DP, 3, xn, (double)__uint_as_float(p->b2max_bits));
+        split_score_bound(d, DP, 3, xn, (double)__uint_as_float(rep_fold(p->b2max_rep)));
     const double xlo = xn * (1.0 - rho), xhi = xn * (1.0 + 2.0 * rho);
     const float *x = X + (rows ? (int64_t)ro(rows)[q] : q) * d;
     auto dist = [&](int64_t b) {

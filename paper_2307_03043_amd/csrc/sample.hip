@@ -46,7 +46,7 @@ __device__ __forceinline__ void weight_blocksum(const float *__restrict__ D, int
                                                 Blk b) {
     __shared__ unsigned long long buf[kScanThreads];
     if (p->status != CHAMFER_OK) return;
-    const uint32_t mb = p->max_d_bits;
+    const uint32_t mb = rep_fold(p->max_d_rep);
     unsigned long long sum = 0;
     if (__uint_as_float(mb) > 0.0f) {
         const int s = fixed_point_exponent(mb, q);
@@ -83,8 +83,8 @@ __device__ __forceinline__ void scan_blocksums(unsigned long long *blocksums, in
         carry += tot;
         __syncthreads();
     }
+    const uint32_t mb = rep_fold(p->max_d_rep);
     if (threadIdx.x == 0) {
-        const uint32_t mb = p->max_d_bits;
         const bool zero = !(__uint_as_float(mb) > 0.0f);
         p->W = carry;
         p->s = zero ? 0 : fixed_point_exponent(mb, q);
@@ -303,7 +303,7 @@ __global__ void k_unit_weights(float *D, int32_t *nn, int32_t *scale, int64_t nA
         if (nn) nn[a] = -1;
         if (scale) scale[a] = -1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) p->max_d_bits = __float_as_uint(1.0f);
+    if (blockIdx.x == 0 && threadIdx.x == 0) p->max_d_rep[0] = __float_as_uint(1.0f);
 }
 
 hipError_t launch_unit_weights(float *D, int32_t *nn, int32_t *scale, int64_t nA, DevParams *p,
