@@ -1024,7 +1024,7 @@ __device__ __forceinline__ void hash_tile(
             bool mine = false;
             for (int it = 0; it < kLeaders && rest != 0; ++it) {
                 const int leader = __ffsll((long long)rest) - 1;
-                const unsigned long long lk = __shfl(key, leader);
+                const unsigned long long lk = lane_u64(key, leader);
                 rest &= ~__ballot(active && key == lk);
                 mine |= lane == leader;
             }
@@ -1043,7 +1043,7 @@ __device__ __forceinline__ void hash_tile(
             bool mine = false;
             for (int it = 0; it < kLeaders && rest != 0; ++it) {
                 const int leader = __ffsll((long long)rest) - 1;
-                const unsigned long long lk = __shfl(key, leader);
+                const unsigned long long lk = lane_u64(key, leader);
                 rest &= ~__ballot(active && key == lk);
                 mine |= lane == leader;
             }
@@ -1098,7 +1098,7 @@ __device__ __forceinline__ void hash_tile(
             bool mine = false;
             for (int it = 0; it < kLeaders && rest != 0; ++it) {
                 const int leader = __ffsll((long long)rest) - 1;
-                const unsigned long long lk = __shfl(key, leader);
+                const unsigned long long lk = lane_u64(key, leader);
                 const unsigned long long same = __ballot(active && key == lk);
                 if ((same >> lane) & 1ull) mine = __popcll(same & ((1ull << lane) - 1)) < W;
                 rest &= ~same;
@@ -1655,11 +1655,13 @@ __global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB
             // the lowest lane's key: its lanes fold their b into it (a key
             // repeated across wavefronts at coarse scales goes in once per
             // wavefront); the others insert on their own
-            const unsigned long long lk = __shfl(key, __ffsll((long long)__ballot(valid)) - 1);
+            const unsigned long long vm = __ballot(valid);
+            const int first = vm ? __ffsll((long long)vm) - 1 : 0;  // wave-uniform
+            const unsigned long long lk = lane_u64(key, first);
             const bool same = valid && key == lk;
-            int mb = same ? b : INT_MAX;
-            for (int off = 32; off > 0; off >>= 1) mb = min(mb, __shfl_xor(mb, off));
-            const bool leader = same && (__ffsll((long long)__ballot(same)) - 1) == lane;
+            // the lowest b among the lanes holding the first valid lane's key
+            const int mb = __ockl_wfred_min_i32(same ? b : INT_MAX);
+            const bool leader = same && lane == first;
             if (leader) b = mb;
             if (!valid || (same && !leader)) continue;
             int s = (int)(home_slot(key, log2cap) & (uint64_t)(S - 1));

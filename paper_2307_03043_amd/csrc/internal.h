@@ -67,6 +67,14 @@ __device__ __forceinline__ uint32_t rep_fold(const uint32_t *rep) {
     return m;
 }
 
+// Lane l's 64-bit value in every lane (l wave-uniform; a scalar register
+// read, no LDS round trip).
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // One bucket of a scale's open-addressing table: key -> lowest b index.
 struct alignas(16) Bucket {
     unsigned long long key;
