@@ -23,28 +23,32 @@ __device__ __forceinline__ int fixed_point_exponent(uint32_t max_d_bits, int q) 
     return 47 - q - e;
 }
 
-// Block-wide inclusive scan of one uint64 per thread (Hillis-Steele in LDS).
+// Block-wide inclusive scan of one uint64 per thread: a shuffle scan in each
+// wavefront, then each wavefront adds the totals of the wavefronts before it
+// (integer sums: the same values as any other order).  buf holds NT / 64
+// totals.
 template <int NT>
 __device__ unsigned long long block_inclusive_scan(unsigned long long v,
                                                    unsigned long long *buf) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        const unsigned long long add = t >= off ? buf[t - off] : 0ull;
-        __syncthreads();
-        buf[t] += add;
-        __syncthreads();
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole wavefronts");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, off);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), off);
+        if (lane >= off) v += ((unsigned long long)hi << 32) | lo;
     }
-    const unsigned long long r = buf[t];
+    if (lane == 63) buf[wv] = v;
     __syncthreads();
-    return r;
+    for (int w = 0; w < wv; ++w) v += buf[w];
+    __syncthreads();
+    return v;
 }
 
 __device__ __forceinline__ void weight_blocksum(const float *__restrict__ D, int64_t nA, int q,
                                                 unsigned long long *blocksums, const DevParams *p,
                                                 Blk b) {
-    __shared__ unsigned long long buf[kScanThreads];
+    __shared__ unsigned long long buf[kScanThreads / 64];
     if (p->status != CHAMFER_OK) return;
     const uint32_t mb = rep_fold(p->max_d_rep);
     unsigned long long sum = 0;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(kScanThreads) void k_weight_blocksum(
 // Exclusive scan of the block sums in place; W = total.  One block of 1024.
 __device__ __forceinline__ void scan_blocksums(unsigned long long *blocksums, int64_t nblk, int q,
                                                DevParams *p) {
-    __shared__ unsigned long long buf[1024];
+    __shared__ unsigned long long buf[1024 / 64];
     if (p->status != CHAMFER_OK) return;
     unsigned long long carry = 0;
     for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blo
 __device__ __forceinline__ void prefix(const float *__restrict__ D, int64_t nA,
                                        const unsigned long long *blockoffs,
                                        unsigned long long *P, const DevParams *p, Blk b) {
-    __shared__ unsigned long long buf[kScanThreads];
+    __shared__ unsigned long long buf[kScanThreads / 64];
     if (p->status != CHAMFER_OK) return;
     const int s = p->s;
     const bool zero = p->all_zero != 0;
