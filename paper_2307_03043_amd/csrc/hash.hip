@@ -1759,7 +1759,10 @@ hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, 
                                                               w.bins, w.entries);
     k_region_build<<<(unsigned)(L * R), 256, (size_t)S * 12, st>>>(w.entries, nB, L, log2cap,
                                                                    tables, w.bins, w.spilled);
-    k_spill_insert<<<256, 256, 0, st>>>(w.bins, w.entries, nB, L, log2cap, tables, w.spilled);
+    // a wavefront per (scale, region): most have nothing kept aside, and a
+    // wavefront that walked several regions waited on each one's inserts
+    k_spill_insert<<<(unsigned)((L * R + 3) / 4), 256, 0, st>>>(w.bins, w.entries, nB, L,
+                                                                 log2cap, tables, w.spilled);
     return hipGetLastError();
 }
 
