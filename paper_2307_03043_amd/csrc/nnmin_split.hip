@@ -728,8 +728,10 @@ __global__ __launch_bounds__(256) void k_split_resolve(
 // Rescans of the deferred form: each listed (query, chunk) pair is cut into
 // pieces of kRedoRows rows dealt to the wavefronts of a fixed grid, so a
 // few long chunks do not serialise on one wavefront; each piece merges its
-// canonical minimum into best[query] with a 64-bit atomicMin.
-constexpr int64_t kRedoRows = 256;
+// canonical minimum into best[query] with a 64-bit atomicMin.  A piece is one
+// row per lane (with four rows per lane, each lane's rows were four chains of
+// dependent loads one after another).
+constexpr int64_t kRedoRows = 64;
 constexpr unsigned kGridRedo = 256;
 // Chunks up to this many rows are rescanned by the resolving wavefront
 // itself (a third launch costs more than such rescans at 10^5 points: 347-row
