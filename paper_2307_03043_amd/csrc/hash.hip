@@ -1367,18 +1367,20 @@ __host__ __device__ inline int64_t part_regions(int log2cap) {
 int64_t part_blocks(int64_t nB) { return (nB + kPartBlock - 1) / kPartBlock; }
 bool part_build_ok(int log2cap) { return part_regions(log2cap) <= kMaxRegions; }
 
+static_assert(sizeof(uint3) == 12, "a (key, b) pair is three words");
+
 size_t part_work_bytes(int L, int64_t nB, int log2cap, PartWork *w, char *base) {
     const int64_t R = part_regions(log2cap), nblk = part_blocks(nB);
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t b_keys = al((size_t)L * nB * sizeof(uint64_t));
     const size_t b_offs = al((size_t)L * nblk * R * sizeof(uint32_t));
     const size_t b_bins = al((size_t)L * R * 3 * sizeof(uint32_t));
-    const size_t b_ent = al((size_t)L * nB * sizeof(uint4));
+    const size_t b_ent = al((size_t)L * nB * sizeof(uint3));
     if (w) {
         w->keys = reinterpret_cast<uint64_t *>(base);
         w->offs = reinterpret_cast<uint32_t *>(base + b_keys);
         w->bins = reinterpret_cast<uint32_t *>(base + b_keys + b_offs);
-        w->entries = reinterpret_cast<uint4 *>(base + b_keys + b_offs + b_bins);
+        w->entries = reinterpret_cast<uint3 *>(base + b_keys + b_offs + b_bins);
         w->spilled = reinterpret_cast<uint32_t *>(base + b_keys + b_offs + b_bins + b_ent);
     }
     return b_keys + b_offs + b_bins + b_ent + 256;
@@ -1565,7 +1567,7 @@ __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict
                                                       int64_t nB, int log2cap, int64_t nblk,
                                                       const uint32_t *__restrict__ offs,
                                                       const uint32_t *__restrict__ bins,
-                                                      uint4 *entries) {
+                                                      uint3 *entries) {
     extern __shared__ uint32_t sm[];
     const int R = (int)part_regions(log2cap);
     uint32_t *cnt = sm;               // [R] counts, then the block's region starts
@@ -1608,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict
         const unsigned long long key = sk[pos];
         const uint32_t g = key_region(key, log2cap);
         const size_t dst = (size_t)i * nB + bn[g * 3] + o[g] + (pos - cnt[g]);
-        entries[dst] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)sb[pos], 0u);
+        entries[dst] = make_uint3((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)sb[pos]);
     }
 }
 
@@ -1620,7 +1622,7 @@ __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict
 // thread are read before any is inserted (one round of loads).
 constexpr int kRegionPrefetch = 8;
 
-__global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB, int L,
+__global__ __launch_bounds__(256) void k_region_build(uint3 *entries, int64_t nB, int L,
                                                       int log2cap, Bucket *tables, uint32_t *bins,
                                                       uint32_t *spilled) {
     extern __shared__ unsigned long long tk[];  // [S] keys, then [S] values
@@ -1636,14 +1638,14 @@ __global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB
         tv[s] = INT_MAX;
     }
     if (threadIdx.x == 0) nspill = 0;
-    uint4 *run = entries + (size_t)i * nB + start;
+    uint3 *run = entries + (size_t)i * nB + start;
     const int lane = threadIdx.x & 63;
     for (uint32_t base = 0; base < count; base += 256 * kRegionPrefetch) {
-        uint4 e[kRegionPrefetch];
+        uint3 e[kRegionPrefetch];
 #pragma unroll
         for (int q = 0; q < kRegionPrefetch; ++q) {
             const uint32_t at = base + q * 256 + threadIdx.x;
-            e[q] = at < count ? run[at] : make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
+            e[q] = at < count ? run[at] : make_uint3(0xffffffffu, 0xffffffffu, 0u);
         }
         __syncthreads();  // the table is initialised; every pair read before spills overwrite
 #pragma unroll
@@ -1677,7 +1679,7 @@ __global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB
             }
             if (!done) {
                 const uint32_t r = atomicAdd(&nspill, 1u);
-                run[r] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)b, 0u);
+                run[r] = make_uint3((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)b);
             }
         }
         __syncthreads();
@@ -1712,7 +1714,7 @@ __global__ __launch_bounds__(256) void k_region_build(uint4 *entries, int64_t nB
 // The pairs the LDS builds kept aside, inserted with the global insert; a
 // single flag word says whether there are any.
 __global__ __launch_bounds__(256) void k_spill_insert(const uint32_t *__restrict__ bins,
-                                                      const uint4 *__restrict__ entries,
+                                                      const uint3 *__restrict__ entries,
                                                       int64_t nB, int L, int log2cap,
                                                       Bucket *tables, const uint32_t *spilled) {
     if (*spilled == 0) return;
@@ -1723,9 +1725,9 @@ __global__ __launch_bounds__(256) void k_spill_insert(const uint32_t *__restrict
         const uint32_t ns = bins[r * 3 + 2];
         if (ns == 0) continue;
         const int64_t i = r / R;
-        const uint4 *run = entries + (size_t)i * nB + bins[r * 3];
+        const uint3 *run = entries + (size_t)i * nB + bins[r * 3];
         for (uint32_t e = lane; e < ns; e += 64) {
-            const uint4 v = run[e];
+            const uint3 v = run[e];
             table_insert(tables + ((size_t)i << log2cap), table_fps(tables, L, log2cap, (int)i),
                          log2cap, (unsigned long long)v.x | ((unsigned long long)v.y << 32),
                          (int)v.z);

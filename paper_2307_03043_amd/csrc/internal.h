@@ -412,7 +412,7 @@ struct PartWork {
     uint64_t *keys;    // [L][nB] (the empty key for a dropped duplicate)
     uint32_t *offs;    // [L][blocks][regions]
     uint32_t *bins;    // [L][regions][3]: first entry, count, spilled
-    uint4 *entries;    // [L][nB] (key lo, key hi, b, 0) grouped by region
+    uint3 *entries;    // [L][nB] (key lo, key hi, b) grouped by region
     uint32_t *spilled; // [1] some region kept pairs aside for the global insert
 };
 bool part_build_ok(int log2cap);
