@@ -474,7 +474,6 @@ void job_stage_blocks(const Job &J, int64_t out[kBsCount]) {
     out[kBsProbe] = J.nb_hashA;
     out[kBsWsum] = J.nb_scan;
     out[kBsWscan] = 1;
-    out[kBsPrefix] = J.nb_scan;
     out[kBsSample] = J.nb_sample;
     out[kBsCast] = (int64_t)J.nb_castB + J.nb_castX;
     out[kBsNN] = J.nb_nn;
@@ -687,11 +686,12 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
         int32_t *nn = ax.crude_nn ? ax.crude_nn : at<int32_t>(ws, pl.off_nn);
         if ((rc = crude_core(pl, A, B, seed, D, nn, scale, ws, st, ev, nb2, bsplit))) return rc;
     }
-    uint64_t *P = at<uint64_t>(ws, pl.off_P);
+    uint64_t *P = at<uint64_t>(ws, pl.off_P);  // in-block prefixes of the weights
     int32_t *idx = at<int32_t>(ws, pl.off_idx);
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
-    CH_TRY(launch_sample(seed, P, n_A, pl.T, idx, best, p, st));
+    CH_TRY(launch_sample(seed, P, at<uint64_t>(ws, pl.off_blocksums), n_A, pl.T, idx, best, p,
+                         st));
     CH_TRY(mark(ev, 4, st));
     // the split table of the draws (part of the exact pass); B's was written
     // while B was hashed, except for the uniform baseline, which does not

@@ -185,7 +185,7 @@ struct Job {
     int64_t table_count;
     float *D;
     int32_t *nn;
-    unsigned long long *blocksums, *P;
+    unsigned long long *blocksums, *P;  // block totals (then offsets); in-block prefixes
     int32_t *idx;
     unsigned long long *best;
     float *nb2;
@@ -213,7 +213,6 @@ enum BatchStage {
     kBsProbe,   // CrudeNN of A
     kBsWsum,    // fixed-point weights: block sums
     kBsWscan,   // scan of the block sums, W and s
-    kBsPrefix,  // prefix P
     kBsSample,  // T draws
     kBsCast,    // low-precision copies of B and of the sampled rows, or B's split table
     kBsNN,      // exact nearest neighbours of the samples
@@ -423,10 +422,14 @@ hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, 
                              hipStream_t st);
 // Empty tables (window W).
 hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStream_t st);
-hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
+// Weights: per-block totals into blocksums (scanned in place to the blocks'
+// offsets) and each point's in-block inclusive prefix into Ploc [n_A].
+hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *Ploc,
                           DevParams *p, hipStream_t st);
-hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,
-                         unsigned long long *best, DevParams *p, hipStream_t st);
+// Draws from P_a = offs[a / kScanBlock] + Ploc_a (launch_weights' outputs).
+hipError_t launch_sample(uint64_t seed, const uint64_t *Ploc, const uint64_t *offs, int64_t nA,
+                         int64_t T, int32_t *idx, unsigned long long *best, DevParams *p,
+                         hipStream_t st);
 hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *idx,
                                  const float *D, int64_t T, int metric, DevParams *p,
                                  double *eta_out, chamfer_aux aux, hipStream_t st);

@@ -1,8 +1,9 @@
 // Importance sampling (the Chamfer-Estimate figure, steps 1-4) on the GPU:
-// fixed-point weights w_a = ceil(D_a 2^s), their inclusive prefix P and
-// total W (two-level scan), T i.i.d. draws u ~ U[0, W) by Lemire's bounded
-// integers on Philox4x64-10 with the sample index min{a : P_a > u}, and the
-// final reweighted mean eta = (1/T) sum_l (W / w_{x_l}) m_l in double.
+// fixed-point weights w_a = ceil(D_a 2^s), their inclusive prefix P (kept
+// as block offsets plus in-block prefixes) and total W (two-level scan),
+// T i.i.d. draws u ~ U[0, W) by Lemire's bounded integers on Philox4x64-10
+// with the sample index min{a : P_a > u}, and the final reweighted mean
+// eta = (1/T) sum_l (W / w_{x_l}) m_l in double.
 //
 // Everything is integer arithmetic except the final sum, which is a fixed
 // order tree in double: results do not depend on scheduling.
@@ -45,28 +46,41 @@ __device__ unsigned long long block_inclusive_scan(unsigned long long v,
     return v;
 }
 
+// Block b.id of kScanBlock points: each point's weight w_a and its
+// inclusive prefix within the block (Ploc, uint64), and the block's total
+// (blocksums[b.id]).  After the scan of the totals, P_a = blocksums[a /
+// kScanBlock] + Ploc_a.
 __device__ __forceinline__ void weight_blocksum(const float *__restrict__ D, int64_t nA, int q,
-                                                unsigned long long *blocksums, const DevParams *p,
+                                                unsigned long long *blocksums,
+                                                unsigned long long *Ploc, const DevParams *p,
                                                 Blk b) {
     __shared__ unsigned long long buf[kScanThreads / 64];
     if (p->status != CHAMFER_OK) return;
     const uint32_t mb = rep_fold(p->max_d_rep);
-    unsigned long long sum = 0;
-    if (__uint_as_float(mb) > 0.0f) {
-        const int s = fixed_point_exponent(mb, q);
-        const int64_t base = b.id * kScanBlock + threadIdx.x * kScanItems;
+    const bool pos = __uint_as_float(mb) > 0.0f;  // else every weight is 0
+    const int s = pos ? fixed_point_exponent(mb, q) : 0;
+    const int64_t base = b.id * kScanBlock + threadIdx.x * kScanItems;
+    unsigned long long w[kScanItems];
+    unsigned long long own = 0;
 #pragma unroll
-        for (int j = 0; j < kScanItems; ++j)
-            if (base + j < nA) sum += weight_of(ro(D)[base + j], s);
+    for (int j = 0; j < kScanItems; ++j) {
+        w[j] = (pos && base + j < nA) ? weight_of(ro(D)[base + j], s) : 0ull;
+        own += w[j];
     }
-    const unsigned long long inc = block_inclusive_scan<kScanThreads>(sum, buf);
+    const unsigned long long inc = block_inclusive_scan<kScanThreads>(own, buf);
+    unsigned long long run = inc - own;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        run += w[j];
+        if (base + j < nA) Ploc[base + j] = run;
+    }
     if (threadIdx.x == kScanThreads - 1) blocksums[b.id] = inc;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_weight_blocksum(
     const float *__restrict__ D, int64_t nA, int q, unsigned long long *blocksums,
-    const DevParams *p) {
-    weight_blocksum(D, nA, q, blocksums, p, grid_blk());
+    unsigned long long *Ploc, const DevParams *p) {
+    weight_blocksum(D, nA, q, blocksums, Ploc, p, grid_blk());
 }
 
 // Exclusive scan of the block sums in place; W = total.  One block of 1024.
@@ -101,72 +115,52 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blo
     scan_blocksums(blocksums, nblk, q, p);
 }
 
-__device__ __forceinline__ void prefix(const float *__restrict__ D, int64_t nA,
-                                       const unsigned long long *blockoffs,
-                                       unsigned long long *P, const DevParams *p, Blk b) {
-    __shared__ unsigned long long buf[kScanThreads / 64];
-    if (p->status != CHAMFER_OK) return;
-    const int s = p->s;
-    const bool zero = p->all_zero != 0;
-    const int64_t base = b.id * kScanBlock + threadIdx.x * kScanItems;
-    unsigned long long w[kScanItems];
-    unsigned long long own = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        w[j] = (!zero && base + j < nA) ? weight_of(ro(D)[base + j], s) : 0ull;
-        own += w[j];
-    }
-    const unsigned long long inc = block_inclusive_scan<kScanThreads>(own, buf);
-    unsigned long long run = ro(blockoffs)[b.id] + inc - own;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        run += w[j];
-        if (base + j < nA) P[base + j] = run;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_prefix(const float *__restrict__ D, int64_t nA,
-                                                         const unsigned long long *blockoffs,
-                                                         unsigned long long *P,
-                                                         const DevParams *p) {
-    prefix(D, nA, blockoffs, P, p, grid_blk());
-}
-
 int64_t scan_blocks(int64_t nA) { return (nA + kScanBlock - 1) / kScanBlock; }
 
-hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *P,
+hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *Ploc,
                           DevParams *p, hipStream_t st) {
     const int64_t nblk = scan_blocks(nA);
     auto *bs = reinterpret_cast<unsigned long long *>(blocksums);
-    k_weight_blocksum<<<(unsigned)nblk, kScanThreads, 0, st>>>(D, nA, q, bs, p);
+    k_weight_blocksum<<<(unsigned)nblk, kScanThreads, 0, st>>>(
+        D, nA, q, bs, reinterpret_cast<unsigned long long *>(Ploc), p);
     k_scan_blocksums<<<1, 1024, 0, st>>>(bs, nblk, q, p);
-    k_prefix<<<(unsigned)nblk, kScanThreads, 0, st>>>(D, nA, bs,
-                                                       reinterpret_cast<unsigned long long *>(P),
-                                                       p);
     return hipGetLastError();
 }
 
 // Draw l: word 0 of Philox4x64-10 at counter (l, attempt, SAMPLE, 0), key
 // (seed, 0); Lemire: m = x W, reject while (m mod 2^64) < (2^64 - W) mod W,
 // u = m >> 64; idx = min{a : P_a > u}.  Also resets the nearest-neighbour
-// slot of the draw.  The search first finds, in LDS, the first of kFences
-// evenly spaced fences P[(i + 1) S - 1] (S = ceil(n_A / kFences), the last
-// one P[n_A - 1] = W > u) above u, then searches the S entries it closes in
-// memory: the same index with log2 S dependent loads instead of log2 n_A.
-// Every thread of the workgroup must call it (one barrier).
+// slot of the draw.  P_a is the block offset offs[a / kScanBlock] (the
+// scanned block totals, held in LDS when there are at most kOffsLds blocks)
+// plus the in-block prefix Ploc_a.  The search first finds, in LDS, the
+// first of kFences evenly spaced fences P[(i + 1) S - 1] (S = ceil(n_A /
+// kFences), the last one P[n_A - 1] = W > u) above u, then searches the S
+// entries it closes in memory: the same index with log2 S dependent loads
+// instead of log2 n_A.  Every thread of the workgroup must call it (one
+// barrier).
 constexpr int kFences = 1024;
+constexpr int64_t kOffsLds = 4096;  // block offsets in LDS up to n_A = 4 Mi points
 
-__device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *__restrict__ P,
-                                       int64_t nA, int64_t T, int32_t *idx,
-                                       unsigned long long *best, const DevParams *p, Blk blk) {
+__device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *__restrict__ Ploc,
+                                       const unsigned long long *__restrict__ offs, int64_t nA,
+                                       int64_t T, int32_t *idx, unsigned long long *best,
+                                       const DevParams *p, Blk blk) {
     __shared__ unsigned long long fence[kFences];
+    __shared__ unsigned long long boff[kOffsLds];
     const int64_t l = blk.id * blockDim.x + threadIdx.x;
     const uint64_t W = p->W;
     const bool ok = p->status == CHAMFER_OK && W != 0;  // uniform
     const int64_t S = (nA + kFences - 1) / kFences;
-    if (ok)
-        for (int i = threadIdx.x; i < kFences; i += blockDim.x)
-            fence[i] = ro(P)[min((int64_t)(i + 1) * S - 1, nA - 1)];
+    const int64_t nblk = (nA + kScanBlock - 1) / kScanBlock;
+    const bool lds_off = nblk <= kOffsLds;  // uniform
+    if (ok) {
+        if (lds_off)
+            for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) boff[i] = ro(offs)[i];
+        for (int i = threadIdx.x; i < kFences; i += blockDim.x) {
+            const int64_t a = min((int64_t)(i + 1) * S - 1, nA - 1);
+            fence[i] = ro(offs)[a / kScanBlock] + ro(Ploc)[a];
+        }
+    }
     __syncthreads();
     if (l >= T) return;
     best[l] = ~0ull;
@@ -198,7 +192,9 @@ __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *
     int64_t a = (int64_t)f0 * S, b = min((int64_t)(f0 + 1) * S - 1, nA - 1);
     while (a < b) {
         const int64_t mid = a + ((b - a) >> 1);
-        if (ro(P)[mid] > u)
+        const int64_t j = mid / kScanBlock;
+        const unsigned long long pm = (lds_off ? boff[j] : ro(offs)[j]) + ro(Ploc)[mid];
+        if (pm > u)
             b = mid;
         else
             a = mid + 1;
@@ -206,19 +202,21 @@ __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *
     idx[l] = (int32_t)a;
 }
 
-__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ P, int64_t nA,
-                         int64_t T, int32_t *idx, unsigned long long *best,
-                         const DevParams *p) {
-    sample(seed, P, nA, T, idx, best, p, grid_blk());
+__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ Ploc,
+                         const unsigned long long *__restrict__ offs, int64_t nA, int64_t T,
+                         int32_t *idx, unsigned long long *best, const DevParams *p) {
+    sample(seed, Ploc, offs, nA, T, idx, best, p, grid_blk());
 }
 
 int64_t sample_blocks(int64_t T) { return (T + 255) / 256; }
 
-hipError_t launch_sample(uint64_t seed, const uint64_t *P, int64_t nA, int64_t T, int32_t *idx,
-                         unsigned long long *best, DevParams *p, hipStream_t st) {
+hipError_t launch_sample(uint64_t seed, const uint64_t *Ploc, const uint64_t *offs, int64_t nA,
+                         int64_t T, int32_t *idx, unsigned long long *best, DevParams *p,
+                         hipStream_t st) {
     if (T <= 0) return hipSuccess;
     k_sample<<<(unsigned)sample_blocks(T), 256, 0, st>>>(
-        seed, reinterpret_cast<const unsigned long long *>(P), nA, T, idx, best, p);
+        seed, reinterpret_cast<const unsigned long long *>(Ploc),
+        reinterpret_cast<const unsigned long long *>(offs), nA, T, idx, best, p);
     return hipGetLastError();
 }
 
@@ -335,7 +333,7 @@ constexpr unsigned kGridScan = 1024, kGridWscan = kBatchMax, kGridSample = 256,
 
 __global__ __launch_bounds__(kScanThreads) void kb_wsum(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsWsum, [&](const Job &J, Blk b) {
-        weight_blocksum(J.D, J.nA, J.q, J.blocksums, J.p, b);
+        weight_blocksum(J.D, J.nA, J.q, J.blocksums, J.P, J.p, b);
     });
 }
 
@@ -345,15 +343,9 @@ __global__ __launch_bounds__(1024) void kb_wscan(const Batch *__restrict__ bt) {
     });
 }
 
-__global__ __launch_bounds__(kScanThreads) void kb_prefix(const Batch *__restrict__ bt) {
-    batch_loop(bt, kBsPrefix, [&](const Job &J, Blk b) {
-        prefix(J.D, J.nA, J.blocksums, J.P, J.p, b);
-    });
-}
-
 __global__ __launch_bounds__(256) void kb_sample(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsSample, [&](const Job &J, Blk b) {
-        sample(J.seed, J.P, J.nA, J.T, J.idx, J.best, J.p, b);
+        sample(J.seed, J.P, J.blocksums, J.nA, J.T, J.idx, J.best, J.p, b);
     });
 }
 
@@ -366,7 +358,6 @@ __global__ __launch_bounds__(256) void kb_final(const Batch *__restrict__ bt, in
 hipError_t launch_batch_weights(const Batch *bt, hipStream_t st) {
     kb_wsum<<<kGridScan, kScanThreads, 0, st>>>(bt);
     kb_wscan<<<kGridWscan, 1024, 0, st>>>(bt);
-    kb_prefix<<<kGridScan, kScanThreads, 0, st>>>(bt);
     return hipGetLastError();
 }
 
