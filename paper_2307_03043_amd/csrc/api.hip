@@ -690,8 +690,8 @@ int chamfer_estimate(const float *A, const float *B, int64_t n_A, int64_t n_B, i
     int32_t *idx = at<int32_t>(ws, pl.off_idx);
     auto *best = at<unsigned long long>(ws, pl.off_best);
     CH_TRY(launch_weights(D, n_A, pl.q, at<uint64_t>(ws, pl.off_blocksums), P, p, st));
-    CH_TRY(launch_sample(seed, P, at<uint64_t>(ws, pl.off_blocksums), n_A, pl.T, idx, best, p,
-                         st));
+    CH_TRY(launch_sample(seed, P, at<uint64_t>(ws, pl.off_blocksums), n_A, pl.T, pl.q, idx, best,
+                         p, st));
     CH_TRY(mark(ev, 4, st));
     // the split table of the draws (part of the exact pass); B's was written
     // while B was hashed, except for the uniform baseline, which does not

@@ -426,9 +426,10 @@ hipError_t launch_tables_empty(Bucket *tables, int L, int log2cap, int W, hipStr
 // offsets) and each point's in-block inclusive prefix into Ploc [n_A].
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *Ploc,
                           DevParams *p, hipStream_t st);
-// Draws from P_a = offs[a / kScanBlock] + Ploc_a (launch_weights' outputs).
+// Draws from P_a = offs[a / kScanBlock] + Ploc_a (launch_weights' outputs;
+// q as for launch_weights).
 hipError_t launch_sample(uint64_t seed, const uint64_t *Ploc, const uint64_t *offs, int64_t nA,
-                         int64_t T, int32_t *idx, unsigned long long *best, DevParams *p,
+                         int64_t T, int q, int32_t *idx, unsigned long long *best, DevParams *p,
                          hipStream_t st);
 hipError_t launch_estimate_final(const unsigned long long *best, const int32_t *idx,
                                  const float *D, int64_t T, int metric, DevParams *p,

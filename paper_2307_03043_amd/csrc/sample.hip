@@ -24,6 +24,10 @@ __device__ __forceinline__ int fixed_point_exponent(uint32_t max_d_bits, int q) 
     return 47 - q - e;
 }
 
+// Blocks (of kScanBlock points) whose offsets the sampler holds in LDS:
+// up to n_A = 4 Mi points.
+constexpr int64_t kOffsLds = 4096;
+
 // Block-wide inclusive scan of one uint64 per thread: a shuffle scan in each
 // wavefront, then each wavefront adds the totals of the wavefronts before it
 // (integer sums: the same values as any other order).  buf holds NT / 64
@@ -117,13 +121,17 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *blo
 
 int64_t scan_blocks(int64_t nA) { return (nA + kScanBlock - 1) / kScanBlock; }
 
+// Up to kOffsLds blocks the sampler scans the block totals itself (one
+// launch fewer); above, k_scan_blocksums does.
+bool sample_scans(int64_t nA) { return scan_blocks(nA) <= kOffsLds; }
+
 hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums, uint64_t *Ploc,
                           DevParams *p, hipStream_t st) {
     const int64_t nblk = scan_blocks(nA);
     auto *bs = reinterpret_cast<unsigned long long *>(blocksums);
     k_weight_blocksum<<<(unsigned)nblk, kScanThreads, 0, st>>>(
         D, nA, q, bs, reinterpret_cast<unsigned long long *>(Ploc), p);
-    k_scan_blocksums<<<1, 1024, 0, st>>>(bs, nblk, q, p);
+    if (!sample_scans(nA)) k_scan_blocksums<<<1, 1024, 0, st>>>(bs, nblk, q, p);
     return hipGetLastError();
 }
 
@@ -139,28 +147,66 @@ hipError_t launch_weights(const float *D, int64_t nA, int q, uint64_t *blocksums
 // instead of log2 n_A.  Every thread of the workgroup must call it (one
 // barrier).
 constexpr int kFences = 1024;
-constexpr int64_t kOffsLds = 4096;  // block offsets in LDS up to n_A = 4 Mi points
 
+// local (at most kOffsLds blocks, 256 threads): offs holds the blocks'
+// totals, not yet scanned; every workgroup scans them into LDS itself, and
+// workgroup 0 stores W, s and all_zero (what k_scan_blocksums stores).
 __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *__restrict__ Ploc,
                                        const unsigned long long *__restrict__ offs, int64_t nA,
                                        int64_t T, int32_t *idx, unsigned long long *best,
-                                       const DevParams *p, Blk blk) {
+                                       DevParams *p, int q, bool local, Blk blk) {
     __shared__ unsigned long long fence[kFences];
     __shared__ unsigned long long boff[kOffsLds];
+    __shared__ unsigned long long sbuf[4];
+    __shared__ unsigned long long total;
     const int64_t l = blk.id * blockDim.x + threadIdx.x;
-    const uint64_t W = p->W;
-    const bool ok = p->status == CHAMFER_OK && W != 0;  // uniform
+    const bool st_ok = p->status == CHAMFER_OK;  // uniform
     const int64_t S = (nA + kFences - 1) / kFences;
     const int64_t nblk = (nA + kScanBlock - 1) / kScanBlock;
-    const bool lds_off = nblk <= kOffsLds;  // uniform
-    if (ok) {
-        if (lds_off)
+    const bool lds_off = nblk <= kOffsLds;  // uniform; true when local
+    uint64_t W;
+    if (local) {
+        // thread t: a run of `per` consecutive totals (loads in flight
+        // together), their sum scanned across the workgroup, then the run's
+        // exclusive offsets
+        constexpr int kPer = kOffsLds / 256;
+        const int64_t i0 = (int64_t)threadIdx.x * kPer;
+        unsigned long long v[kPer];
+        unsigned long long own = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            v[j] = (st_ok && i0 + j < nblk) ? ro(offs)[i0 + j] : 0ull;
+            own += v[j];
+        }
+        const unsigned long long inc = block_inclusive_scan<256>(own, sbuf);
+        unsigned long long run = inc - own;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (i0 + j < nblk) boff[i0 + j] = run;
+            run += v[j];
+        }
+        if (threadIdx.x == 255) total = inc;
+        const uint32_t mb = rep_fold(p->max_d_rep);
+        __syncthreads();
+        W = total;
+        if (blk.id == 0 && threadIdx.x == 0 && st_ok) {
+            const bool zero = !(__uint_as_float(mb) > 0.0f);
+            p->W = W;
+            p->s = zero ? 0 : fixed_point_exponent(mb, q);
+            p->all_zero = zero ? 1 : 0;
+        }
+    } else {
+        W = p->W;
+        if (st_ok && W != 0 && lds_off)
             for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) boff[i] = ro(offs)[i];
+    }
+    const bool ok = st_ok && W != 0;  // uniform
+    if (ok)
         for (int i = threadIdx.x; i < kFences; i += blockDim.x) {
             const int64_t a = min((int64_t)(i + 1) * S - 1, nA - 1);
-            fence[i] = ro(offs)[a / kScanBlock] + ro(Ploc)[a];
+            const int64_t j = a / kScanBlock;
+            fence[i] = (local ? boff[j] : ro(offs)[j]) + ro(Ploc)[a];
         }
-    }
     __syncthreads();
     if (l >= T) return;
     best[l] = ~0ull;
@@ -202,21 +248,27 @@ __device__ __forceinline__ void sample(uint64_t seed, const unsigned long long *
     idx[l] = (int32_t)a;
 }
 
-__global__ void k_sample(uint64_t seed, const unsigned long long *__restrict__ Ploc,
-                         const unsigned long long *__restrict__ offs, int64_t nA, int64_t T,
-                         int32_t *idx, unsigned long long *best, const DevParams *p) {
-    sample(seed, Ploc, offs, nA, T, idx, best, p, grid_blk());
+__global__ __launch_bounds__(256) void k_sample(uint64_t seed,
+                                                const unsigned long long *__restrict__ Ploc,
+                                                const unsigned long long *__restrict__ offs,
+                                                int64_t nA, int64_t T, int32_t *idx,
+                                                unsigned long long *best, DevParams *p, int q,
+                                                int local) {
+    sample(seed, Ploc, offs, nA, T, idx, best, p, q, local != 0, grid_blk());
 }
 
 int64_t sample_blocks(int64_t T) { return (T + 255) / 256; }
 
 hipError_t launch_sample(uint64_t seed, const uint64_t *Ploc, const uint64_t *offs, int64_t nA,
-                         int64_t T, int32_t *idx, unsigned long long *best, DevParams *p,
+                         int64_t T, int q, int32_t *idx, unsigned long long *best, DevParams *p,
                          hipStream_t st) {
-    if (T <= 0) return hipSuccess;
-    k_sample<<<(unsigned)sample_blocks(T), 256, 0, st>>>(
+    const bool local = sample_scans(nA);
+    if (T <= 0 && !local) return hipSuccess;
+    // with T <= 0 one workgroup still stores W and s
+    k_sample<<<(unsigned)(T > 0 ? sample_blocks(T) : 1), 256, 0, st>>>(
         seed, reinterpret_cast<const unsigned long long *>(Ploc),
-        reinterpret_cast<const unsigned long long *>(offs), nA, T, idx, best, p);
+        reinterpret_cast<const unsigned long long *>(offs), nA, T, idx, best, p, q,
+        local ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -345,7 +397,7 @@ __global__ __launch_bounds__(1024) void kb_wscan(const Batch *__restrict__ bt) {
 
 __global__ __launch_bounds__(256) void kb_sample(const Batch *__restrict__ bt) {
     batch_loop(bt, kBsSample, [&](const Job &J, Blk b) {
-        sample(J.seed, J.P, J.blocksums, J.nA, J.T, J.idx, J.best, J.p, b);
+        sample(J.seed, J.P, J.blocksums, J.nA, J.T, J.idx, J.best, J.p, J.q, false, b);
     });
 }
 
