@@ -1337,13 +1337,14 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
 
 // ------------------------------------------------------ partitioned build
 // The W = 1 tables of the direct path, built without global atomics.  A
-// table of 2^c slots is cut into regions of S = 2^min(c, 12) slots, and a
+// table of 2^c slots is cut into regions of S = 2^min(c, 11) slots, and a
 // key's region is the top bits of its home slot.  From B's keys (hash mode
 // 5, a wavefront's duplicate keys dropped): per scale, each block of
-// kPartBlock keys counts its keys per region (k_part_hist), one workgroup
-// per scale turns the counts into offsets (k_part_scan), the blocks write
-// their (key, b) pairs grouped by region (k_part_scatter, runs of a region
-// contiguous), and one workgroup per (scale, region) inserts the region's
+// kPartBlock keys counts its keys per region (k_part_hist), the counts
+// become offsets (small partitions: inside k_part_scatter, each workgroup
+// from its scale's counts; large ones: k_part_scan_rows and k_part_base),
+// the blocks write their (key, b) pairs grouped by region (k_part_scatter,
+// runs of a region contiguous), and one workgroup per (scale, region) inserts the region's
 // pairs into a table in LDS -- linear probing from the home slot, lowest b
 // per key, LDS atomics only -- and writes all S slots out
 // (k_region_build).  The LDS build never wraps: a pair whose probe reaches
@@ -1392,9 +1393,10 @@ __device__ __forceinline__ uint32_t key_region(unsigned long long key, int log2c
 
 // In-place exclusive prefix sum of v[0..R) (R <= 1024) by a workgroup of
 // 256 threads; returns the total.  Each thread sums up to four consecutive
-// values, the 256 partial sums are scanned in LDS, then written back.
+// values, the 256 partial sums are scanned by wavefront shuffles (tmp: the
+// four wavefronts' totals), then written back.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, int R, uint32_t *tmp) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int per = (R + 255) / 256;
     uint32_t loc[4] = {0, 0, 0, 0};
     uint32_t sum = 0;
@@ -1404,16 +1406,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *v, int R, uin
             loc[q] = v[t * per + q];
             sum += loc[q];
         }
-    tmp[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t x = t >= off ? tmp[t - off] : 0u;
-        __syncthreads();
-        tmp[t] += x;
-        __syncthreads();
+    // inclusive scan of the groups' sums: shuffles in each wavefront, then
+    // the totals of the wavefronts before
+    uint32_t x = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off);
+        if (lane >= off) x += y;
     }
-    uint32_t run = tmp[t] - sum;  // exclusive prefix of this thread's group
-    const uint32_t total = tmp[255];
+    if (lane == 63) tmp[wv] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wv; ++w) before += tmp[w];
+    const uint32_t total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    uint32_t run = before + x - sum;  // exclusive prefix of this thread's group
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         if (q < per && t * per + q < R) {
@@ -1448,45 +1454,10 @@ __global__ __launch_bounds__(256) void k_part_hist(const uint64_t *__restrict__ 
     for (int g = threadIdx.x; g < R; g += 256) o[g] = cnt[g];
 }
 
-// Per scale: offs becomes the exclusive prefix over blocks of each region's
-// counts; bins[(i R + g) 3 + {0, 1, 2}] = the region's first entry (in the
-// scale's [nB] span of entries), its count, and 0 (spill count); the spill
-// flag is cleared.
-__global__ __launch_bounds__(256) void k_part_scan(int64_t nB, int log2cap, int64_t nblk,
-                                                   uint32_t *offs, uint32_t *bins,
-                                                   uint32_t *spilled) {
-    extern __shared__ uint32_t tot[];  // [R], then [256] scan scratch
-    const int R = (int)part_regions(log2cap);
-    const int64_t i = blockIdx.x;
-    if (i == 0 && threadIdx.x == 0) *spilled = 0;  // read after the region builds
-    for (int g = threadIdx.x; g < R; g += 256) {
-        uint32_t run = 0;
-        uint32_t *o = offs + (size_t)i * nblk * R + g;
-        int64_t j = 0;
-        for (; j + 4 <= nblk; j += 4) {
-            const uint32_t c0 = o[(j + 0) * R], c1 = o[(j + 1) * R];
-            const uint32_t c2 = o[(j + 2) * R], c3 = o[(j + 3) * R];
-            o[(j + 0) * R] = run;
-            o[(j + 1) * R] = run + c0;
-            o[(j + 2) * R] = run + c0 + c1;
-            o[(j + 3) * R] = run + c0 + c1 + c2;
-            run += c0 + c1 + c2 + c3;
-        }
-        for (; j < nblk; ++j) {
-            const uint32_t c = o[j * R];
-            o[j * R] = run;
-            run += c;
-        }
-        tot[g] = run;
-        bins[((size_t)i * R + g) * 3 + 1] = run;
-        bins[((size_t)i * R + g) * 3 + 2] = 0;
-    }
-    __syncthreads();
-    block_exclusive_scan(tot, R, tot + R);
-    for (int g = threadIdx.x; g < R; g += 256) bins[((size_t)i * R + g) * 3 + 0] = tot[g];
-}
-
-// The same for large partitions (many blocks and regions), in two launches:
+// Large partitions (many blocks and regions): the counts become offsets in
+// two launches (offs: the exclusive prefix over blocks of each region's
+// counts; bins[(i R + g) 3 + {0, 1, 2}] = the region's first entry in the
+// scale's [nB] span of entries, its count, and 0, the spill count):
 // k_part_scan_rows takes 64 regions of one scale per workgroup, each
 // wavefront a contiguous quarter of the blocks (loads coalesced over the
 // regions, eight in flight per lane), and writes the regions' totals;
@@ -1563,19 +1534,51 @@ __global__ __launch_bounds__(256) void k_part_base(int log2cap, uint32_t *bins,
 // The block's (key, b) pairs grouped by region: counted in LDS, placed in
 // LDS in region order, then written so that consecutive threads write
 // consecutive entries of a region's run.
+// fused (small partitions, nblk x R <= kPartScanOneGroup): offs holds the
+// raw counts of k_part_hist; the workgroup derives its offsets in every
+// region and the regions' first entries from its scale's counts itself,
+// and workgroup j = 0 of each scale writes the scale's bins (what
+// k_part_scan does for the other form).
 __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict__ keys,
                                                       int64_t nB, int log2cap, int64_t nblk,
                                                       const uint32_t *__restrict__ offs,
-                                                      const uint32_t *__restrict__ bins,
-                                                      uint3 *entries) {
+                                                      uint32_t *bins, uint3 *entries,
+                                                      uint32_t *spilled, int fused) {
     extern __shared__ uint32_t sm[];
     const int R = (int)part_regions(log2cap);
     uint32_t *cnt = sm;               // [R] counts, then the block's region starts
     uint32_t *fill = sm + R;          // [R + 256] scan scratch, then positions per region
     auto *sk = reinterpret_cast<unsigned long long *>(sm + 2 * R + 256);  // [kPartBlock]
     int32_t *sb = reinterpret_cast<int32_t *>(sk + kPartBlock);                      // [kPartBlock]
+    uint32_t *gbase = reinterpret_cast<uint32_t *>(sb + kPartBlock);  // [R] fused: first entry
+    uint32_t *gtot = gbase + R;                                        // [R] fused: region totals
     __shared__ uint32_t total;
     const int64_t i = blockIdx.x / nblk, j = blockIdx.x - i * nblk;
+    if (fused) {
+        if (i == 0 && j == 0 && threadIdx.x == 0) *spilled = 0;  // read after the region builds
+        for (int g = threadIdx.x; g < R; g += 256) {
+            const CH_RO uint32_t *o = ro(offs) + (size_t)i * nblk * R + g;
+            uint32_t before = 0, all = 0;
+#pragma unroll 8
+            for (int64_t b = 0; b < nblk; ++b) {
+                const uint32_t c = o[b * R];
+                before += b < j ? c : 0u;
+                all += c;
+            }
+            gbase[g] = before;
+            gtot[g] = all;
+            if (j == 0) {
+                bins[((size_t)i * R + g) * 3 + 1] = all;
+                bins[((size_t)i * R + g) * 3 + 2] = 0;
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(gtot, R, fill);
+        for (int g = threadIdx.x; g < R; g += 256) {
+            gbase[g] += gtot[g];
+            if (j == 0) bins[((size_t)i * R + g) * 3 + 0] = gtot[g];
+        }
+    }
     for (int g = threadIdx.x; g < R; g += 256) cnt[g] = 0;
     __syncthreads();
     constexpr int kPer = kPartBlock / 256;
@@ -1609,7 +1612,8 @@ __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict
     for (uint32_t pos = threadIdx.x; pos < n; pos += 256) {
         const unsigned long long key = sk[pos];
         const uint32_t g = key_region(key, log2cap);
-        const size_t dst = (size_t)i * nB + bn[g * 3] + o[g] + (pos - cnt[g]);
+        const uint32_t first = fused ? gbase[g] : bn[g * 3] + o[g];
+        const size_t dst = (size_t)i * nB + first + (pos - cnt[g]);
         entries[dst] = make_uint3((uint32_t)key, (uint32_t)(key >> 32), (uint32_t)sb[pos]);
     }
 }
@@ -1735,9 +1739,10 @@ __global__ __launch_bounds__(256) void k_spill_insert(const uint32_t *__restrict
     }
 }
 
-// Largest count table (blocks x regions) of one scale that one workgroup
-// scans (10^5 points: 25 x 128); above it the two-launch scan (10^6 points,
-// 245 x 1024: 88 us in one workgroup per scale).
+// Largest count table (blocks x regions) of one scale that each scatter
+// workgroup reads and scans itself (10^5 points: 25 x 128); above it the
+// two-launch scan (10^6 points, 245 x 1024: 88 us in one workgroup per
+// scale, about 15 us in two launches).
 constexpr int64_t kPartScanOneGroup = 16384;
 
 hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, Bucket *tables,
@@ -1748,17 +1753,16 @@ hipError_t launch_part_build(const PartWork &w, int64_t nB, int L, int log2cap, 
     const int S = 1 << region_bits(log2cap);
     k_part_hist<<<(unsigned)(L * nblk), 256, (size_t)R * sizeof(uint32_t), st>>>(
         w.keys, nB, log2cap, nblk, w.offs);
-    if (nblk * R <= kPartScanOneGroup) {
-        k_part_scan<<<(unsigned)L, 256, ((size_t)R + 256) * sizeof(uint32_t), st>>>(
-            nB, log2cap, nblk, w.offs, w.bins, w.spilled);
-    } else {
+    const bool fused = nblk * R <= kPartScanOneGroup;  // the scatter scans the counts itself
+    if (!fused) {
         k_part_scan_rows<<<(unsigned)(L * ((R + 63) / 64)), 256, 0, st>>>(log2cap, nblk, w.offs,
                                                                          w.bins);
         k_part_base<<<(unsigned)L, 256, 0, st>>>(log2cap, w.bins, w.spilled);
     }
-    const size_t lds_sc = (2 * (size_t)R + 256) * sizeof(uint32_t) + (size_t)kPartBlock * 12;
-    k_part_scatter<<<(unsigned)(L * nblk), 256, lds_sc, st>>>(w.keys, nB, log2cap, nblk, w.offs,
-                                                              w.bins, w.entries);
+    const size_t lds_sc = (2 * (size_t)R + 256) * sizeof(uint32_t) + (size_t)kPartBlock * 12 +
+                          (fused ? 2 * (size_t)R * sizeof(uint32_t) : 0);
+    k_part_scatter<<<(unsigned)(L * nblk), 256, lds_sc, st>>>(
+        w.keys, nB, log2cap, nblk, w.offs, w.bins, w.entries, w.spilled, fused ? 1 : 0);
     k_region_build<<<(unsigned)(L * R), 256, (size_t)S * 12, st>>>(w.entries, nB, L, log2cap,
                                                                    tables, w.bins, w.spilled);
     // a wavefront per (scale, region): most have nothing kept aside, and a
