@@ -1344,15 +1344,16 @@ hipError_t launch_hash(int mode, const float *X, int64_t n, const float *Bpts, i
 // become offsets (small partitions: inside k_part_scatter, each workgroup
 // from its scale's counts; large ones: k_part_scan_rows and k_part_base),
 // the blocks write their (key, b) pairs grouped by region (k_part_scatter,
-// runs of a region contiguous), and one workgroup per (scale, region) inserts the region's
-// pairs into a table in LDS -- linear probing from the home slot, lowest b
-// per key, LDS atomics only -- and writes all S slots out
-// (k_region_build).  The LDS build never wraps: a pair whose probe reaches
-// the region's end is kept aside and inserted afterwards with the global
-// insert (k_spill_insert), which continues into the next region like any
-// linear probe; the probe then finds every key as after the global insert.
+// runs of a region contiguous), and one workgroup per (scale, region)
+// inserts the region's pairs into a table in LDS -- linear probing from
+// the home slot, lowest b per key, LDS atomics only -- and writes all S
+// slots out (k_region_build).  The LDS build never wraps: a pair whose
+// probe reaches the region's end is kept aside and inserted afterwards with
+// the global insert (k_spill_insert), which continues into the next region
+// like any linear probe; the probe then finds every key as after the global
+// insert.
 // A region holds at most S keys against about S / 2 expected (tables are
-// at most half full), so on hashed keys the spill is empty in practice.
+// at most half full), so on hashed keys few pairs spill.
 
 constexpr int kRegionBits = 11;
 constexpr int kPartBlock = 4096;   // keys per histogram / scatter workgroup
@@ -1537,8 +1538,9 @@ __global__ __launch_bounds__(256) void k_part_base(int log2cap, uint32_t *bins,
 // fused (small partitions, nblk x R <= kPartScanOneGroup): offs holds the
 // raw counts of k_part_hist; the workgroup derives its offsets in every
 // region and the regions' first entries from its scale's counts itself,
-// and workgroup j = 0 of each scale writes the scale's bins (what
-// k_part_scan does for the other form).
+// and workgroup j = 0 of each scale writes the scale's bins and workgroup 0
+// clears the spill flag (what k_part_scan_rows and k_part_base do for large
+// partitions).
 __global__ __launch_bounds__(256) void k_part_scatter(const uint64_t *__restrict__ keys,
                                                       int64_t nB, int log2cap, int64_t nblk,
                                                       const uint32_t *__restrict__ offs,
