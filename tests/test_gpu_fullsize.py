@@ -251,3 +251,25 @@ def test_probe_tile_distance_ragged(ch, orc, metric, d):
     assert np.array_equal(out["crude_scale"].cpu().numpy(), c["scale"])
     assert np.array_equal(out["crude_nn"].cpu().numpy(), c["nn"])
     assert np.array_equal(out["crude_D"].cpu().numpy().view(np.uint32), c["D"].view(np.uint32))
+
+
+def test_sampler_block_offsets_in_memory(ch, orc):
+    """Above 4096 weight blocks (n_A > 4 Mi points) the block totals are
+    scanned by their own kernel and the sampler reads the block offsets from
+    memory instead of scanning them into LDS: W, s and every sampled index
+    against the oracle's weights and draws on the GPU's own D_a."""
+    n_a = 4096 * 1024 + 777
+    print(f"[case] sampler, block offsets in memory, n_A={n_a}", flush=True)
+    rng = np.random.default_rng(44)
+    A = rng.uniform(-50, 50, (n_a, 3)).astype(np.float32)
+    B = rng.uniform(-50, 50, (2000, 3)).astype(np.float32)
+    T, seed = 3000, 9
+    out = ch.chamfer_estimate(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), 1, 0.2,
+                              T, seed)
+    torch.cuda.synchronize()
+    D = out["crude_D"].cpu().numpy()
+    s, _, P, W, zero = orc.weights(D)
+    assert not zero
+    assert int(out["W"].cpu().numpy().view(np.uint64)[0]) == W
+    assert int(out["s"].cpu().numpy()[0]) == s
+    assert np.array_equal(out["sample_idx"].cpu().numpy(), orc.sample(seed, P, W, T))
